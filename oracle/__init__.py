@@ -1,0 +1,18 @@
+"""Plain, slow FP64 CPU oracle for the local ETKF frame of Gray et al.,
+"Local ensemble transform Kalman filter, a fast non-stationary control law for
+adaptive optics on ELTs" (arXiv:1408.7069).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and its
+Python binding) may import, call or link anything in this package; only the
+tests, the smoke check and the CPU-baseline leg of the benchmark use it.  It
+shares no code, constants or helpers with the GPU path: the two meet only
+through the seeded synthetic inputs.
+
+Modules
+  geometry    pupil mask, actuator grid, Fried slope operator, domains, taper
+  letkf       forecast, per-domain analysis (three independent forms), gather
+  kalman      brute-force Kalman update (the exact limit the ETKF must reach)
+  philox      Philox4x32-10 counter-based generator and the noise-bank lookup
+  accounting  the paper's operation counts (App. B, Tables 1, 3, 4)
+  adjoint     hand-written reverse-mode gradient of the residual-variance loss
+"""
