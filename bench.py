@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark of the local ETKF frame on one MI355X.
+
+Workload: 80x80 Shack-Hartmann subapertures, 28 % central obscuration (4632
+valid subapertures, 9264 slopes, 4836 valid actuator nodes), ensemble m = 64,
+4x4-subaperture domains with a 1-subaperture halo (332 local analyses per
+frame).  FP32 state and matrix-core contractions, FP64 eigensolve.  Synthetic
+inputs: an AR(1) von Karman true phase, its Fried slopes plus N(0, 0.1^2)
+noise, and model noise drawn on the device from a bank of von Karman screens.
+All inputs are resident in HBM before timing starts.
+
+One step = one letkf_step: the fused forecast, all local analyses in one
+launch (graph replay) and the gather.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LETKF frames/sec and local analyses/sec at 80×80 SH, m=64; batched vs plain"
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def algorithmic_flops(m: int, p_list, n_list) -> dict:
+    """Nominal work of one frame's analyses (per domain: Gram 2 m^2 p, symmetric
+    EVD with vectors 9 m^3, transform 2 m^3, update 2 n m^2 + 2 n m, the slope
+    stencil 4 p m and Y^T d 2 p m)."""
+    p = np.asarray(p_list, dtype=np.float64)
+    n = np.asarray(n_list, dtype=np.float64)
+    d = len(p)
+    return {"gram": float(np.sum(2 * m * m * p)), "evd": 9.0 * m ** 3 * d, "transform": 2.0 * m ** 3 * d,
+            "update": float(np.sum(2 * n * m * m + 2 * n * m)), "stencil": float(np.sum(6 * p * m))}
+
+
+def make_inputs(f, wl_mod, w, frames: int, rng):
+    """Slopes of an AR(1) true phase for `frames` frames, resident on the GPU."""
+    import torch
+    geo = f.geometry(0)
+    ij = geo["node_ij"]
+    truth = wl_mod.ar1_truth(w.n_sub, frames, w.pitch, w.r0, w.L0, w.a, rng)
+    ph = torch.from_numpy(np.ascontiguousarray(truth[:, ij[:, 0], ij[:, 1]], dtype=np.float32)).cuda()
+    p = f.sizes["n_slopes"]
+    y = torch.empty((frames, p), dtype=torch.float32, device="cuda")
+    for k in range(frames):
+        f.slopes(ph[k], out=y[k])
+    noise = torch.from_numpy(wl_mod.gaussian_noise((frames, p), w.sigma, rng).astype(np.float32)).cuda()
+    y += noise
+    torch.cuda.synchronize()
+    return y, truth, ij
+
+
+def time_steps(f, y, K, W, plain=False, per_step=False):
+    import torch
+    step = f.step_plain if plain else f.step
+    for k in range(W):
+        step(y[k % y.shape[0]])
+    torch.cuda.synchronize()
+    if per_step:
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        for k in range(K):
+            ev[k][0].record()
+            step(y[(W + k) % y.shape[0]])
+            ev[k][1].record()
+        torch.cuda.synchronize()
+        return np.array([a.elapsed_time(b) for a, b in ev])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(K):
+        step(y[(W + k) % y.shape[0]])
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / K
+
+
+def cpu_baseline(w, bank, seed, truth, sigma_noise, budget_s=12.0):
+    """The FP64 oracle on the same workload, one thread, frames until the budget.
+    Its slopes are made from the same true phase with the oracle's own operator."""
+    from threadpoolctl import threadpool_limits
+    from oracle import geometry as og
+    from oracle import letkf as ol
+    from oracle import philox
+    G = og.Geometry(og.pupil_mask(w.n_sub, w.obscuration))
+    ij0 = G.node_coords()
+    y_host = [og.apply_slopes(G, truth[k][ij0[:, 0], ij0[:, 1]]) + sigma_noise[k] for k in range(len(truth))]
+    doms = og.domains(G, w.b, w.h)
+    prm = ol.Params(a=w.a, rho=w.rho, b=w.b, h=w.h)
+    r = np.full(G.n_slopes, w.sigma ** 2)
+    ij = G.node_coords()
+    Xa = np.zeros((G.n_nodes, w.m))
+    done, t0 = 0, time.perf_counter()
+    with threadpool_limits(limits=1):
+        while done < 2 or time.perf_counter() - t0 < budget_s:
+            V = philox.bank_noise(bank, ij, w.m, seed, 0, done)
+            Xa = ol.step(G, doms, Xa, V, y_host[done % len(y_host)], r, prm)
+            done += 1
+            if done >= len(y_host):
+                break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} frames of the same 80x80 m=64 workload (332 local analyses each), "
+                      f"NumPy FP64 with LAPACK eigh, one thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--copies", type=int, default=4, help="instances of the workload in one launch (batched throughput line)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: timed steps only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the frame is not sharded "
+              "across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1408_7069_amd import binding as B
+    from paper_1408_7069_amd import workload as wl
+
+    torch.cuda.init()
+    w = wl.workloads(2)[0]
+    rng = np.random.default_rng(w.seed)
+    bank = wl.bank_for(w, rng, n_screens=16)
+    seed = 0x5EED0000 + w.seed
+    spec = B.InstanceSpec(n_sub=w.n_sub, m=w.m, domain_size=w.b, halo=w.h, obscuration=w.obscuration,
+                          rho=w.rho, r_sigma2=w.sigma ** 2, ar_coeff=w.a, noise_bank=bank, seed=seed,
+                          precision=B.FP32)
+    f = B.Letkf([spec])
+    K, W = args.steps, args.warmup
+    frames = min(K + W, 600)
+    y, truth, ij = make_inputs(f, wl, w, frames, rng)
+    print(f"# inputs ready: {frames} frames of slopes on the GPU", file=sys.stderr, flush=True)
+
+    if args.profile:
+        time_steps(f, y, K, W)
+        print(json.dumps({"profile_run": True, "steps": K}))
+        return
+
+    sched = f.autotune(y[0], frames=10)
+    ms = time_steps(f, y, K, W)
+    fps = 1000.0 / ms
+    n_dom = f.sizes["n_domains"]
+    # per-step distribution and the analysis kernel's launch duration (direct
+    # launches, no graph: one analysis launch plus the one-thread frame counter)
+    f.set_schedule(False, sched[1])
+    per = time_steps(f, y, min(K, 200), 5, per_step=True)
+    f.set_schedule(*sched)
+    kernel_ms = float(np.mean(per))
+    # plain form: one launch per domain, no graph
+    plain_ms = time_steps(f, y, args.plain_steps, 1, plain=True)
+
+    g = f.geometry(0)
+    p_list = np.diff(g["obs_off"])
+    n_list = np.diff(g["own_off"])
+    fl = algorithmic_flops(w.m, p_list, n_list)
+    total = sum(fl.values())
+    achieved = total / (kernel_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": "k_analysis<float,true>", "kernel_ms": round(kernel_ms, 4),
+            "flops_per_launch": total, "flops_breakdown": fl}
+
+    # batched throughput: several copies of the workload in one launch
+    copies = None
+    if args.copies > 1:
+        fc = B.Letkf([spec] * args.copies)
+        yc = y[:, :].repeat(1, args.copies)
+        msc = time_steps(fc, yc, min(K, 200), 10)
+        copies = {"instances": args.copies, "ms_per_step": round(msc, 4),
+                  "local_analyses_per_s": round(args.copies * n_dom * 1000.0 / msc, 1),
+                  "frac_of_fp64_peak": round(args.copies * total / (msc * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+        fc.close()
+
+    out = {
+        "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "80x80 SH, 28% obscuration, m=64, 4x4-subaperture domains, halo 1: "
+                               "332 local analyses per frame in one graph-replayed launch",
+                   "n_slopes": int(f.sizes["n_slopes"]), "n_nodes": int(f.sizes["n_nodes"]),
+                   "domains": int(n_dom), "schedule": {"graph": sched[0], "xcd_order": sched[1]}},
+        "local_analyses_per_s": round(fps * n_dom, 1),
+        "plain": {"ms_per_step": round(plain_ms, 4), "frames_per_s": round(1000.0 / plain_ms, 2),
+                  "launches_per_step": int(n_dom)},
+        "step_ms_p50": round(float(np.percentile(per, 50)), 4),
+        "step_ms_p99": round(float(np.percentile(per, 99)), 4),
+        "batched_copies": copies,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        nrng = np.random.default_rng(w.seed + 1)
+        T = min(frames, 40)
+        out["cpu_baseline"] = cpu_baseline(w, bank, seed, truth[:T],
+                                           wl.gaussian_noise((T, f.sizes["n_slopes"]), w.sigma, nrng))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

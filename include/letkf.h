@@ -1,0 +1,210 @@
+/*
+ * letkf.h -- C ABI of the MI355X (gfx950) local ensemble transform Kalman
+ * filter frame for zonal adaptive-optics control (Gray et al., "Local ensemble
+ * transform Kalman filter, a fast non-stationary control law for adaptive
+ * optics on ELTs", arXiv:1408.7069).
+ *
+ * One frame k is
+ *   forecast  X_b = a X_a + V                      (Sec. 3.1.2, member prediction;
+ *                                                    App. B.2 with A_tur = a Id)
+ *   analysis  per domain l, independently          (Sec. 4.2)
+ *               Y_l  = observation-region rows of D (X_b - x_b 1^T), scaled by
+ *                      sqrt(g), g = f^2 / (s r) (taper f on Sigma_w^{-1/2}, Sec. 4.1)
+ *               A~   = (m-1)/rho I + Y_l^T Y_l      (m x m, Sec. 3.1.1 EVD matrix)
+ *               A~   = Q Lambda Q^T                 (FP64 Jacobi eigensolve)
+ *               w    = A~^{-1} Y_l^T sqrt(g) d_l,   W = sqrt((m-1)/rho) A~^{-1/2}
+ *               X_a,l = (x_b,l + X_l' w) 1^T + sqrt(rho) X_l' W   (owned rows)
+ *   gather    the owned rows of all domains form X_a (Sec. 4.2, concatenation)
+ * with D the Fried-geometry Shack-Hartmann slope operator (App. B).
+ *
+ * Layouts at this boundary
+ *   nodes     valid actuator nodes of the (N+1)^2 grid, row-major; a node is
+ *             valid when it is a corner of a valid subaperture.
+ *   slopes    [x-slopes of the valid subapertures, row-major; y-slopes, same
+ *             order]; p = 2 * (valid subapertures).
+ *   ensemble  [node][member] (member index fastest), one block per instance,
+ *             instances concatenated in creation order.
+ *   element type: float for LETKF_FP32, double for LETKF_FP64.
+ * Device pointers are HIP device addresses on the handle's device; `stream`
+ * is a hipStream_t (NULL = the default stream).  The caller keeps every
+ * buffer it passes valid until the work on `stream` completes.
+ *
+ * Ownership: the handle owns all device memory it allocates; getters copy
+ * out.  A handle is used from one host thread and one stream at a time.
+ *
+ * Errors: every int-returning call returns LETKF_OK (0) or a negative code;
+ * letkf_strerror() gives a message, letkf_last_error() the detail of the
+ * most recent failure on the calling thread.
+ */
+#ifndef LETKF_H
+#define LETKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LETKF_OK 0
+#define LETKF_E_INVAL (-1)      /* bad configuration, size or argument        */
+#define LETKF_E_NOMEM (-2)      /* device or host allocation failed           */
+#define LETKF_E_DEVICE (-3)     /* HIP runtime error                          */
+#define LETKF_E_NONFINITE (-4)  /* NaN/Inf met in the slopes or the update     */
+#define LETKF_E_NOCONV (-5)     /* eigensolve hit max_sweeps in >= 1 domain   */
+#define LETKF_E_STATE (-6)      /* call out of order (e.g. analyse before forecast) */
+
+#define LETKF_FP32 0            /* FP32 state and MFMA contractions, FP64 eigensolve */
+#define LETKF_FP64 1            /* FP64 everywhere                                    */
+
+/* Per-domain status bits (letkf_status). */
+#define LETKF_FLAG_NONFINITE 1
+#define LETKF_FLAG_NOCONV 2
+
+typedef struct letkf_handle letkf_handle;
+
+/* One adaptive-optics instance.  Host pointers are read during letkf_create
+ * only. */
+typedef struct letkf_config {
+  int32_t n_sub;               /* N: N x N subapertures (Sec. 5 set-up)            */
+  const uint8_t *subap_mask;   /* N*N row-major, 1 = valid; NULL = annulus rule:
+                                  valid when > 50 % of the subaperture lies in
+                                  eps*N/2 <= r <= N/2 (Sec. 5), 64x64 sampling    */
+  double obscuration;          /* eps, used when subap_mask == NULL                */
+  int32_t m;                   /* ensemble size, 2 <= m <= 64                      */
+  int32_t domain_size;         /* b: domains are b x b subaperture blocks (Sec. 4.1) */
+  int32_t halo;                /* h >= 0: observation region = block grown by h    */
+  double rho;                  /* multiplicative inflation > 0                     */
+  const double *r_diag;        /* p noise variances (Sigma_w diagonal, Sec. 3.1.1);
+                                  NULL = r_sigma2 for every slope                  */
+  double r_sigma2;             /* used when r_diag == NULL                         */
+  double r_scale;              /* s > 0: Sigma_w = s diag(r)                       */
+  double ar_coeff;             /* a: AR(1) turbulence model (App. B)               */
+  double taper_c;              /* Gaspari-Cohn half width in pitches (Sec. 4.1
+                                  smooth localisation); 0 = no taper               */
+  const float *noise_bank;     /* optional model-noise bank, bank_screens periodic
+                                  bank_side x bank_side screens (row-major); used
+                                  when a forecast is given no explicit V          */
+  int32_t bank_screens;
+  int32_t bank_side;           /* power of two, >= N + 1                           */
+  uint64_t seed;               /* Philox4x32-10 key for the bank draws             */
+  int32_t precision;           /* LETKF_FP32 or LETKF_FP64 (same for all instances) */
+  double jacobi_tol;           /* stop after a sweep whose largest relative off-
+                                  diagonal measure is <= tol; 0 = 1e-5 (FP32),
+                                  1e-10 (FP64)                                     */
+  int32_t max_sweeps;          /* 0 = 30                                           */
+} letkf_config;
+
+/* Sizes of one instance (or totals when instance = -1). */
+typedef struct letkf_sizes {
+  int64_t n_nodes;             /* valid nodes                                      */
+  int64_t n_slopes;            /* p                                                */
+  int64_t n_domains;
+  int64_t ensemble_elems;      /* sum of n_nodes * m                               */
+  int64_t obs_total;           /* sum over domains of local slopes                 */
+  int32_t m;                   /* ensemble size (instance) or max m (totals)       */
+  int32_t max_owned;           /* largest number of owned nodes in a domain        */
+  int32_t max_obs;             /* largest local slope count p_l                    */
+  int32_t max_patch;           /* largest node patch (owned + stencil corners)     */
+  int32_t n_sub;               /* N of the instance (0 for totals)                 */
+  int32_t n_instances;
+} letkf_sizes;
+
+/* Build the geometry of every instance on the host (pupil mask, node and slope
+ * numbering, b x b domains with halo h, taper distances, a work list in
+ * instance-major, row-major domain order) and allocate the device state on `device`.  The ensemble starts at
+ * zero (Sec. 3.1: X_{1/0} = 0).  Returns LETKF_E_INVAL for m < 2 or m > 64,
+ * rho <= 0, r_scale <= 0, any r <= 0, b < 1, h < 0, b + 2h > 7 (a domain's
+ * node patch must fit one 64-lane wavefront),
+ * an instance with no valid subaperture, or a bank that is not a power of two
+ * wide or is narrower than N + 1. */
+int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device,
+                 letkf_handle **out);
+void letkf_destroy(letkf_handle *h);
+const char *letkf_strerror(int code);
+const char *letkf_last_error(void);
+
+int letkf_query(letkf_handle *h, int32_t instance, letkf_sizes *out);
+
+/* Host-only planning of one configuration (no device work): the sizes and
+ * integer maps letkf_create would build, for checks and for callers that size
+ * their buffers first.  Array arguments as in letkf_geometry; pass NULL for
+ * every array to get the sizes only. */
+int letkf_plan(const letkf_config *cfg, letkf_sizes *sizes, int32_t *node_ij, int32_t *owner,
+               int32_t *obs_off, int32_t *obs_idx, int32_t *own_off, int32_t *own_idx);
+
+/* Integer maps of one instance (host buffers, any may be NULL):
+ * node_ij[2n] grid (row, column) of each node; owner[n] domain of each node;
+ * obs_off[nd+1] / obs_idx[obs_total] the local slope list of each domain
+ * (global slope numbers); own_off[nd+1] / own_idx[n] its owned nodes. */
+int letkf_geometry(letkf_handle *h, int32_t instance, int32_t *node_ij, int32_t *owner,
+                   int32_t *obs_off, int32_t *obs_idx, int32_t *own_off, int32_t *own_idx);
+
+/* Forecast X_b = a X_a + V (Sec. 3.1.2).  V_dev: ensemble layout, or NULL to
+ * draw V from each instance's noise bank (LETKF_E_INVAL if it has none).
+ * Advances the frame counter. */
+int letkf_forecast(letkf_handle *h, const void *V_dev, void *stream);
+
+/* Analysis of X_b with the slopes y_dev (all instances concatenated), all
+ * domains of all instances in one launch; the owned rows form X_a. */
+int letkf_analyse(letkf_handle *h, const void *y_dev, void *stream);
+
+/* One whole frame (forecast fused into the analysis: each domain forms its own
+ * node patch of X_b), replayed from a HIP graph built on the first call. */
+int letkf_step(letkf_handle *h, const void *V_dev, const void *y_dev, void *stream);
+
+/* The same frame without batching: one launch per domain, no graph. */
+int letkf_step_plain(letkf_handle *h, const void *V_dev, const void *y_dev, void *stream);
+
+/* Copy the analysis ensemble / its member mean ([node] per instance) out, or
+ * set the ensemble (restart, tests).  on_device != 0: dst/src are device
+ * pointers on the handle's device; else host pointers.  Synchronous. */
+int letkf_get_ensemble(letkf_handle *h, void *dst, int on_device);
+int letkf_set_ensemble(letkf_handle *h, const void *src, int on_device);
+int letkf_get_forecast(letkf_handle *h, void *dst, int on_device);
+int letkf_get_mean(letkf_handle *h, void *dst, int on_device);
+
+/* Frame counter (drives the bank draws): get / set, for exact restarts. */
+int letkf_get_frame(letkf_handle *h, uint32_t *frame);
+int letkf_set_frame(letkf_handle *h, uint32_t frame);
+
+/* Per-domain status bits of the last analysis, in work-list order mapped back
+ * to (instance, domain): flags[sum of domains].  Synchronous.  Returns
+ * LETKF_E_NOCONV / LETKF_E_NONFINITE when any bit is set, else LETKF_OK. */
+int letkf_status(letkf_handle *h, int32_t *flags);
+
+/* Change rho, r_scale and taper_c of one instance (tuning runs). */
+int letkf_set_params(letkf_handle *h, int32_t instance, double rho, double r_scale,
+                     double taper_c);
+
+/* Apply the Fried slope operator D (App. B) to one phase vector per
+ * instance: phase_dev [node] -> slopes_dev [slope], instances concatenated. */
+int letkf_slopes(letkf_handle *h, const void *phase_dev, void *slopes_dev, void *stream);
+
+/* Last-call timing knobs picked by letkf_autotune (or set by hand):
+ * use_graph (0/1) for letkf_step and xcd_order (0/1) for the block to work
+ * item mapping. */
+int letkf_set_schedule(letkf_handle *h, int32_t use_graph, int32_t xcd_order);
+int letkf_get_schedule(letkf_handle *h, int32_t *use_graph, int32_t *xcd_order);
+
+/* Time the step under each schedule on `stream` (frames frames each, using
+ * the given V/y buffers) and keep the fastest; results are cached in
+ * cache_path (text, one line per shape) when cache_path != NULL. */
+int letkf_autotune(letkf_handle *h, const void *V_dev, const void *y_dev, int32_t frames,
+                   const char *cache_path, void *stream);
+
+/* Symmetric positive definite eigensolve by the same FP64 wave-level Jacobi
+ * the analysis uses (Cholesky A = L L^T, then one-sided Jacobi rotations of
+ * the columns of L until they are orthogonal; their squared norms are the
+ * eigenvalues and the normalised columns the eigenvectors).  A_dev: batch
+ * row-major m x m FP64 matrices (m <= 64); Q_dev: batch m x m (column k =
+ * eigenvector k); lam_dev: batch x m; sweeps_dev: batch int32 sweeps used
+ * (NULL allowed).  Eigenvalues are not sorted.  Stateless. */
+int letkf_eigh_spd(const double *A_dev, int32_t m, int32_t batch, double tol,
+                   int32_t max_sweeps, double *Q_dev, double *lam_dev, int32_t *sweeps_dev,
+                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LETKF_H */

@@ -2,18 +2,8 @@
 adaptive optics (Gray et al., arXiv:1408.7069).
 
 The compute path is the HIP library `libletkf.so` (built for gfx950 from
-`csrc/`), reached through the C ABI declared in `include/letkf.h`; `binding`
-is its thin ctypes wrapper.  `workload` only makes seeded synthetic inputs.
-The binding is imported lazily so that the input generators stay usable on
-machines without the library; every compute call fails loudly when the
-library is missing.
+`csrc/`), reached through the C ABI declared in `include/letkf.h`;
+`paper_1408_7069_amd.binding` is its thin ctypes wrapper and raises on import
+when the library is missing (there is no CPU fallback).
+`paper_1408_7069_amd.workload` only makes seeded synthetic inputs.
 """
-
-__all__ = ["binding", "workload"]
-
-
-def __getattr__(name):
-    if name == "binding":
-        from . import binding
-        return binding
-    raise AttributeError(name)

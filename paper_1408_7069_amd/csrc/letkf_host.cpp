@@ -1,0 +1,950 @@
+// Host side of libletkf: geometry planner, device state, launches, C ABI.
+//
+// Geometry (planned once per instance at letkf_create):
+//  * valid subapertures: > 50 % of the area inside the annulus eps N/2 <= r <= N/2
+//    (Sec. 5), sampled 64 x 64 with exact integer radii, or a caller mask;
+//  * valid nodes: corners of valid subapertures (Fried geometry, App. B),
+//    numbered row-major; slopes [x of valid subapertures; y same order];
+//  * domains: b x b subaperture blocks owning the nodes (i, j) with
+//    (min(i / b, nb - 1), min(j / b, nb - 1)), nb = ceil(N / b); observation
+//    region = the block grown by h subapertures (Sec. 4.1);
+//  * per domain, a node patch (owned nodes first, then the other corners of
+//    the region's subapertures) that the analysis kernel loads into LDS.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/letkf.h"
+#include "letkf_types.h"
+
+using namespace letkf;
+
+extern "C" hipError_t letkf_launch_analysis_f32(const void *args, int fused, int grid, size_t lds,
+                                                hipStream_t s);
+extern "C" hipError_t letkf_launch_analysis_f64(const void *args, int fused, int grid, size_t lds,
+                                                hipStream_t s);
+extern "C" const void *letkf_analysis_kernel(int fp64, int fused);
+extern "C" hipError_t letkf_launch_forecast(int fp64, const InstDesc *insts, int n_inst,
+                                            const int32_t *node_ij, const void *xa, const void *v,
+                                            const float *bank, const uint32_t *frame, void *xb,
+                                            int64_t max_elems, hipStream_t s);
+extern "C" hipError_t letkf_launch_frame_advance(uint32_t *frame, hipStream_t s);
+extern "C" const void *letkf_frame_advance_kernel(void);
+extern "C" hipError_t letkf_launch_slopes(int fp64, const InstDesc *insts, int n_inst,
+                                          const int32_t *subap_nodes, const void *phase,
+                                          void *slopes, int max_subaps, hipStream_t s);
+extern "C" hipError_t letkf_launch_mean(int fp64, const InstDesc *insts, int n_inst, const void *x,
+                                        void *mean, int max_nodes, hipStream_t s);
+extern "C" hipError_t letkf_launch_eigh(const double *A, int m, int batch, double tol,
+                                        int max_sweeps, double *Q, double *lam, int32_t *sweeps,
+                                        hipStream_t s);
+extern "C" size_t letkf_args_size(int fp64);
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(LETKF_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_));      \
+  } while (0)
+
+// Mirror of the kernel argument block (layout must match AnaArgs<T>).
+template <typename T> struct AnaArgsHost {
+  const InstDesc *inst;
+  const DomItem *items;
+  int32_t item_base, n_items, xcd_order, noise_bank;
+  const int32_t *patch_node;
+  const uint32_t *obs_corner;
+  const int32_t *obs_sub;
+  const double *obs_dist;
+  const int32_t *node_ij;
+  const double *r_diag;
+  const T *x_in;
+  const T *v_in;
+  const float *bank;
+  const T *y;
+  T *x_out;
+  int32_t *flags;
+  const uint32_t *frame;
+  double jtol;
+  int32_t max_sweeps;
+  int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u;
+};
+
+struct InstGeom {
+  int N = 0, b = 0, h = 0, m = 0;
+  std::vector<uint8_t> mask;           // N*N
+  std::vector<int32_t> node_index;     // (N+1)^2, -1 invalid
+  std::vector<int32_t> node_ij;        // 2 n
+  std::vector<int32_t> subaps;         // 2 p_sap (i, j)
+  std::vector<int32_t> subap_nodes;    // 4 p_sap
+  int n_nodes = 0, n_subaps = 0;
+  // domains
+  std::vector<std::array<int, 2>> blocks;
+  std::vector<std::vector<int32_t>> owned, patch, obs_sub;
+  std::vector<std::vector<uint32_t>> obs_corner;
+  std::vector<std::vector<double>> obs_dist;
+  std::vector<int32_t> owner;          // n
+};
+
+}  // namespace
+
+struct letkf_handle {
+  int device = 0;
+  int fp64 = 0;
+  size_t esize = 4;
+  int n_inst = 0;
+  std::vector<InstGeom> geom;
+  std::vector<InstDesc> desc;
+  std::vector<DomItem> items;
+  std::vector<int32_t> dom_base;  // first global domain number of each instance
+  int64_t total_x = 0, total_y = 0, total_nodes = 0, total_obs = 0;
+  int max_patch = 0, max_obs_sub = 0, max_own = 0, max_m = 0, max_subaps = 0, max_nodes = 0;
+  int64_t max_elems = 0;
+  bool any_bank = false, all_bank = true;
+  double jtol = 0.0;
+  int max_sweeps = 30;
+  size_t lds = 0;
+  int32_t off[8] = {0};
+  // device
+  InstDesc *d_desc = nullptr;
+  DomItem *d_items = nullptr;
+  int32_t *d_patch = nullptr, *d_obs_sub = nullptr, *d_node_ij = nullptr, *d_subap_nodes = nullptr;
+  uint32_t *d_obs_corner = nullptr;
+  double *d_obs_dist = nullptr;
+  float *d_bank = nullptr;
+  double *d_r = nullptr;
+  void *d_xa[2] = {nullptr, nullptr};
+  void *d_xb = nullptr;
+  void *d_tmp = nullptr;  // mean scratch
+  uint32_t *d_frame = nullptr;
+  int32_t *d_flags = nullptr;
+  int cur = 0;
+  bool have_xb = false;
+  // graph replay of the fused frame, one per ping-pong parity
+  int use_graph = 1, xcd_order = 1;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraphNode_t gnode[2] = {nullptr, nullptr};
+  std::vector<unsigned char> gargs[2];
+};
+
+namespace {
+
+// ---------------------------------------------------------------- geometry
+std::vector<uint8_t> annulus_mask(int N, double eps) {
+  const int ss = 64;
+  const int64_t outer = (int64_t)ss * N * (int64_t)ss * N;
+  const double inner = (eps * N * ss) * (eps * N * ss);
+  std::vector<uint8_t> mask((size_t)N * N, 0);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      int lit = 0;
+      for (int t = 0; t < ss; ++t) {
+        const int64_t Y = 2LL * ss * i + 2 * t + 1 - (int64_t)ss * N;
+        for (int u = 0; u < ss; ++u) {
+          const int64_t X = 2LL * ss * j + 2 * u + 1 - (int64_t)ss * N;
+          const int64_t r2 = X * X + Y * Y;
+          if (r2 <= outer && (double)r2 >= inner) ++lit;
+        }
+      }
+      mask[(size_t)i * N + j] = 2 * lit > ss * ss;
+    }
+  return mask;
+}
+
+int plan_instance(const letkf_config &c, InstGeom &g, std::string &err) {
+  const int N = c.n_sub;
+  g.N = N;
+  g.b = c.domain_size;
+  g.h = c.halo;
+  g.m = c.m;
+  g.mask = c.subap_mask ? std::vector<uint8_t>(c.subap_mask, c.subap_mask + (size_t)N * N)
+                        : annulus_mask(N, c.obscuration);
+  for (auto &v : g.mask) v = v ? 1 : 0;
+  const int N1 = N + 1;
+  std::vector<uint8_t> nv((size_t)N1 * N1, 0);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j)
+      if (g.mask[(size_t)i * N + j])
+        nv[i * N1 + j] = nv[(i + 1) * N1 + j] = nv[i * N1 + j + 1] = nv[(i + 1) * N1 + j + 1] = 1;
+  g.node_index.assign((size_t)N1 * N1, -1);
+  int k = 0;
+  for (int i = 0; i < N1; ++i)
+    for (int j = 0; j < N1; ++j)
+      if (nv[i * N1 + j]) {
+        g.node_index[i * N1 + j] = k++;
+        g.node_ij.push_back(i);
+        g.node_ij.push_back(j);
+      }
+  g.n_nodes = k;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j)
+      if (g.mask[(size_t)i * N + j]) {
+        g.subaps.push_back(i);
+        g.subaps.push_back(j);
+        g.subap_nodes.push_back(g.node_index[i * N1 + j]);
+        g.subap_nodes.push_back(g.node_index[i * N1 + j + 1]);
+        g.subap_nodes.push_back(g.node_index[(i + 1) * N1 + j]);
+        g.subap_nodes.push_back(g.node_index[(i + 1) * N1 + j + 1]);
+      }
+  g.n_subaps = (int)(g.subaps.size() / 2);
+  if (g.n_subaps == 0) {
+    err = "instance has no valid subaperture";
+    return LETKF_E_INVAL;
+  }
+  std::vector<int32_t> sub_id((size_t)N * N, -1);
+  for (int q = 0; q < g.n_subaps; ++q) sub_id[g.subaps[2 * q] * N + g.subaps[2 * q + 1]] = q;
+  // domains
+  const int b = g.b, h = g.h, nb = (N + b - 1) / b;
+  std::vector<std::vector<int32_t>> blk_nodes((size_t)nb * nb);
+  g.owner.assign(g.n_nodes, -1);
+  for (int n = 0; n < g.n_nodes; ++n) {
+    const int i = g.node_ij[2 * n], j = g.node_ij[2 * n + 1];
+    const int I = std::min(i / b, nb - 1), J = std::min(j / b, nb - 1);
+    blk_nodes[I * nb + J].push_back(n);
+  }
+  for (int I = 0; I < nb; ++I)
+    for (int J = 0; J < nb; ++J) {
+      auto &own = blk_nodes[I * nb + J];
+      if (own.empty()) continue;
+      const int d = (int)g.owned.size();
+      for (int n : own) g.owner[n] = d;
+      g.blocks.push_back({I, J});
+      g.owned.push_back(own);  // ascending: nodes were visited in index order
+      std::vector<int32_t> obs;
+      const int i0 = std::max(I * b - h, 0), i1 = std::min(std::min((I + 1) * b, N) + h, N);
+      const int j0 = std::max(J * b - h, 0), j1 = std::min(std::min((J + 1) * b, N) + h, N);
+      for (int i = i0; i < i1; ++i)
+        for (int j = j0; j < j1; ++j)
+          if (sub_id[i * N + j] >= 0) obs.push_back(sub_id[i * N + j]);
+      // patch: owned first, then the other corners (ascending)
+      std::vector<int32_t> patch = own;
+      std::vector<int32_t> extra;
+      for (int q : obs)
+        for (int t = 0; t < 4; ++t) {
+          const int nd = g.subap_nodes[4 * q + t];
+          if (g.owner[nd] != d || std::find(own.begin(), own.end(), nd) == own.end())
+            extra.push_back(nd);
+        }
+      std::sort(extra.begin(), extra.end());
+      extra.erase(std::unique(extra.begin(), extra.end()), extra.end());
+      for (int nd : extra)
+        if (std::find(own.begin(), own.end(), nd) == own.end()) patch.push_back(nd);
+      if (patch.size() > (size_t)kMaxPatch || obs.size() > (size_t)kMaxObsSub) {
+        err = "domain patch exceeds 64 nodes or 64 observation subapertures";
+        return LETKF_E_INVAL;
+      }
+      std::vector<uint32_t> corners;
+      std::vector<double> dist;
+      for (int q : obs) {
+        uint32_t w = 0;
+        for (int t = 0; t < 4; ++t) {
+          const int nd = g.subap_nodes[4 * q + t];
+          const int loc = (int)(std::find(patch.begin(), patch.end(), nd) - patch.begin());
+          w |= (uint32_t)loc << (8 * t);
+        }
+        corners.push_back(w);
+        const double dy = g.subaps[2 * q] + 0.5 - (I + 0.5) * b;
+        const double dx = g.subaps[2 * q + 1] + 0.5 - (J + 0.5) * b;
+        dist.push_back(std::sqrt(dy * dy + dx * dx));
+      }
+      g.patch.push_back(patch);
+      g.obs_sub.push_back(obs);
+      g.obs_corner.push_back(corners);
+      g.obs_dist.push_back(dist);
+    }
+  return LETKF_OK;
+}
+
+int validate(const letkf_config &c, int idx, std::string &err) {
+  std::ostringstream o;
+  o << "instance " << idx << ": ";
+  if (c.n_sub < 1 || c.n_sub > 4096) err = o.str() + "n_sub out of range";
+  else if (c.m < 2 || c.m > 64) err = o.str() + "m must be in [2, 64]";
+  else if (c.domain_size < 1) err = o.str() + "domain_size must be >= 1";
+  else if (c.halo < 0) err = o.str() + "halo must be >= 0";
+  else if (c.domain_size + 2 * c.halo > 7) err = o.str() + "domain_size + 2*halo must be <= 7";
+  else if (!(c.rho > 0)) err = o.str() + "rho must be > 0";
+  else if (!(c.r_scale > 0)) err = o.str() + "r_scale must be > 0";
+  else if (!c.r_diag && !(c.r_sigma2 > 0)) err = o.str() + "r_sigma2 must be > 0";
+  else if (!(c.taper_c >= 0)) err = o.str() + "taper_c must be >= 0";
+  else if (!c.subap_mask && !(c.obscuration >= 0 && c.obscuration < 1)) err = o.str() + "obscuration must be in [0, 1)";
+  else if (c.precision != LETKF_FP32 && c.precision != LETKF_FP64) err = o.str() + "unknown precision";
+  else if (c.noise_bank && (c.bank_screens < 1 || c.bank_side < c.n_sub + 1 ||
+                            (c.bank_side & (c.bank_side - 1)) != 0))
+    err = o.str() + "noise bank needs >= 1 screen and a power-of-two side >= N + 1";
+  else return LETKF_OK;
+  return LETKF_E_INVAL;
+}
+
+template <typename T> int to_device(T **dst, const std::vector<T> &src) {
+  const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+  hipError_t e = hipMalloc((void **)dst, bytes);
+  if (e != hipSuccess) return fail(LETKF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  if (!src.empty()) HIPCHK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return LETKF_OK;
+}
+
+size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+void free_handle(letkf_handle *h) {
+  if (!h) return;
+  hipSetDevice(h->device);
+  for (int p = 0; p < 2; ++p) {
+    if (h->gexec[p]) hipGraphExecDestroy(h->gexec[p]);
+    if (h->graph[p]) hipGraphDestroy(h->graph[p]);
+  }
+  void *ptrs[] = {h->d_desc, h->d_items, h->d_patch, h->d_obs_sub, h->d_node_ij, h->d_subap_nodes,
+                  h->d_obs_corner, h->d_obs_dist, h->d_bank, h->d_r, h->d_xa[0], h->d_xa[1],
+                  h->d_xb, h->d_tmp, h->d_frame, h->d_flags};
+  for (void *p : ptrs)
+    if (p) hipFree(p);
+  delete h;
+}
+
+template <typename T>
+AnaArgsHost<T> make_args(letkf_handle *h, bool fused, const void *V, const void *y, int xa_in,
+                         int xa_out) {
+  AnaArgsHost<T> A;
+  std::memset(&A, 0, sizeof(A));
+  A.inst = h->d_desc;
+  A.items = h->d_items;
+  A.item_base = 0;
+  A.n_items = (int32_t)h->items.size();
+  A.xcd_order = h->xcd_order;
+  A.noise_bank = (fused && V == nullptr) ? 1 : 0;
+  A.patch_node = h->d_patch;
+  A.obs_corner = h->d_obs_corner;
+  A.obs_sub = h->d_obs_sub;
+  A.obs_dist = h->d_obs_dist;
+  A.node_ij = h->d_node_ij;
+  A.r_diag = h->d_r;
+  A.x_in = fused ? (const T *)h->d_xa[xa_in] : (const T *)h->d_xb;
+  A.v_in = (const T *)V;
+  A.bank = h->d_bank;
+  A.y = (const T *)y;
+  A.x_out = (T *)h->d_xa[xa_out];
+  A.flags = h->d_flags;
+  A.frame = h->d_frame;
+  A.jtol = h->jtol;
+  A.max_sweeps = h->max_sweeps;
+  A.off_xs = h->off[0];
+  A.off_xm = h->off[1];
+  A.off_sg = h->off[2];
+  A.off_dd = h->off[3];
+  A.off_yb = h->off[4];
+  A.off_pn = h->off[5];
+  A.off_s = h->off[6];
+  A.off_u = h->off[7];
+  return A;
+}
+
+int grid_for(const letkf_handle *h) {
+  const int n = (int)h->items.size();
+  return h->xcd_order ? 8 * ((n + 7) / 8) : n;
+}
+
+int launch_analysis(letkf_handle *h, bool fused, const void *V, const void *y, int xa_in, int xa_out,
+                    hipStream_t s) {
+  if (h->fp64) {
+    auto A = make_args<double>(h, fused, V, y, xa_in, xa_out);
+    HIPCHK(letkf_launch_analysis_f64(&A, fused, grid_for(h), h->lds, s));
+  } else {
+    auto A = make_args<float>(h, fused, V, y, xa_in, xa_out);
+    HIPCHK(letkf_launch_analysis_f32(&A, fused, grid_for(h), h->lds, s));
+  }
+  return LETKF_OK;
+}
+
+int check_noise(letkf_handle *h, const void *V) {
+  if (!V && !h->all_bank)
+    return fail(LETKF_E_INVAL, "no V given and not every instance has a noise bank");
+  return LETKF_OK;
+}
+
+// Build (once per parity) or refresh the graph of the fused frame.
+int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
+  const int p = h->cur;
+  std::vector<unsigned char> args;
+  if (h->fp64) {
+    auto A = make_args<double>(h, true, V, y, p, 1 - p);
+    args.assign((unsigned char *)&A, (unsigned char *)&A + sizeof(A));
+  } else {
+    auto A = make_args<float>(h, true, V, y, p, 1 - p);
+    args.assign((unsigned char *)&A, (unsigned char *)&A + sizeof(A));
+  }
+  hipKernelNodeParams kp{};
+  kp.blockDim = dim3(64);
+  kp.gridDim = dim3(grid_for(h));
+  kp.func = (void *)letkf_analysis_kernel(h->fp64, 1);
+  kp.sharedMemBytes = (unsigned)h->lds;
+  if (!h->gexec[p]) {
+    h->gargs[p] = args;
+    void *kargs[] = {h->gargs[p].data()};
+    kp.kernelParams = kargs;
+    kp.extra = nullptr;
+    HIPCHK(hipGraphCreate(&h->graph[p], 0));
+    HIPCHK(hipGraphAddKernelNode(&h->gnode[p], h->graph[p], nullptr, 0, &kp));
+    // then the frame counter of the bank draws
+    hipKernelNodeParams kp2{};
+    void *a2[] = {&h->d_frame};
+    kp2.blockDim = dim3(64);
+    kp2.gridDim = dim3(1);
+    kp2.func = (void *)letkf_frame_advance_kernel();
+    kp2.kernelParams = a2;
+    kp2.extra = nullptr;
+    kp2.sharedMemBytes = 0;
+    hipGraphNode_t adv;
+    HIPCHK(hipGraphAddKernelNode(&adv, h->graph[p], &h->gnode[p], 1, &kp2));
+    HIPCHK(hipGraphInstantiate(&h->gexec[p], h->graph[p], nullptr, nullptr, 0));
+  } else if (args != h->gargs[p]) {
+    h->gargs[p] = args;
+    void *kargs[] = {h->gargs[p].data()};
+    kp.kernelParams = kargs;
+    kp.extra = nullptr;
+    HIPCHK(hipGraphExecKernelNodeSetParams(h->gexec[p], h->gnode[p], &kp));
+  }
+  HIPCHK(hipGraphLaunch(h->gexec[p], s));
+  return LETKF_OK;
+}
+
+}  // namespace
+
+static void instance_sizes(const InstGeom &g, letkf_sizes &s);
+
+// ======================================================================== ABI
+extern "C" {
+
+const char *letkf_strerror(int code) {
+  switch (code) {
+    case LETKF_OK: return "ok";
+    case LETKF_E_INVAL: return "invalid argument or configuration";
+    case LETKF_E_NOMEM: return "out of memory";
+    case LETKF_E_DEVICE: return "HIP runtime error";
+    case LETKF_E_NONFINITE: return "non-finite slopes or update in at least one domain";
+    case LETKF_E_NOCONV: return "eigensolve did not converge in at least one domain";
+    case LETKF_E_STATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+const char *letkf_last_error(void) { return g_last_error.c_str(); }
+
+int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, letkf_handle **out) {
+  if (!out) return fail(LETKF_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfgs || n_instances < 1) return fail(LETKF_E_INVAL, "need at least one instance");
+  std::string err;
+  for (int i = 0; i < n_instances; ++i) {
+    if (validate(cfgs[i], i, err) != LETKF_OK) return fail(LETKF_E_INVAL, err);
+    if (cfgs[i].precision != cfgs[0].precision)
+      return fail(LETKF_E_INVAL, "all instances of a handle must share the precision");
+  }
+  letkf_handle *h = new letkf_handle();
+  h->device = device;
+  h->fp64 = cfgs[0].precision == LETKF_FP64;
+  h->esize = h->fp64 ? 8 : 4;
+  h->n_inst = n_instances;
+  h->jtol = cfgs[0].jacobi_tol > 0 ? cfgs[0].jacobi_tol : (h->fp64 ? 1e-10 : 1e-5);
+  h->max_sweeps = cfgs[0].max_sweeps > 0 ? cfgs[0].max_sweeps : 30;
+  h->geom.resize(n_instances);
+  std::vector<int32_t> patch, obs_sub, node_ij, subap_nodes;
+  std::vector<uint32_t> obs_corner;
+  std::vector<double> obs_dist;
+  std::vector<float> bank;
+  std::vector<double> r;
+  int64_t x_off = 0, y_off = 0, node_off = 0, bank_off = 0;
+  int dom_total = 0;
+  for (int i = 0; i < n_instances; ++i) {
+    const letkf_config &c = cfgs[i];
+    InstGeom &g = h->geom[i];
+    int rc = plan_instance(c, g, err);
+    if (rc != LETKF_OK) {
+      free_handle(h);
+      return fail(rc, "instance " + std::to_string(i) + ": " + err);
+    }
+    InstDesc d{};
+    d.x_off = x_off;
+    d.y_off = y_off;
+    d.node_off = node_off;
+    d.bank_off = c.noise_bank ? bank_off : -1;
+    d.n_nodes = g.n_nodes;
+    d.n_slopes = 2 * g.n_subaps;
+    d.n_subaps = g.n_subaps;
+    d.m = c.m;
+    d.bank_screens = c.noise_bank ? c.bank_screens : 0;
+    d.bank_side = c.noise_bank ? c.bank_side : 0;
+    d.seed_lo = (uint32_t)(c.seed & 0xffffffffu);
+    d.seed_hi = (uint32_t)(c.seed >> 32);
+    d.instance = (uint32_t)i;
+    d.a = c.ar_coeff;
+    d.rho = c.rho;
+    d.r_scale = c.r_scale;
+    d.taper_c = c.taper_c;
+    h->desc.push_back(d);
+    for (int q = 0; q < 2 * g.n_subaps; ++q) {
+      const double rv = c.r_diag ? c.r_diag[q] : c.r_sigma2;
+      if (!(rv > 0)) {
+        free_handle(h);
+        return fail(LETKF_E_INVAL, "instance " + std::to_string(i) + ": noise variances must be > 0");
+      }
+      r.push_back(rv);
+    }
+    node_ij.insert(node_ij.end(), g.node_ij.begin(), g.node_ij.end());
+    subap_nodes.insert(subap_nodes.end(), g.subap_nodes.begin(), g.subap_nodes.end());
+    if (c.noise_bank) {
+      const size_t nb = (size_t)c.bank_screens * c.bank_side * c.bank_side;
+      bank.insert(bank.end(), c.noise_bank, c.noise_bank + nb);
+      bank_off += (int64_t)nb;
+      h->any_bank = true;
+    } else {
+      h->all_bank = false;
+    }
+    h->dom_base.push_back(dom_total);
+    for (size_t dd = 0; dd < g.owned.size(); ++dd) {
+      DomItem it{};
+      it.inst = i;
+      it.dom = (int)dd;
+      it.n_own = (int)g.owned[dd].size();
+      it.n_patch = (int)g.patch[dd].size();
+      it.n_obs = (int)g.obs_sub[dd].size();
+      it.patch_off = (int)patch.size();
+      it.obs_off = (int)obs_sub.size();
+      patch.insert(patch.end(), g.patch[dd].begin(), g.patch[dd].end());
+      obs_sub.insert(obs_sub.end(), g.obs_sub[dd].begin(), g.obs_sub[dd].end());
+      obs_corner.insert(obs_corner.end(), g.obs_corner[dd].begin(), g.obs_corner[dd].end());
+      obs_dist.insert(obs_dist.end(), g.obs_dist[dd].begin(), g.obs_dist[dd].end());
+      h->items.push_back(it);
+      h->max_patch = std::max(h->max_patch, it.n_patch);
+      h->max_obs_sub = std::max(h->max_obs_sub, it.n_obs);
+      h->max_own = std::max(h->max_own, it.n_own);
+      h->total_obs += 2 * it.n_obs;
+    }
+    dom_total += (int)g.owned.size();
+    h->max_m = std::max(h->max_m, c.m);
+    h->max_subaps = std::max(h->max_subaps, g.n_subaps);
+    h->max_nodes = std::max(h->max_nodes, g.n_nodes);
+    h->max_elems = std::max(h->max_elems, (int64_t)g.n_nodes * c.m);
+    x_off += (int64_t)g.n_nodes * c.m;
+    y_off += 2LL * g.n_subaps;
+    node_off += g.n_nodes;
+  }
+  h->total_x = x_off;
+  h->total_y = y_off;
+  h->total_nodes = node_off;
+  // LDS layout of the analysis kernel
+  const size_t T = h->esize;
+  const size_t p4 = (size_t)((2 * h->max_obs_sub + 3) & ~3);
+  size_t o = 0;
+  h->off[0] = (int32_t)o; o = align16(o + (size_t)h->max_patch * kXsStride * T);
+  h->off[1] = (int32_t)o; o = align16(o + 64 * T);
+  h->off[2] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * 8);
+  h->off[3] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * 8);
+  h->off[4] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * T);
+  h->off[5] = (int32_t)o; o = align16(o + 64 * 4);
+  h->off[6] = (int32_t)o; o = align16(o + 6 * 64 * 8);
+  h->off[7] = (int32_t)o;
+  size_t u = std::max({p4 * kYsStride * T, (size_t)64 * kXsStride * T, (size_t)64 * 33 * 8,
+                       (size_t)64 * kYsStride * T});
+  h->lds = align16(o + u);
+
+  int rc = LETKF_OK;
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    free_handle(h);
+    return fail(LETKF_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  }
+  for (int fused = 0; fused < 2; ++fused)
+    hipFuncSetAttribute(letkf_analysis_kernel(h->fp64, fused),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
+  (void)hipGetLastError();
+  if ((rc = to_device(&h->d_desc, h->desc)) || (rc = to_device(&h->d_items, h->items)) ||
+      (rc = to_device(&h->d_patch, patch)) || (rc = to_device(&h->d_obs_sub, obs_sub)) ||
+      (rc = to_device(&h->d_obs_corner, obs_corner)) || (rc = to_device(&h->d_obs_dist, obs_dist)) ||
+      (rc = to_device(&h->d_node_ij, node_ij)) || (rc = to_device(&h->d_subap_nodes, subap_nodes)) ||
+      (rc = to_device(&h->d_r, r)) || (rc = to_device(&h->d_bank, bank))) {
+    free_handle(h);
+    return rc;
+  }
+  const size_t xbytes = (size_t)h->total_x * T;
+  for (void **p : {&h->d_xa[0], &h->d_xa[1], &h->d_xb}) {
+    if (hipMalloc(p, std::max<size_t>(xbytes, 16)) != hipSuccess) {
+      free_handle(h);
+      return fail(LETKF_E_NOMEM, "hipMalloc of the ensemble failed");
+    }
+    hipMemset(*p, 0, std::max<size_t>(xbytes, 16));
+  }
+  if (hipMalloc(&h->d_tmp, std::max<size_t>((size_t)h->total_nodes * T, 16)) != hipSuccess ||
+      hipMalloc((void **)&h->d_frame, 16) != hipSuccess ||
+      hipMalloc((void **)&h->d_flags, std::max<size_t>(h->items.size(), 1) * 4) != hipSuccess) {
+    free_handle(h);
+    return fail(LETKF_E_NOMEM, "hipMalloc failed");
+  }
+  hipMemset(h->d_frame, 0, 16);
+  hipMemset(h->d_flags, 0, std::max<size_t>(h->items.size(), 1) * 4);
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_handle(h);
+    return fail(LETKF_E_DEVICE, std::string("create: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return LETKF_OK;
+}
+
+void letkf_destroy(letkf_handle *h) { free_handle(h); }
+
+int letkf_query(letkf_handle *h, int32_t instance, letkf_sizes *out) {
+  if (!h || !out) return fail(LETKF_E_INVAL, "NULL argument");
+  if (instance < -1 || instance >= h->n_inst) return fail(LETKF_E_INVAL, "bad instance");
+  letkf_sizes s{};
+  s.n_instances = h->n_inst;
+  if (instance < 0) {
+    s.n_nodes = h->total_nodes;
+    s.n_slopes = h->total_y;
+    s.n_domains = (int64_t)h->items.size();
+    s.ensemble_elems = h->total_x;
+    s.obs_total = h->total_obs;
+    s.m = h->max_m;
+    s.max_owned = h->max_own;
+    s.max_obs = 2 * h->max_obs_sub;
+    s.max_patch = h->max_patch;
+  } else {
+    instance_sizes(h->geom[instance], s);
+    s.n_instances = h->n_inst;
+  }
+  *out = s;
+  return LETKF_OK;
+}
+
+static void export_maps(const InstGeom &g, int32_t *node_ij, int32_t *owner, int32_t *obs_off,
+                        int32_t *obs_idx, int32_t *own_off, int32_t *own_idx) {
+  if (node_ij) std::copy(g.node_ij.begin(), g.node_ij.end(), node_ij);
+  if (owner) std::copy(g.owner.begin(), g.owner.end(), owner);
+  const int nd = (int)g.owned.size();
+  int64_t o = 0, w = 0;
+  for (int d = 0; d < nd; ++d) {
+    if (obs_off) obs_off[d] = (int32_t)o;
+    if (own_off) own_off[d] = (int32_t)w;
+    for (int q : g.obs_sub[d]) {
+      if (obs_idx) obs_idx[o] = q;
+      ++o;
+    }
+    for (int q : g.obs_sub[d]) {
+      if (obs_idx) obs_idx[o] = q + g.n_subaps;
+      ++o;
+    }
+    for (int n : g.owned[d]) {
+      if (own_idx) own_idx[w] = n;
+      ++w;
+    }
+  }
+  if (obs_off) obs_off[nd] = (int32_t)o;
+  if (own_off) own_off[nd] = (int32_t)w;
+}
+
+static void instance_sizes(const InstGeom &g, letkf_sizes &s) {
+  s = letkf_sizes{};
+  s.n_instances = 1;
+  s.n_nodes = g.n_nodes;
+  s.n_slopes = 2 * g.n_subaps;
+  s.n_domains = (int64_t)g.owned.size();
+  s.ensemble_elems = (int64_t)g.n_nodes * g.m;
+  s.m = g.m;
+  s.n_sub = g.N;
+  for (size_t d = 0; d < g.owned.size(); ++d) {
+    s.obs_total += 2 * (int64_t)g.obs_sub[d].size();
+    s.max_owned = std::max(s.max_owned, (int32_t)g.owned[d].size());
+    s.max_obs = std::max(s.max_obs, (int32_t)(2 * g.obs_sub[d].size()));
+    s.max_patch = std::max(s.max_patch, (int32_t)g.patch[d].size());
+  }
+}
+
+int letkf_geometry(letkf_handle *h, int32_t instance, int32_t *node_ij, int32_t *owner,
+                   int32_t *obs_off, int32_t *obs_idx, int32_t *own_off, int32_t *own_idx) {
+  if (!h || instance < 0 || instance >= h->n_inst) return fail(LETKF_E_INVAL, "bad instance");
+  export_maps(h->geom[instance], node_ij, owner, obs_off, obs_idx, own_off, own_idx);
+  return LETKF_OK;
+}
+
+int letkf_plan(const letkf_config *cfg, letkf_sizes *sizes, int32_t *node_ij, int32_t *owner,
+               int32_t *obs_off, int32_t *obs_idx, int32_t *own_off, int32_t *own_idx) {
+  if (!cfg) return fail(LETKF_E_INVAL, "cfg is NULL");
+  std::string err;
+  if (validate(*cfg, 0, err) != LETKF_OK) return fail(LETKF_E_INVAL, err);
+  InstGeom g;
+  if (plan_instance(*cfg, g, err) != LETKF_OK) return fail(LETKF_E_INVAL, err);
+  if (sizes) instance_sizes(g, *sizes);
+  export_maps(g, node_ij, owner, obs_off, obs_idx, own_off, own_idx);
+  return LETKF_OK;
+}
+
+int letkf_forecast(letkf_handle *h, const void *V_dev, void *stream) {
+  if (!h) return fail(LETKF_E_INVAL, "NULL handle");
+  int rc = check_noise(h, V_dev);
+  if (rc) return rc;
+  hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(letkf_launch_forecast(h->fp64, h->d_desc, h->n_inst, h->d_node_ij, h->d_xa[h->cur], V_dev,
+                               h->d_bank, h->d_frame, h->d_xb, h->max_elems, s));
+  HIPCHK(letkf_launch_frame_advance(h->d_frame, s));
+  h->have_xb = true;
+  return LETKF_OK;
+}
+
+int letkf_analyse(letkf_handle *h, const void *y_dev, void *stream) {
+  if (!h || !y_dev) return fail(LETKF_E_INVAL, "NULL argument");
+  if (!h->have_xb) return fail(LETKF_E_STATE, "letkf_analyse needs a preceding letkf_forecast");
+  hipSetDevice(h->device);
+  int rc = launch_analysis(h, false, nullptr, y_dev, h->cur, h->cur, (hipStream_t)stream);
+  if (rc) return rc;
+  h->have_xb = false;
+  return LETKF_OK;
+}
+
+int letkf_step(letkf_handle *h, const void *V_dev, const void *y_dev, void *stream) {
+  if (!h || !y_dev) return fail(LETKF_E_INVAL, "NULL argument");
+  int rc = check_noise(h, V_dev);
+  if (rc) return rc;
+  hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (h->use_graph) {
+    rc = graph_step(h, V_dev, y_dev, s);  // analysis + frame advance
+    if (rc) return rc;
+  } else {
+    rc = launch_analysis(h, true, V_dev, y_dev, h->cur, 1 - h->cur, s);
+    if (rc) return rc;
+    HIPCHK(letkf_launch_frame_advance(h->d_frame, s));
+  }
+  h->cur = 1 - h->cur;
+  h->have_xb = false;
+  return LETKF_OK;
+}
+
+int letkf_step_plain(letkf_handle *h, const void *V_dev, const void *y_dev, void *stream) {
+  if (!h || !y_dev) return fail(LETKF_E_INVAL, "NULL argument");
+  int rc = check_noise(h, V_dev);
+  if (rc) return rc;
+  hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int n = (int)h->items.size();
+  for (int i = 0; i < n; ++i) {
+    if (h->fp64) {
+      auto A = make_args<double>(h, true, V_dev, y_dev, h->cur, 1 - h->cur);
+      A.item_base = i;
+      A.xcd_order = 0;
+      HIPCHK(letkf_launch_analysis_f64(&A, 1, 1, h->lds, s));
+    } else {
+      auto A = make_args<float>(h, true, V_dev, y_dev, h->cur, 1 - h->cur);
+      A.item_base = i;
+      A.xcd_order = 0;
+      HIPCHK(letkf_launch_analysis_f32(&A, 1, 1, h->lds, s));
+    }
+  }
+  HIPCHK(letkf_launch_frame_advance(h->d_frame, s));
+  h->cur = 1 - h->cur;
+  h->have_xb = false;
+  return LETKF_OK;
+}
+
+static int copy_state(letkf_handle *h, void *dst, const void *src, size_t bytes, int on_device,
+                      bool to_dev_state) {
+  hipSetDevice(h->device);
+  HIPCHK(hipDeviceSynchronize());
+  hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice
+                              : (to_dev_state ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost);
+  HIPCHK(hipMemcpy(dst, src, bytes, k));
+  return LETKF_OK;
+}
+
+int letkf_get_ensemble(letkf_handle *h, void *dst, int on_device) {
+  if (!h || !dst) return fail(LETKF_E_INVAL, "NULL argument");
+  return copy_state(h, dst, h->d_xa[h->cur], (size_t)h->total_x * h->esize, on_device, false);
+}
+
+int letkf_set_ensemble(letkf_handle *h, const void *src, int on_device) {
+  if (!h || !src) return fail(LETKF_E_INVAL, "NULL argument");
+  h->have_xb = false;
+  return copy_state(h, h->d_xa[h->cur], src, (size_t)h->total_x * h->esize, on_device, true);
+}
+
+int letkf_get_forecast(letkf_handle *h, void *dst, int on_device) {
+  if (!h || !dst) return fail(LETKF_E_INVAL, "NULL argument");
+  if (!h->have_xb) return fail(LETKF_E_STATE, "no forecast pending");
+  return copy_state(h, dst, h->d_xb, (size_t)h->total_x * h->esize, on_device, false);
+}
+
+int letkf_get_mean(letkf_handle *h, void *dst, int on_device) {
+  if (!h || !dst) return fail(LETKF_E_INVAL, "NULL argument");
+  hipSetDevice(h->device);
+  HIPCHK(letkf_launch_mean(h->fp64, h->d_desc, h->n_inst, h->d_xa[h->cur], h->d_tmp, h->max_nodes,
+                           nullptr));
+  return copy_state(h, dst, h->d_tmp, (size_t)h->total_nodes * h->esize, on_device, false);
+}
+
+int letkf_get_frame(letkf_handle *h, uint32_t *frame) {
+  if (!h || !frame) return fail(LETKF_E_INVAL, "NULL argument");
+  return copy_state(h, frame, h->d_frame, 4, 0, false);
+}
+
+int letkf_set_frame(letkf_handle *h, uint32_t frame) {
+  if (!h) return fail(LETKF_E_INVAL, "NULL handle");
+  return copy_state(h, h->d_frame, &frame, 4, 0, true);
+}
+
+int letkf_status(letkf_handle *h, int32_t *flags) {
+  if (!h || !flags) return fail(LETKF_E_INVAL, "NULL argument");
+  std::vector<int32_t> f(h->items.size());
+  int rc = copy_state(h, f.data(), h->d_flags, f.size() * 4, 0, false);
+  if (rc) return rc;
+  int any = 0;
+  for (size_t i = 0; i < f.size(); ++i) {
+    const DomItem &it = h->items[i];
+    flags[h->dom_base[it.inst] + it.dom] = f[i];
+    any |= f[i];
+  }
+  if (any & LETKF_FLAG_NONFINITE) return LETKF_E_NONFINITE;
+  if (any & LETKF_FLAG_NOCONV) return LETKF_E_NOCONV;
+  return LETKF_OK;
+}
+
+int letkf_set_params(letkf_handle *h, int32_t instance, double rho, double r_scale, double taper_c) {
+  if (!h || instance < 0 || instance >= h->n_inst) return fail(LETKF_E_INVAL, "bad instance");
+  if (!(rho > 0) || !(r_scale > 0) || !(taper_c >= 0)) return fail(LETKF_E_INVAL, "bad parameter");
+  InstDesc &d = h->desc[instance];
+  d.rho = rho;
+  d.r_scale = r_scale;
+  d.taper_c = taper_c;
+  hipSetDevice(h->device);
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(h->d_desc + instance, &d, sizeof(d), hipMemcpyHostToDevice));
+  return LETKF_OK;
+}
+
+int letkf_slopes(letkf_handle *h, const void *phase_dev, void *slopes_dev, void *stream) {
+  if (!h || !phase_dev || !slopes_dev) return fail(LETKF_E_INVAL, "NULL argument");
+  hipSetDevice(h->device);
+  HIPCHK(letkf_launch_slopes(h->fp64, h->d_desc, h->n_inst, h->d_subap_nodes, phase_dev, slopes_dev,
+                             h->max_subaps, (hipStream_t)stream));
+  return LETKF_OK;
+}
+
+int letkf_set_schedule(letkf_handle *h, int32_t use_graph, int32_t xcd_order) {
+  if (!h) return fail(LETKF_E_INVAL, "NULL handle");
+  if (xcd_order != h->xcd_order) {
+    for (int p = 0; p < 2; ++p) {
+      if (h->gexec[p]) hipGraphExecDestroy(h->gexec[p]);
+      if (h->graph[p]) hipGraphDestroy(h->graph[p]);
+      h->gexec[p] = nullptr;
+      h->graph[p] = nullptr;
+      h->gargs[p].clear();
+    }
+  }
+  h->use_graph = use_graph ? 1 : 0;
+  h->xcd_order = xcd_order ? 1 : 0;
+  return LETKF_OK;
+}
+
+int letkf_get_schedule(letkf_handle *h, int32_t *use_graph, int32_t *xcd_order) {
+  if (!h) return fail(LETKF_E_INVAL, "NULL handle");
+  if (use_graph) *use_graph = h->use_graph;
+  if (xcd_order) *xcd_order = h->xcd_order;
+  return LETKF_OK;
+}
+
+int letkf_autotune(letkf_handle *h, const void *V_dev, const void *y_dev, int32_t frames,
+                   const char *cache_path, void *stream) {
+  if (!h || !y_dev || frames < 1) return fail(LETKF_E_INVAL, "bad argument");
+  std::ostringstream key;
+  key << "gfx950 fp" << (h->fp64 ? 64 : 32) << " items " << h->items.size() << " m " << h->max_m
+      << " patch " << h->max_patch << " obs " << h->max_obs_sub;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      const size_t bar = line.find(" | ");
+      if (bar != std::string::npos && line.substr(0, bar) == key.str()) {
+        int g = 1, x = 1;
+        if (sscanf(line.c_str() + bar + 3, "graph %d xcd %d", &g, &x) == 2)
+          return letkf_set_schedule(h, g, x);
+      }
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipSetDevice(h->device);
+  // keep the state: tuning frames must not change it
+  const size_t xbytes = (size_t)h->total_x * h->esize;
+  void *backup = nullptr;
+  HIPCHK(hipMalloc(&backup, std::max<size_t>(xbytes, 16)));
+  uint32_t frame0 = 0;
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(backup, h->d_xa[h->cur], xbytes, hipMemcpyDeviceToDevice));
+  HIPCHK(hipMemcpy(&frame0, h->d_frame, 4, hipMemcpyDeviceToHost));
+  const int cur0 = h->cur;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bg = 1, bx = 1;
+  for (int g = 0; g < 2; ++g)
+    for (int x = 0; x < 2; ++x) {
+      letkf_set_schedule(h, g, x);
+      int rc = letkf_step(h, V_dev, y_dev, stream);  // warm-up (and graph build)
+      if (rc) return rc;
+      HIPCHK(hipEventRecord(e0, s));
+      for (int f = 0; f < frames; ++f)
+        if ((rc = letkf_step(h, V_dev, y_dev, stream))) return rc;
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        bg = g;
+        bx = x;
+      }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  HIPCHK(hipDeviceSynchronize());
+  h->cur = cur0;
+  HIPCHK(hipMemcpy(h->d_xa[h->cur], backup, xbytes, hipMemcpyDeviceToDevice));
+  HIPCHK(hipMemcpy(h->d_frame, &frame0, 4, hipMemcpyHostToDevice));
+  hipFree(backup);
+  letkf_set_schedule(h, bg, bx);
+  if (cache_path) {
+    std::ofstream o(cache_path, std::ios::app);
+    o << key.str() << " | graph " << bg << " xcd " << bx << " ms_per_frame " << best / frames << "\n";
+  }
+  return LETKF_OK;
+}
+
+int letkf_eigh_spd(const double *A_dev, int32_t m, int32_t batch, double tol, int32_t max_sweeps,
+                   double *Q_dev, double *lam_dev, int32_t *sweeps_dev, void *stream) {
+  if (!A_dev || !Q_dev || !lam_dev || m < 1 || m > 64 || batch < 0)
+    return fail(LETKF_E_INVAL, "bad argument");
+  if (batch == 0) return LETKF_OK;
+  HIPCHK(letkf_launch_eigh(A_dev, m, batch, tol > 0 ? tol : 1e-12, max_sweeps > 0 ? max_sweeps : 30,
+                           Q_dev, lam_dev, sweeps_dev, (hipStream_t)stream));
+  return LETKF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Device-side descriptors shared by the host planner and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+
+namespace letkf {
+
+constexpr int kLanes = 64;        // one wavefront per local analysis
+constexpr int kMaxObsSub = 64;    // (b + 2h)^2 observation subapertures at most
+constexpr int kMaxOwned = 64;     // (b + 1)^2 owned nodes at most
+constexpr int kMaxPatch = 64;     // owned nodes + every corner of the region
+constexpr int kYsStride = 80;     // row stride of K-major MFMA operands (no bank conflicts)
+constexpr int kXsStride = 65;     // row stride of node rows (lane = row reads)
+
+// One adaptive-optics instance.
+struct InstDesc {
+  int64_t x_off;       // element offset of [node][m] ensemble
+  int64_t y_off;       // offset of its slopes (and of its r_diag entries)
+  int64_t node_off;    // offset of its node_ij / node tables
+  int64_t bank_off;    // element offset of its noise bank (-1: none)
+  int32_t n_nodes, n_slopes, n_subaps, m;
+  int32_t bank_screens, bank_side;
+  uint32_t seed_lo, seed_hi;
+  uint32_t instance, pad0;
+  double a, rho, r_scale, taper_c;
+};
+
+// One (instance, domain) work item.  Patch entries 0..n_own-1 are the owned
+// nodes in ascending order; the rest are the other corners of the region.
+struct DomItem {
+  int32_t inst;
+  int32_t dom;         // domain number within the instance
+  int32_t n_own, n_patch, n_obs;   // n_obs observation subapertures (p_l = 2 n_obs)
+  int32_t patch_off;   // into patch_node
+  int32_t obs_off;     // into obs_corner / obs_sub / obs_dist
+  int32_t pad0;
+};
+
+}  // namespace letkf

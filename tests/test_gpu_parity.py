@@ -1,0 +1,284 @@
+"""Parity of the HIP frame with the FP64 oracle, through the C ABI.
+
+Bars: FP64 handles 1e-10 and FP32 handles 1e-4 in max relative error
+(max |gpu - oracle| / max |oracle|) on the analysis mean and members, per
+frame from identical inputs; integer maps and noise draws bit-exact."""
+import numpy as np
+import pytest
+
+from _cases import Case, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def B():
+    from paper_1408_7069_amd import binding
+    return binding
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a).ravel()).to(DEV)
+
+
+def _ens(f, m):
+    return f.get_ensemble().cpu().numpy().astype(np.float64).reshape(-1, m)
+
+
+def _frame_vs_oracle(case, f, Xa_prev, V, y):
+    f.step(_t(y), V=_t(V))
+    torch.cuda.synchronize()
+    got = _ens(f, case.m)
+    Xb = case.prm.a * Xa_prev + np.asarray(V, np.float64)
+    ref = case.oracle_analysis(Xb, y)
+    return got, ref
+
+
+@pytest.mark.parametrize("fp64,tol", [(True, 1e-10), (False, 1e-4)])
+def test_smallest_workload_frames(fp64, tol):
+    # 8x8 square pupil, 2x2 domains, halo 1, m = 20 (16 domains)
+    case = Case(8, None, 2, 1, 20, seed=1, fp64=fp64, pitch=0.4)
+    f = B().Letkf([case.spec(B())])
+    Xa = np.zeros((case.G.n_nodes, case.m))
+    for k in range(6):
+        V, y = case.noise(), case.slopes(case.truth())
+        got, ref = _frame_vs_oracle(case, f, Xa, V, y)
+        assert rel_err(got.mean(1), ref.mean(1)) <= tol, k
+        assert rel_err(got, ref) <= tol, k
+        Xa = ref
+    rc, flags = f.status()
+    assert rc == 0 and not flags.any()
+
+
+@pytest.mark.parametrize("fp64,tol", [(True, 1e-10), (False, 1e-4)])
+def test_forecast_then_analyse_equals_fused_step(fp64, tol):
+    case = Case(12, 0.28, 4, 1, 32, seed=2, fp64=fp64)
+    bb = B()
+    f1, f2 = bb.Letkf([case.spec(bb)]), bb.Letkf([case.spec(bb)])
+    X0 = (case.rng.standard_normal((case.G.n_nodes, case.m)) * 3).astype(case.dt)
+    f1.set_ensemble(_t(X0))
+    f2.set_ensemble(_t(X0))
+    V, y = case.noise(), case.slopes(case.truth())
+    f1.forecast(_t(V))
+    Xb = f1.get_forecast().cpu().numpy().astype(np.float64).reshape(-1, case.m)
+    ref_b = case.prm.a * X0.astype(np.float64) + V.astype(np.float64)
+    assert rel_err(Xb, ref_b) <= (1e-15 if fp64 else 1e-6)
+    f1.analyse(_t(y))
+    f2.step(_t(y), V=_t(V))
+    torch.cuda.synchronize()
+    a1, a2 = _ens(f1, case.m), _ens(f2, case.m)
+    assert np.array_equal(a1, a2)
+    ref = case.oracle_analysis(Xb, y)
+    assert rel_err(a1, ref) <= tol
+
+
+def test_analyse_before_forecast_is_a_state_error():
+    case = Case(8, None, 2, 1, 8, seed=3)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    with pytest.raises(bb.LetkfError) as e:
+        f.analyse(_t(case.slopes(case.truth())))
+    assert e.value.code == bb.E_STATE
+
+
+@pytest.mark.parametrize("fp64,tol", [(True, 1e-10), (False, 1e-4)])
+def test_taper_and_noise_scale(fp64, tol):
+    # the 12x12 copy of the tuning workload: Gaspari-Cohn taper c = 2, s != 1
+    case = Case(12, 0.28, 4, 1, 64, seed=4, fp64=fp64, taper_c=2.0, r_scale=1.3)
+    f = B().Letkf([case.spec(B())])
+    Xa = np.zeros((case.G.n_nodes, case.m))
+    for k in range(3):
+        V, y = case.noise(), case.slopes(case.truth())
+        got, ref = _frame_vs_oracle(case, f, Xa, V, y)
+        assert rel_err(got, ref) <= tol, k
+        Xa = ref
+
+
+def test_bank_draws_match_the_oracle_bit_exactly():
+    case = Case(16, 0.2, 4, 1, 48, seed=5)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    for frame in range(3):
+        assert f.get_frame() == frame
+        f.forecast(None)
+        Xb = f.get_forecast().cpu().numpy().reshape(-1, case.m)
+        ref = case.bank_V(frame).astype(np.float32)   # X_a = 0: X_b is the draw itself
+        assert np.array_equal(Xb, ref), frame
+        f.set_ensemble(torch.zeros(f.sizes["ensemble_elems"], dtype=torch.float32, device=DEV))
+
+
+def test_fused_step_with_bank_noise():
+    case = Case(20, 0.28, 4, 1, 40, seed=6)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    Xa = np.zeros((case.G.n_nodes, case.m))
+    for frame in range(3):
+        y = case.slopes(case.truth())
+        f.step(_t(y), V=None)
+        torch.cuda.synchronize()
+        got = _ens(f, case.m)
+        ref = case.oracle_analysis(case.prm.a * Xa + case.bank_V(frame), y)
+        assert rel_err(got, ref) <= 1e-4, frame
+        Xa = ref
+
+
+def test_full_size_80x80_m64_in_the_timed_configuration():
+    # the benchmark shape (4632 subapertures, 4836 nodes, 332 domains), graph
+    # replay with the XCD-ordered work list, compared domain by domain
+    case = Case(80, 0.28, 4, 1, 64, seed=7)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    f.set_schedule(True, True)
+    assert f.sizes["n_domains"] == 332 and f.sizes["n_nodes"] == 4836
+    Xa = np.zeros((case.G.n_nodes, case.m))
+    for frame in range(2):
+        y = case.slopes(case.truth())
+        f.step(_t(y), V=None)
+        torch.cuda.synchronize()
+        got = _ens(f, case.m)
+        ref = case.oracle_analysis(case.prm.a * Xa + case.bank_V(frame), y)
+        assert rel_err(got.mean(1), ref.mean(1)) <= 1e-4
+        assert rel_err(got, ref) <= 1e-4
+        worst = max(rel_err(got[d.owned], ref[d.owned]) for d in case.doms)
+        assert worst <= 1e-3
+        Xa = ref
+
+
+def test_many_instances_in_one_launch():
+    bb = B()
+    cases = [Case(16, 0.0, 4, 1, 32, seed=10), Case(23, 0.14, 4, 1, 48, seed=11),
+             Case(12, 0.28, 4, 1, 64, seed=12), Case(9, None, 3, 1, 20, seed=13)]
+    f = bb.Letkf([c.spec(bb) for c in cases])
+    V = [c.noise() for c in cases]
+    ys = [c.slopes(c.truth()) for c in cases]
+    f.step(_t(np.concatenate([y.ravel() for y in ys])), V=_t(np.concatenate([v.ravel() for v in V])))
+    torch.cuda.synchronize()
+    got = f.get_ensemble().cpu().numpy().astype(np.float64)
+    off = 0
+    for c, v, y in zip(cases, V, ys):
+        n = c.G.n_nodes * c.m
+        ref = c.oracle_analysis(v, y)
+        assert rel_err(got[off:off + n].reshape(-1, c.m), ref) <= 1e-4
+        off += n
+
+
+def test_plain_graph_and_direct_launches_agree_bitwise():
+    case = Case(24, 0.2, 4, 1, 64, seed=14)
+    bb = B()
+    outs = []
+    for mode in ["plain", (True, True), (True, False), (False, True), (False, False)]:
+        f = bb.Letkf([case.spec(bb)])
+        rng = np.random.default_rng(0)
+        for k in range(2):
+            y = (rng.standard_normal(case.G.n_slopes) * 2).astype(np.float32)
+            if mode == "plain":
+                f.step_plain(_t(y), V=None)
+            else:
+                f.set_schedule(*mode)
+                f.step(_t(y), V=None)
+        torch.cuda.synchronize()
+        outs.append(f.get_ensemble().cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
+def test_restart_continues_bit_identically():
+    case = Case(16, 0.28, 4, 1, 32, seed=15)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    ys = [case.slopes(case.truth()) for _ in range(5)]
+    for y in ys[:3]:
+        f.step(_t(y), V=None)
+    state, frame = f.get_ensemble().clone(), f.get_frame()
+    g = bb.Letkf([case.spec(bb)])
+    g.set_ensemble(state)
+    g.set_frame(frame)
+    for y in ys[3:]:
+        f.step(_t(y), V=None)
+        g.step(_t(y), V=None)
+    torch.cuda.synchronize()
+    assert np.array_equal(f.get_ensemble().cpu().numpy(), g.get_ensemble().cpu().numpy())
+
+
+def test_flags_nonfinite_and_noconv():
+    case = Case(16, 0.0, 4, 1, 32, seed=16)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    X0 = (case.rng.standard_normal((case.G.n_nodes, case.m))).astype(np.float32)
+    f.set_ensemble(_t(X0))
+    V = case.noise()
+    y = case.slopes(case.truth())
+    y[case.doms[0].obs[0]] = np.nan
+    f.forecast(_t(V))
+    Xb = f.get_forecast().cpu().numpy().reshape(-1, case.m)
+    f.analyse(_t(y))
+    rc, flags = f.status()
+    assert rc == bb.E_NONFINITE
+    hit = [k for k, d in enumerate(case.doms) if case.doms[0].obs[0] in d.obs]
+    assert set(np.nonzero(flags & bb.FLAG_NONFINITE)[0]) == set(hit)
+    got = f.get_ensemble().cpu().numpy().reshape(-1, case.m)
+    for k in hit:
+        assert np.array_equal(got[case.doms[k].owned], Xb[case.doms[k].owned])
+    assert np.isfinite(got).all()
+    # one sweep cannot converge: every domain is flagged and keeps its forecast
+    g = bb.Letkf([case.spec(bb, max_sweeps=1, jacobi_tol=1e-14)])
+    g.set_ensemble(_t(X0))
+    g.forecast(_t(V))
+    Xb = g.get_forecast().cpu().numpy().reshape(-1, case.m)
+    g.analyse(_t(case.slopes(case.truth())))
+    rc, flags = g.status()
+    assert rc == bb.E_NOCONV and np.all(flags & bb.FLAG_NOCONV)
+    assert np.array_equal(g.get_ensemble().cpu().numpy().reshape(-1, case.m), Xb)
+
+
+@pytest.mark.parametrize("N,eps,b,h,m", [(1, None, 1, 0, 2), (5, None, 1, 0, 3), (13, 0.3, 3, 2, 17),
+                                         (17, 0.0, 5, 1, 64), (10, None, 2, 0, 64), (7, None, 7, 0, 9)])
+def test_edge_shapes(N, eps, b, h, m):
+    case = Case(N, eps, b, h, m, seed=N * 7 + m)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    X0 = (case.rng.standard_normal((case.G.n_nodes, case.m))).astype(np.float32)
+    f.set_ensemble(_t(X0))
+    V, y = case.noise(), case.slopes(case.truth())
+    f.step(_t(y), V=_t(V))
+    torch.cuda.synchronize()
+    got = _ens(f, m)
+    ref = case.oracle_analysis(case.prm.a * X0.astype(np.float64) + V.astype(np.float64), y)
+    assert rel_err(got, ref) <= 1e-4
+
+
+def test_slope_operator_kernel():
+    bb = B()
+    cases = [Case(16, 0.2, 4, 1, 8, seed=20), Case(9, None, 3, 1, 8, seed=21)]
+    f = bb.Letkf([c.spec(bb) for c in cases])
+    ph = [c.truth().astype(np.float32) for c in cases]
+    s = f.slopes(_t(np.concatenate(ph))).cpu().numpy()
+    from oracle import geometry as geo
+    ref = np.concatenate([geo.apply_slopes(c.G, p.astype(np.float64)) for c, p in zip(cases, ph)])
+    assert rel_err(s, ref) <= 1e-6
+
+
+def test_geometry_maps_are_the_oracles():
+    from oracle import geometry as geo
+    case = Case(40, 0.14, 4, 1, 50, seed=22)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    g = f.geometry(0)
+    assert np.array_equal(g["node_ij"], case.G.node_coords())
+    assert np.array_equal(g["owner"], geo.owner_map(case.G, case.doms))
+
+
+def test_runs_are_deterministic():
+    case = Case(32, 0.14, 4, 1, 64, seed=23)
+    bb = B()
+    res = []
+    for _ in range(2):
+        f = bb.Letkf([case.spec(bb)])
+        rng = np.random.default_rng(5)
+        for _k in range(3):
+            f.step(_t((rng.standard_normal(case.G.n_slopes) * 3).astype(np.float32)), V=None)
+        torch.cuda.synchronize()
+        res.append(f.get_ensemble().cpu().numpy())
+    assert np.array_equal(res[0], res[1])
