@@ -17,7 +17,8 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libletkf.so")
+# LETKF_LIBRARY selects another build of the same ABI (e.g. an instrumented one).
+LIB_PATH = os.environ.get("LETKF_LIBRARY", os.path.join(_HERE, "libletkf.so"))
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")

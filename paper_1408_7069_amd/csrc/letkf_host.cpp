@@ -49,6 +49,9 @@ extern "C" hipError_t letkf_launch_eigh(const double *A, int m, int batch, doubl
                                         int max_sweeps, double *Q, double *lam, int32_t *sweeps,
                                         hipStream_t s);
 extern "C" size_t letkf_args_size(int fp64);
+extern "C" int letkf_analysis_threads(void);
+extern "C" size_t letkf_analysis_scratch_doubles(void);
+extern "C" size_t letkf_analysis_tb_bytes(void);
 
 namespace {
 
@@ -393,7 +396,7 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
     args.assign((unsigned char *)&A, (unsigned char *)&A + sizeof(A));
   }
   hipKernelNodeParams kp{};
-  kp.blockDim = dim3(64);
+  kp.blockDim = dim3(letkf_analysis_threads());
   kp.gridDim = dim3(grid_for(h));
   kp.func = (void *)letkf_analysis_kernel(h->fp64, 1);
   kp.sharedMemBytes = (unsigned)h->lds;
@@ -561,9 +564,9 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   h->off[3] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * 8);
   h->off[4] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * T);
   h->off[5] = (int32_t)o; o = align16(o + 64 * 4);
-  h->off[6] = (int32_t)o; o = align16(o + 6 * 64 * 8);
+  h->off[6] = (int32_t)o; o = align16(o + letkf_analysis_scratch_doubles() * 8);
   h->off[7] = (int32_t)o;
-  size_t u = std::max({p4 * kYsStride * T, (size_t)64 * kXsStride * T, (size_t)64 * 33 * 8,
+  size_t u = std::max({p4 * kYsStride * T, (size_t)64 * kXsStride * T, letkf_analysis_tb_bytes(),
                        (size_t)64 * kYsStride * T});
   h->lds = align16(o + u);
 

@@ -1,7 +1,7 @@
 // gfx950 kernels of the local ETKF frame (Gray et al., arXiv:1408.7069).
 //
-// k_analysis: one wavefront per (instance, domain) work item, all items of a
-// frame in one launch.  Per item (Sec. 4.2):
+// k_analysis: one 256-thread workgroup (4 wavefronts) per (instance, domain)
+// work item, all items of a frame in one launch.  Per item (Sec. 4.2):
 //   1. node patch of the forecast ensemble into LDS (fused form: a X_a + V,
 //      Sec. 3.1.2 member prediction), member = lane;
 //   2. member means, the Fried slopes of the observation region (App. B) as
@@ -9,15 +9,22 @@
 //      Sec. 4.1), and the scaled innovation;
 //   3. Gram Y^T Y on the matrix cores (FP32 MFMA 16x16x4; FP64 MFMA in FP64
 //      mode), A~ = (m-1)/rho I + Y^T Y promoted to FP64;
-//   4. FP64 Cholesky A~ = L L^T with row i of L in lane i's registers;
-//   5. FP64 one-sided Jacobi on the columns of L (register resident, parallel
-//      round-robin ordering, column dot products summed through an LDS
-//      transpose) until the columns are orthogonal: L J = U with U^T U =
-//      Lambda and A~ = (U Lambda^{-1/2}) Lambda (U Lambda^{-1/2})^T;
-//   6. W = sqrt(c) U Lambda^{-3/2} U^T on the matrix cores; the mean weights
-//      w = A~^{-1} b come from the Cholesky factor by two triangular solves;
+//   4. FP64 Cholesky A~ = L L^T and the mean weights w = A~^{-1} b by two
+//      triangular solves;
+//   5. FP64 one-sided Jacobi on the columns of L until they are orthogonal:
+//      L J = U with U^T U = Lambda, so A~ = (U Lambda^{-1/2}) Lambda
+//      (U Lambda^{-1/2})^T;
+//   6. W = sqrt(c) U Lambda^{-3/2} U^T on the matrix cores;
 //   7. owned rows: X_a = (x_b + X' w) 1^T + sqrt(rho) X' W (matrix cores),
 //      written straight into the global analysis ensemble (the gather).
+//
+// Layout of the 64 x 64 FP64 factor during stages 4-6: lane = row; the 64
+// columns sit on 64 "positions" of a round-robin tournament, wave q holding
+// positions 8q..8q+7 (lo[j]) and 63-8q-j (hi[j]), so pair k = (k, 63-k) is
+// (lo[j], hi[j]) of one wave.  After each round every position p >= 1 hands
+// its column to p+1 (63 -> 1, 0 fixed): two columns per wave cross to the
+// neighbouring wave through LDS, 63 rounds visit every pair once and bring
+// every column home.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -26,13 +33,16 @@
 
 namespace letkf {
 
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <typename T> struct Mfma;
 // Output row of accumulator element r in `lane` (column = lane % 16): the
 // FP32 16x16x4 form gives each lane four consecutive rows, the FP64 form four
 // rows four apart.
+template <typename T> struct Mfma;
 template <> struct Mfma<float> {
   typedef f32x4 V;
   __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
@@ -120,177 +130,403 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Solve L L^T w = b with row `lane` of L in x[] and b_lane in b: forward then
-// backward substitution; returns w_lane.  invd: 1 / L_kk (LDS).
-__device__ inline double cholesky_solve64(const double x[64], const double *invd, double b,
-                                          int lane) {
-  double r = b, z = 0.0;
-#pragma unroll
-  for (int j = 0; j < 64; ++j) {
-    const double zj = bcast_lane(r, j) * invd[j];
-    if (lane == j) z = zj;
-    if (lane > j) r = fma(-x[j], zj, r);
-  }
-  double w = 0.0;
-#pragma unroll
-  for (int i = 63; i >= 0; --i) {
-    const double s = wave_sum(lane > i ? x[i] * w : 0.0);
-    if (lane == i) w = (z - s) * invd[i];
-  }
-  return w;
-}
-
 __device__ inline double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
 
-// C = M^T M for a K x 64 operand M (rows of stride ld) on the matrix cores:
-// the 10 upper 16x16 tiles, accumulated in registers.
-template <typename T>
-__device__ inline void syrk_tiles(const T *M, int ld, int ksteps, typename Mfma<T>::V acc[10],
-                                  int lane) {
-  const int c16 = lane & 15, k4 = lane >> 4;
-  int t = 0;
-#pragma unroll
-  for (int I = 0; I < 4; ++I)
-#pragma unroll
-    for (int J = I; J < 4; ++J) acc[t++] = Mfma<T>::zero();
-  for (int kk = 0; kk < ksteps; ++kk) {
-    const T *row = M + (4 * kk + k4) * ld;
-    T a[4];
-#pragma unroll
-    for (int I = 0; I < 4; ++I) a[I] = row[16 * I + c16];
-    t = 0;
-#pragma unroll
-    for (int I = 0; I < 4; ++I)
-#pragma unroll
-      for (int J = I; J < 4; ++J) {
-        acc[t] = Mfma<T>::mac(a[I], a[J], acc[t]);
-        ++t;
-      }
-  }
+// LDS traffic of one wavefront only: in-order within the wave, so a compiler
+// barrier suffices between the writes and the reads of other lanes.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Write the symmetric 64x64 result of syrk_tiles (times alpha) row-major.
-template <typename T>
-__device__ inline void store_sym(const typename Mfma<T>::V acc[10], T *out, int ld, T alpha,
-                                 int lane) {
-  const int c16 = lane & 15;
-  int t = 0;
-#pragma unroll
-  for (int I = 0; I < 4; ++I)
-#pragma unroll
-    for (int J = I; J < 4; ++J) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * I + Mfma<T>::row(lane, r), j = 16 * J + c16;
-        const T v = alpha * acc[t][r];
-        out[i * ld + j] = v;
-        if (I != J) out[j * ld + i] = v;
-      }
-      ++t;
-    }
+// 1/x and 1/sqrt(x) from the hardware estimates refined by Newton steps.
+__device__ inline double rcp_nr(double x, int steps) {
+  double y = __builtin_amdgcn_rcp(x);
+  for (int i = 0; i < steps; ++i) y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+__device__ inline double rsq_nr(double x, int steps) {
+  double y = __builtin_amdgcn_rsq(x);
+  for (int i = 0; i < steps; ++i) y = y * fma(-0.5 * x * y, y, 1.5);
+  return y;
 }
 
-// Column sums of a 64 x 32 block held one row per lane (value k of lane i =
-// f(k) in lane i): returns the sum of column (lane & 31) in lanes k and k+32.
+// ------------------------------------------------------------ LDS scratch
+// Small FP64 scratch (offsets in doubles).
+constexpr int S_INVD = 0;      // 1 / L_kk
+constexpr int S_COL = 64;      // 2 x 64: Cholesky column broadcast
+constexpr int S_VEC = 192;     // 64: residual / z of the solves
+constexpr int S_WV = 256;      // 64: w
+constexpr int S_LAM = 320;     // 64: lambda^{-3/4}
+constexpr int S_NRM = 384;     // 4 waves x 16: column norms by register slot
+constexpr int S_XAM = 448;     // 64: analysis mean of the owned rows
+constexpr int S_ROT = 512;     // 4 waves x 8 pairs x (c, s, t gamma, pad)
+constexpr int S_MAX = 640;     // 4 waves (+ pad)
+constexpr int S_XN = 648;      // 4 waves x 16: norms in flight between waves
+constexpr int S_B = 712;       // 64: b = Y^T sqrt(g) d
+constexpr int S_TOTAL = 776;
+constexpr int kTbStride = 9;   // per-wave 64 x 9 transpose buffer for column sums
+constexpr int kTbWave = 64 * kTbStride;
+constexpr int kXchBytes = kWaves * 8 * 64 * 8;   // one block of every wave in flight
+
+// The 64 columns form 8 blocks of 8; wave q holds block q in X[0..7] and
+// block 7 - q in Y[0..7] (ascending columns), lane = row.
+__device__ inline int pos_x(int q, int j) { return 8 * q + j; }
+__device__ inline int pos_y(int q, int j) { return 56 - 8 * q + j; }
+__device__ inline int block_owner(int b) { return b < 4 ? b : 7 - b; }
+
+template <int CTRL> __device__ inline double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 8 lanes of each aligned group of 8 (quad swaps, then the two
+// quads of each half-row), result in all 8 lanes.
+__device__ inline double sum8_dpp(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  return v;
+}
+
+// Sums over the 64 rows (lanes) of 8 per-lane values f(j) of this wave:
+// returns the sum of value (lane >> 3) in the 8 lanes of each group.
 template <typename F>
-__device__ inline double colsum32(F f, double *tbuf, int lane) {
+__device__ inline double group_sums8(F f, double *tb, int r) {
 #pragma unroll
-  for (int k = 0; k < 32; ++k) tbuf[lane * 33 + k] = f(k);
-  __syncthreads();
-  const int col = lane & 31, r0 = (lane >> 5) * 32;
-  double s = 0.0;
-#pragma unroll 8
-  for (int r = 0; r < 32; ++r) s += tbuf[(r0 + r) * 33 + col];
-  __syncthreads();
-  return s + __shfl_xor(s, 32, 64);
+  for (int j = 0; j < 8; ++j) tb[r * kTbStride + j] = f(j);
+  wave_sync();
+  const int g = r >> 3, r0 = (r & 7) * 8;
+  const double a0 = tb[(r0 + 0) * kTbStride + g] + tb[(r0 + 1) * kTbStride + g];
+  const double a1 = tb[(r0 + 2) * kTbStride + g] + tb[(r0 + 3) * kTbStride + g];
+  const double a2 = tb[(r0 + 4) * kTbStride + g] + tb[(r0 + 5) * kTbStride + g];
+  const double a3 = tb[(r0 + 6) * kTbStride + g] + tb[(r0 + 7) * kTbStride + g];
+  const double s = sum8_dpp((a0 + a1) + (a2 + a3));
+  wave_sync();
+  return s;
 }
 
-// Column sums of a 64 x 64 block (value k of lane i = f(k)): lane j gets
-// the sum of column j.
+// Column sums of the distributed 64 x 64 block (f applied to each element)
+// written to out[column].
 template <typename F>
-__device__ inline double colsum64(F f, double *tbuf, int lane) {
-  const double a = colsum32([&](int k) { return f(k); }, tbuf, lane);
-  const double b = colsum32([&](int k) { return f(32 + k); }, tbuf, lane);
-  return lane < 32 ? a : b;
+__device__ inline void column_sums(const double X[8], const double Y[8], F f, double *tb,
+                                   double *out, int q, int r) {
+  const double a = group_sums8([&](int j) { return f(X[j]); }, tb, r);
+  if ((r & 7) == 0) out[pos_x(q, r >> 3)] = a;
+  const double b = group_sums8([&](int j) { return f(Y[j]); }, tb, r);
+  if ((r & 7) == 0) out[pos_y(q, r >> 3)] = b;
 }
 
-// Cholesky of the SPD matrix whose row `lane` is x[0..63] (in place: row i
-// of L, zero above the diagonal).  col: 64 doubles of LDS; invd (may be
-// NULL): 64 doubles of LDS that receive 1 / L_kk.
-__device__ inline void cholesky64(double x[64], double *col, double *invd, int lane) {
-#pragma unroll
+// Right-looking Cholesky of the distributed SPD matrix (in place: column k of
+// L in its slot, zero above the diagonal); 1/L_kk into sm[S_INVD].  The wave
+// holding column k publishes it (updated) in LDS before step k; at step k
+// every wave forms L's column k from it and updates its columns > k.  All
+// register choices are selects on wave-uniform conditions.
+__device__ inline void cholesky_dist(double X[8], double Y[8], double *sm, int q, int r) {
+  if (q == 0) sm[S_COL + r] = X[0];
   for (int k = 0; k < 64; ++k) {
-    const double akk = bcast_lane(x[k], k);
-    const double lkk = sqrt(akk);
-    if (invd && lane == 0) invd[k] = 1.0 / lkk;
-    const double l = lane > k ? x[k] / lkk : 0.0;
-    x[k] = lane > k ? l : (lane == k ? lkk : 0.0);
-    col[lane] = l;
     __syncthreads();
+    const double *raw = sm + S_COL + (k & 1) * 64;
+    double *nxt = sm + S_COL + ((k + 1) & 1) * 64;
+    const double lkk = sqrt(raw[k]);
+    const double il = 1.0 / lkk;
+    const double lr = r > k ? raw[r] * il : 0.0;
+    const double own = r > k ? lr : (r == k ? lkk : 0.0);
+    if (q == 0 && r == 0) sm[S_INVD + k] = il;
+    double pub = 0.0;
 #pragma unroll
-    for (int j = k + 1; j < 64; ++j) x[j] = fma(-l, col[j], x[j]);
+    for (int j = 0; j < 8; ++j) {
+      const int px = pos_x(q, j), py = pos_y(q, j);
+      const double fx = px > k ? raw[px] * il : 0.0;
+      const double fy = py > k ? raw[py] * il : 0.0;
+      X[j] = px == k ? own : fma(-lr, fx, X[j]);
+      Y[j] = py == k ? own : fma(-lr, fy, Y[j]);
+      pub = px == k + 1 ? X[j] : pub;
+      pub = py == k + 1 ? Y[j] : pub;
+    }
+    if (k + 1 < 64 && q == block_owner((k + 1) >> 3)) nxt[r] = pub;
+  }
+  __syncthreads();
+}
+
+// Forward substitution over one block of 8 columns (k0..k0+7 = cols[0..7]).
+__device__ inline void fwd_block(int k0, const double cols[8], double *sm, int r) {
+  double rv = sm[S_VEC + r];
+#pragma unroll
+  for (int jj = 0; jj < 8; ++jj) {
+    const int k = k0 + jj;
+    const double zk = bcast_lane(rv, k) * sm[S_INVD + k];
+    rv = r == k ? zk : (r > k ? fma(-cols[jj], zk, rv) : rv);
+  }
+  sm[S_VEC + r] = rv;
+}
+
+// Backward substitution over one block of 8 columns (descending).
+__device__ inline void bwd_block(int k0, const double cols[8], double *sm, int r) {
+  double wl = sm[S_WV + r];
+  const double z = sm[S_VEC + r];
+#pragma unroll
+  for (int jj = 7; jj >= 0; --jj) {
+    const int k = k0 + jj;
+    const double s = wave_sum(r > k ? cols[jj] * wl : 0.0);
+    const double wk = (bcast_lane(z, k) - s) * sm[S_INVD + k];
+    wl = r == k ? wk : wl;
+  }
+  sm[S_WV + r] = wl;
+}
+
+// Solve L L^T w = b (b in sm[S_VEC] on entry, w in sm[S_WV] on exit).
+__device__ inline void cholesky_solve_dist(const double X[8], const double Y[8], double *sm, int q,
+                                           int r) {
+  for (int kb = 0; kb < 8; ++kb) {
+    if (q == block_owner(kb)) {
+      if (kb < 4) fwd_block(8 * kb, X, sm, r);
+      else fwd_block(8 * kb, Y, sm, r);
+    }
+    __syncthreads();
+  }
+  if (q == 0) sm[S_WV + r] = 0.0;
+  __syncthreads();
+  for (int kb = 7; kb >= 0; --kb) {
+    if (q == block_owner(kb)) {
+      if (kb < 4) bwd_block(8 * kb, X, sm, r);
+      else bwd_block(8 * kb, Y, sm, r);
+    }
     __syncthreads();
   }
 }
 
-// One-sided Jacobi on the columns of x (row = lane) in the round-robin order:
-// positions (k, 63 - k), k < 32, are rotated together; then positions 1..63
-// shift by one (position 0 fixed), so 63 rounds visit every pair once and
-// return every column to its place.  Rotations zero the column inner product
-// (t = sign(z) / (|z| + sqrt(1 + z^2)), z = (|x_q|^2 - |x_p|^2) / (2 x_p.x_q)).
-// Stops after the first sweep whose largest |x_p.x_q| / (|x_p| |x_q|) <= tol.
-// Returns the number of sweeps, or -sweeps when it did not converge.
-__device__ inline int jacobi64(double x[64], double *tbuf, double *rot, double tol,
-                               int max_sweeps, int lane) {
-  double nrm = colsum64([&](int k) { return x[k] * x[k]; }, tbuf, lane);
+// Rotation of one pair: zero the inner product gam of columns with squared
+// norms alp, bet.  t = sign(z) / (|z| + sqrt(1 + z^2)), z = (bet - alp) /
+// (2 gam), taken in FP32 (it only steers convergence); c = (1 + t^2)^{-1/2}
+// in FP64, so (c, s = c t) is orthogonal to working precision.
+__device__ inline void rotation(double alp, double bet, double gam, double &cs, double &sn,
+                                double &tg, double &off) {
+  cs = 1.0;
+  sn = 0.0;
+  tg = 0.0;
+  off = 0.0;
+  if (gam != 0.0) {
+    off = fabs(gam) * rsq_nr(alp * bet, 1);
+    const float z = (float)(bet - alp) / (float)(2.0 * gam);
+    const float az = fabsf(z);
+    const float tf = copysignf(1.0f / (az + sqrtf(fmaf(az, az, 1.0f))), z);
+    const double t = (double)tf;
+    cs = rsq_nr(fma(t, t, 1.0), 2);
+    sn = cs * t;
+    tg = t * gam;
+  }
+}
+
+// One round of 8 pairs (A[j], B[j]) of this wave; norms of A at nA[j], of B
+// at nB[j] (LDS, this wave's slots).  x_p <- c x_p - s x_q, x_q <- s x_p + c x_q.
+template <typename PA, typename PB>
+__device__ inline void jacobi_round(PA pa, PB pb, int ia, int ib, double *nrm, double *rot,
+                                    double *tb, double &maxoff, int r) {
+  const int g = r >> 3;
+  const double gam = group_sums8([&](int j) { return pa(j) * pb(j); }, tb, r);
+  const double alp = nrm[ia], bet = nrm[ib];
+  double cs, sn, tg, off;
+  rotation(alp, bet, gam, cs, sn, tg, off);
+  maxoff = fmax(maxoff, off);
+  if ((r & 7) == 0) {
+    rot[4 * g] = cs;
+    rot[4 * g + 1] = sn;
+    nrm[ia] = alp - tg;
+    nrm[ib] = bet + tg;
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double c_ = rot[4 * j], s_ = rot[4 * j + 1];
+    const double xp = pa(j), xq = pb(j);
+    pa(j) = fma(c_, xp, -s_ * xq);
+    pb(j) = fma(s_, xp, c_ * xq);
+  }
+  wave_sync();
+}
+
+// Move the blocks to the next block-round of the 8-block round robin (block
+// slot 0 fixed, slots 1..7 rotate): X of wave q <- X of wave q-1 (wave 1:
+// Y of wave 0), Y of wave q <- Y of wave q+1 (wave 3: its own X); norms
+// travel with their blocks.
+__device__ inline void exchange_blocks(double X[8], double Y[8], double *sm, double *xch, int q,
+                                       int r) {
+  double *nrm = sm + S_NRM + q * 16;
+  __syncthreads();  // the exchange area overlaps the other waves' round buffers
+  // phase 1: every X, and the norms of both blocks
+#pragma unroll
+  for (int j = 0; j < 8; ++j) xch[(q * 8 + j) * 64 + r] = X[j];
+  if (r < 16) sm[S_XN + q * 16 + r] = nrm[r];
+  __syncthreads();
+  double oldX[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) oldX[j] = X[j];
+  if (q >= 2) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) X[j] = xch[((q - 1) * 8 + j) * 64 + r];
+  }
+  __syncthreads();
+  // phase 2: every Y
+#pragma unroll
+  for (int j = 0; j < 8; ++j) xch[(q * 8 + j) * 64 + r] = Y[j];
+  __syncthreads();
+  if (q == 1) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) X[j] = xch[(0 * 8 + j) * 64 + r];
+  }
+  if (q <= 2) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Y[j] = xch[((q + 1) * 8 + j) * 64 + r];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Y[j] = oldX[j];
+  }
+  // norms: X slots 0..7, Y slots 8..15
+  if (r < 8) {
+    const double *xn = sm + S_XN;
+    nrm[r] = q == 0 ? xn[r] : (q == 1 ? xn[0 * 16 + 8 + r] : xn[(q - 1) * 16 + r]);
+  } else if (r < 16) {
+    const double *xn = sm + S_XN;
+    nrm[r] = q <= 2 ? xn[(q + 1) * 16 + r] : xn[q * 16 + (r - 8)];
+  }
+  __syncthreads();
+}
+
+// Column at slot i of round t of the round robin on 8 (slot 0 fixed, slots
+// 1..7 rotate); round t pairs slots (u, 7 - u), u < 4.
+__host__ __device__ constexpr int intra_slot(int t, int i) {
+  return i == 0 ? 0 : ((i - 1 - t + 70) % 7) + 1;
+}
+
+// One-sided Jacobi on the distributed factor: per sweep, the 7 rounds of
+// pairs inside each block, then 7 block-rounds of 8 rounds pairing X[j] with
+// Y[(j + t) mod 8].  Stops after the first sweep whose largest
+// |x_p.x_q| / (|x_p| |x_q|) is <= tol; returns the sweeps used, negative when
+// max_sweeps was reached first.
+__device__ inline int jacobi_dist(double X[8], double Y[8], double *sm, double *tb, double *xch,
+                                  double tol, int max_sweeps, int q, int r) {
+  double *nrm = sm + S_NRM + q * 16;
+  double *rot = sm + S_ROT + q * 32;
   int sweep = 0;
   bool done = false;
   while (!done && sweep < max_sweeps) {
+    // Fresh squared norms each sweep: the running update alp - t gam is exact
+    // only for the exact angle, and its drift would steer the rotations of
+    // nearly equal columns (a degenerate cluster) instead of their inner
+    // products, stalling convergence.
+    {
+      const double a = group_sums8([&](int j) { return X[j] * X[j]; }, tb, r);
+      const double b = group_sums8([&](int j) { return Y[j] * Y[j]; }, tb, r);
+      if ((r & 7) == 0) {
+        nrm[r >> 3] = a;
+        nrm[8 + (r >> 3)] = b;
+      }
+      wave_sync();
+    }
     double maxoff = 0.0;
-    for (int round = 0; round < 63; ++round) {
-      const double gam = colsum32([&](int k) { return x[k] * x[63 - k]; }, tbuf, lane);
-      const double alp = nrm;
-      const double bet = __shfl(nrm, 63 - lane, 64);
-      double cs = 1.0, sn = 0.0, t = 0.0;
-      if (lane < 32 && gam != 0.0) {
-        maxoff = fmax(maxoff, fabs(gam) / sqrt(alp * bet));
-        const double zeta = (bet - alp) / (2.0 * gam);
-        t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        cs = 1.0 / sqrt(1.0 + t * t);
-        sn = cs * t;
-      }
-      if (lane < 32) {
-        rot[2 * lane] = cs;
-        rot[2 * lane + 1] = sn;
-      }
-      const double nal = alp - t * gam;
-      const double nbe = bet + t * gam;
-      const double nbe_mirror = __shfl(nbe, 63 - lane, 64);
-      const double nrm_new = lane < 32 ? nal : nbe_mirror;
-      __syncthreads();
+    const int g = r >> 3, gu = g & 3, gy = g < 4 ? 0 : 8;
 #pragma unroll
-      for (int k = 0; k < 32; ++k) {
-        const double c_ = rot[2 * k], s_ = rot[2 * k + 1];
-        const double xp = x[k], xq = x[63 - k];
-        x[k] = c_ * xp - s_ * xq;
-        x[63 - k] = s_ * xp + c_ * xq;
-      }
-      const double last = x[63];
+    for (int t = 0; t < 7; ++t) {
+      // groups 0..3: pairs inside X; groups 4..7: the same pairs inside Y
+      jacobi_round(
+          [&](int j) -> double & { return j < 4 ? X[intra_slot(t, j)] : Y[intra_slot(t, j - 4)]; },
+          [&](int j) -> double & {
+            return j < 4 ? X[intra_slot(t, 7 - j)] : Y[intra_slot(t, 7 - (j - 4))];
+          },
+          gy + intra_slot(t, gu), gy + intra_slot(t, 7 - gu), nrm, rot, tb, maxoff, r);
+    }
+    for (int br = 0; br < 7; ++br) {
 #pragma unroll
-      for (int j = 63; j >= 2; --j) x[j] = x[j - 1];
-      x[1] = last;
-      const int src = lane == 0 ? 0 : (lane == 1 ? 63 : lane - 1);
-      nrm = __shfl(nrm_new, src, 64);
-      __syncthreads();
+      for (int t = 0; t < 8; ++t)
+        jacobi_round([&](int j) -> double & { return X[j]; },
+                     [&](int j) -> double & { return Y[(j + t) & 7]; }, g, 8 + ((g + t) & 7), nrm, rot,
+                     tb, maxoff, r);
+      exchange_blocks(X, Y, sm, xch, q, r);
     }
     ++sweep;
-    done = wave_max(maxoff) <= tol;
+    const double wm = wave_max(maxoff);
+    if (r == 0) sm[S_MAX + q] = wm;
+    __syncthreads();
+    const double all = fmax(fmax(sm[S_MAX + 0], sm[S_MAX + 1]), fmax(sm[S_MAX + 2], sm[S_MAX + 3]));
+    done = all <= tol;
+    __syncthreads();
   }
   return done ? sweep : -sweep;
+}
+
+// Load the distributed matrix M (row-major, leading dimension ld) + c I.
+template <typename T>
+__device__ inline void load_dist(const T *M, int ld, double c, double X[8], double Y[8], int q, int r) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int px = pos_x(q, j), py = pos_y(q, j);
+    X[j] = (double)M[r * ld + px] + (r == px ? c : 0.0);
+    Y[j] = (double)M[r * ld + py] + (r == py ? c : 0.0);
+  }
+}
+
+// The 10 upper 16x16 tiles of a symmetric 64x64 product, dealt to the four
+// waves: wave q takes tiles t = q, q + 4, q + 8.
+__device__ inline void tile_of(int t, int &I, int &J) {
+  int a = 0, b = 0, n = 0;
+  for (int x = 0; x < 4; ++x)
+    for (int y = x; y < 4; ++y) {
+      if (n == t) {
+        a = x;
+        b = y;
+      }
+      ++n;
+    }
+  I = a;
+  J = b;
+}
+
+// C = M^T M (K x 64 operand M, rows of stride ld) on the matrix cores: this
+// wave's share of the upper tiles.
+template <typename T>
+__device__ inline void syrk_share(const T *M, int ld, int ksteps, typename Mfma<T>::V acc[3], int q,
+                                  int lane) {
+  const int c16 = lane & 15, k4 = lane >> 4;
+  int I[3], J[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    acc[u] = Mfma<T>::zero();
+    tile_of(q + 4 * u < 10 ? q + 4 * u : 0, I[u], J[u]);
+  }
+  const int nt = q < 2 ? 3 : 2;
+  for (int kk = 0; kk < ksteps; ++kk) {
+    const T *row = M + (4 * kk + k4) * ld;
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+      if (u < nt) acc[u] = Mfma<T>::mac(row[16 * I[u] + c16], row[16 * J[u] + c16], acc[u]);
+  }
+}
+
+template <typename T>
+__device__ inline void syrk_store(const typename Mfma<T>::V acc[3], T *out, int ld, T alpha, int q,
+                                  int lane) {
+  const int c16 = lane & 15;
+  const int nt = q < 2 ? 3 : 2;
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    if (u >= nt) continue;
+    int I, J;
+    tile_of(q + 4 * u, I, J);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + Mfma<T>::row(lane, r), j = 16 * J + c16;
+      const T v = alpha * acc[u][r];
+      out[i * ld + j] = v;
+      if (I != J) out[j * ld + i] = v;
+    }
+  }
 }
 
 template <typename T> struct AnaArgs {
@@ -323,9 +559,10 @@ __device__ inline int xcd_item(int b, int grid) {
 }
 
 template <typename T, bool FUSED>
-__global__ __launch_bounds__(64) void k_analysis(const AnaArgs<T> A) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_analysis(const AnaArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int q = tid >> 6, lane = tid & 63;
   int item = A.xcd_order ? xcd_item((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
   item += A.item_base;
   if (item >= A.n_items) return;
@@ -341,18 +578,18 @@ __global__ __launch_bounds__(64) void k_analysis(const AnaArgs<T> A) {
   double *dd = (double *)(smem + A.off_dd);
   T *yb = (T *)(smem + A.off_yb);
   int *pn = (int *)(smem + A.off_pn);
-  double *sm = (double *)(smem + A.off_s);  // 6 x 64 doubles of small scratch
+  double *sm = (double *)(smem + A.off_s);
   unsigned char *U = smem + A.off_u;
 
-  // ---- 1. node patch of X_b ----
-  const int my_node = lane < np ? A.patch_node[it.patch_off + lane] : 0;
-  pn[lane] = my_node;
+  // ---- 1. node patch of X_b (rows dealt to the four waves) ----
+  if (q == 0) pn[lane] = lane < np ? A.patch_node[it.patch_off + lane] : 0;
   BankDraw bd{};
   const bool use_bank = FUSED && A.noise_bank;
   if (use_bank && lane < m) bd = bank_draw(in, *A.frame, lane);
+  __syncthreads();
   const T a = (T)in.a;
-  for (int r = 0; r < np; ++r) {
-    const int g = __builtin_amdgcn_readlane(my_node, r);
+  for (int r = q; r < np; r += kWaves) {
+    const int g = pn[r];
     T v = (T)0;
     if (lane < m) {
       const int64_t e = in.x_off + (int64_t)g * m + lane;
@@ -373,134 +610,122 @@ __global__ __launch_bounds__(64) void k_analysis(const AnaArgs<T> A) {
     xs[r * kXsStride + lane] = v;
   }
   __syncthreads();
-  if (lane < np) {
+  if (tid < np) {
     T s = (T)0;
-    for (int j = 0; j < m; ++j) s += xs[lane * kXsStride + j];
-    xm[lane] = s / (T)m;
+    for (int j = 0; j < m; ++j) s += xs[tid * kXsStride + j];
+    xm[tid] = s / (T)m;
   }
   __syncthreads();
 
   // ---- 2. local slopes, weights and innovation ----
-  uint32_t my_corner = 0;
   int bad = 0;
-  if (lane < nobs) {
-    my_corner = A.obs_corner[it.obs_off + lane];
-    const int k = A.obs_sub[it.obs_off + lane];
-    const int ca = my_corner & 255, cb = (my_corner >> 8) & 255, cc = (my_corner >> 16) & 255,
-              cd = my_corner >> 24;
+  if (tid < nobs) {
+    const uint32_t cw = A.obs_corner[it.obs_off + tid];
+    const int k = A.obs_sub[it.obs_off + tid];
+    const int ca = cw & 255, cb = (cw >> 8) & 255, cc = (cw >> 16) & 255, cd = cw >> 24;
     const T ybx = (T)0.5 * ((xm[cb] - xm[ca]) + (xm[cd] - xm[cc]));
     const T yby = (T)0.5 * ((xm[cc] - xm[ca]) + (xm[cd] - xm[cb]));
-    const double f = in.taper_c > 0.0 ? gaspari_cohn(A.obs_dist[it.obs_off + lane] / in.taper_c) : 1.0;
+    const double f = in.taper_c > 0.0 ? gaspari_cohn(A.obs_dist[it.obs_off + tid] / in.taper_c) : 1.0;
     const double rx = A.r_diag[in.y_off + k], ry = A.r_diag[in.y_off + in.n_subaps + k];
     const double sgx = f / sqrt(in.r_scale * rx), sgy = f / sqrt(in.r_scale * ry);
     const double yx = (double)A.y[in.y_off + k], yy = (double)A.y[in.y_off + in.n_subaps + k];
     bad = !(isfinite(yx) && isfinite(yy));
-    sg[lane] = sgx;
-    sg[nobs + lane] = sgy;
-    dd[lane] = sgx * (yx - (double)ybx);
-    dd[nobs + lane] = sgy * (yy - (double)yby);
-    yb[lane] = ybx;
-    yb[nobs + lane] = yby;
+    sg[tid] = sgx;
+    sg[nobs + tid] = sgy;
+    dd[tid] = sgx * (yx - (double)ybx);
+    dd[nobs + tid] = sgy * (yy - (double)yby);
+    yb[tid] = ybx;
+    yb[nobs + tid] = yby;
   }
-  bad = __any(bad);
-  __syncthreads();
+  bad = __syncthreads_or(bad);
   T *ys = (T *)U;  // [p4][kYsStride], K-major MFMA operand
-  for (int q = 0; q < nobs; ++q) {
-    const uint32_t cw = (uint32_t)__builtin_amdgcn_readlane((int)my_corner, q);
+  for (int o = q; o < nobs; o += kWaves) {
+    const uint32_t cw = A.obs_corner[it.obs_off + o];
     const int ca = cw & 255, cb = (cw >> 8) & 255, cc = (cw >> 16) & 255, cd = cw >> 24;
     const T pa = xs[ca * kXsStride + lane], pb = xs[cb * kXsStride + lane];
     const T pc = xs[cc * kXsStride + lane], pd = xs[cd * kXsStride + lane];
-    const T sx = (T)0.5 * ((pb - pa) + (pd - pc)) - yb[q];
-    const T sy = (T)0.5 * ((pc - pa) + (pd - pb)) - yb[nobs + q];
-    ys[q * kYsStride + lane] = lane < m ? (T)sg[q] * sx : (T)0;
-    ys[(nobs + q) * kYsStride + lane] = lane < m ? (T)sg[nobs + q] * sy : (T)0;
+    const T sx = (T)0.5 * ((pb - pa) + (pd - pc)) - yb[o];
+    const T sy = (T)0.5 * ((pc - pa) + (pd - pb)) - yb[nobs + o];
+    ys[o * kYsStride + lane] = lane < m ? (T)sg[o] * sx : (T)0;
+    ys[(nobs + o) * kYsStride + lane] = lane < m ? (T)sg[nobs + o] * sy : (T)0;
   }
-  for (int q = p; q < p4; ++q) ys[q * kYsStride + lane] = (T)0;
+  for (int o = p + q; o < p4; o += kWaves) ys[o * kYsStride + lane] = (T)0;
   __syncthreads();
-  double bj = 0.0;  // b = Y^T sqrt(g) d, member = lane
-  for (int s = 0; s < p; ++s) bj = fma((double)ys[s * kYsStride + lane], dd[s], bj);
+  if (q == 0) {  // b = Y^T sqrt(g) d, member = lane
+    double bj = 0.0;
+    for (int s = 0; s < p; ++s) bj = fma((double)ys[s * kYsStride + lane], dd[s], bj);
+    sm[S_VEC + lane] = bj;
+  }
 
   // ---- 3. Gram on the matrix cores ----
-  typename Mfma<T>::V acc[10];
-  syrk_tiles<T>(ys, kYsStride, p4 / 4, acc, lane);
+  typename Mfma<T>::V acc[3];
+  syrk_share<T>(ys, kYsStride, p4 / 4, acc, q, lane);
   __syncthreads();
   T *gram = (T *)U;  // [64][kXsStride]
-  store_sym<T>(acc, gram, kXsStride, (T)1, lane);
+  syrk_store<T>(acc, gram, kXsStride, (T)1, q, lane);
   __syncthreads();
   const double c = (double)(m - 1) / in.rho;
-  double x[64];
-#pragma unroll
-  for (int k = 0; k < 64; ++k) x[k] = (double)gram[lane * kXsStride + k] + (k == lane ? c : 0.0);
+  double X[8], Y[8];
+  load_dist(gram, kXsStride, c, X, Y, q, lane);
   __syncthreads();
 
-  // ---- 4./5. FP64 Cholesky and one-sided Jacobi ----
-  double *tbuf = (double *)U;             // 64 x 33 doubles
-  double *rot = sm;                       // 64 doubles
-  double *col = sm + 64;                  // 64 doubles
-  double *invd = sm + 192;                // 1 / L_kk
-  cholesky64(x, col, invd, lane);
-  __syncthreads();
-  // w = A~^{-1} b from the factor itself, independent of the Jacobi stop
-  const double wbar = cholesky_solve64(x, invd, bj, lane);
-  const int sweeps = jacobi64(x, tbuf, rot, A.jtol, A.max_sweeps, lane);
+  // ---- 4./5. FP64 Cholesky, w, one-sided Jacobi ----
+  cholesky_dist(X, Y, sm, q, lane);
+  cholesky_solve_dist(X, Y, sm, q, lane);
+  double *tb = (double *)U + q * kTbWave;
+  const int sweeps = jacobi_dist(X, Y, sm, tb, (double *)U, A.jtol, A.max_sweeps, q, lane);
   const bool conv = sweeps > 0;
 
-  // ---- 6. transform: lambda, W = sqrt(c) U Lambda^{-3/2} U^T, w ----
-  const double lam = colsum64([&](int k) { return x[k] * x[k]; }, tbuf, lane);  // lane j: eigenvalue j
-  double *lamv = sm + 128;                      // lambda^{-3/4}
-  double *wv = sm + 256;                        // w
-  double *xa_mean = sm + 320;                   // analysis mean of the owned rows
-  lamv[lane] = 1.0 / sqrt(lam * sqrt(lam));
+  // ---- 6. lambda and W = sqrt(c) (U Lambda^{-3/4}) (U Lambda^{-3/4})^T ----
+  column_sums(X, Y, [](double v) { return v * v; }, tb, sm + S_LAM, q, lane);
   __syncthreads();
-  T *ut = (T *)U;     // [64][kYsStride]: (U Lambda^{-3/4})^T, K-major (tbuf is dead)
+  const double lam_l = sm[S_LAM + lane];
+  const bool lam_ok = __syncthreads_and(isfinite(lam_l) && lam_l > 0.0);
+  if (q == 0) sm[S_LAM + lane] = 1.0 / sqrt(lam_l * sqrt(lam_l));
+  __syncthreads();
+  T *ut = (T *)U;  // [64][kYsStride]: (U Lambda^{-3/4})^T, K-major
 #pragma unroll
-  for (int k = 0; k < 64; ++k) ut[k * kYsStride + lane] = (T)(x[k] * lamv[k]);
-  wv[lane] = wbar;
+  for (int j = 0; j < 8; ++j) {
+    const int px = pos_x(q, j), py = pos_y(q, j);
+    ut[px * kYsStride + lane] = (T)(X[j] * sm[S_LAM + px]);
+    ut[py * kYsStride + lane] = (T)(Y[j] * sm[S_LAM + py]);
+  }
   __syncthreads();
-  syrk_tiles<T>(ut, kYsStride, 16, acc, lane);
+  syrk_share<T>(ut, kYsStride, 16, acc, q, lane);
   __syncthreads();
-  T *wmat = ut;      // W row-major [64][kYsStride]
-  store_sym<T>(acc, wmat, kYsStride, (T)sqrt(c), lane);
+  T *wmat = ut;  // W row-major [64][kYsStride]
+  syrk_store<T>(acc, wmat, kYsStride, (T)sqrt(c), q, lane);
   __syncthreads();
 
   // ---- 7. owned rows: X_a = (x_b + X' w) 1^T + sqrt(rho) X' W ----
-  const bool keep_forecast = bad || !conv || !isfinite(lam);
-  if (lane == 0) A.flags[item] = (bad || !isfinite(lam) ? 1 : 0) | (conv ? 0 : 2);
-  if (lane < nown) {
-    double s = (double)xm[lane];
-    const double mu = (double)xm[lane];
-    for (int k = 0; k < m; ++k) s = fma((double)xs[lane * kXsStride + k] - mu, wv[k], s);
-    xa_mean[lane] = s;
+  const bool keep_forecast = bad || !conv || !lam_ok;
+  if (tid == 0) A.flags[item] = (bad || !lam_ok ? 1 : 0) | (conv ? 0 : 2);
+  if (tid < nown) {
+    const double mu = (double)xm[tid];
+    double s = mu;
+    for (int k = 0; k < m; ++k) s = fma((double)xs[tid * kXsStride + k] - mu, sm[S_WV + k], s);
+    sm[S_XAM + tid] = s;
   }
   __syncthreads();
   const T srho = (T)sqrt(in.rho);
   const int c16 = lane & 15, k4 = lane >> 4;
+  const int J = q;  // this wave's 16 members
   for (int I = 0; I * 16 < nown; ++I) {
-    typename Mfma<T>::V o[4];
-#pragma unroll
-    for (int J = 0; J < 4; ++J) o[J] = Mfma<T>::zero();
+    typename Mfma<T>::V o = Mfma<T>::zero();
     const int ia = 16 * I + c16;
     const T mu = ia < nown ? xm[ia] : (T)0;
     for (int kk = 0; kk < 16; ++kk) {
       const int k = 4 * kk + k4;
       const T av = (ia < nown && k < m) ? xs[ia * kXsStride + k] - mu : (T)0;
-#pragma unroll
-      for (int J = 0; J < 4; ++J) o[J] = Mfma<T>::mac(av, wmat[k * kYsStride + 16 * J + c16], o[J]);
+      o = Mfma<T>::mac(av, wmat[k * kYsStride + 16 * J + c16], o);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * I + Mfma<T>::row(lane, r);
-      if (i < nown) {
-        const int g = pn[i];
-        const T base = (T)xa_mean[i];
-#pragma unroll
-        for (int J = 0; J < 4; ++J) {
-          const int j = 16 * J + c16;
-          if (j < m) {
-            const T v = keep_forecast ? xs[i * kXsStride + j] : base + srho * o[J][r];
-            A.x_out[in.x_off + (int64_t)g * m + j] = v;
-          }
-        }
+      const int j = 16 * J + c16;
+      if (i < nown && j < m) {
+        const T v = keep_forecast ? xs[i * kXsStride + j] : (T)sm[S_XAM + i] + srho * o[r];
+        A.x_out[in.x_off + (int64_t)pn[i] * m + j] = v;
       }
     }
   }
@@ -559,35 +784,39 @@ __global__ void k_mean(const InstDesc *insts, const T *x, T *mean) {
   }
 }
 
-// Stand-alone SPD eigensolve, one wavefront per matrix.
-__global__ __launch_bounds__(64) void k_eigh_spd(const double *Am, int m, double tol, int max_sweeps,
-                                                 double *Q, double *lam_out, int32_t *sweeps_out) {
-  __shared__ double tbuf[64 * 33 + 128];
-  const int lane = threadIdx.x;
+// Stand-alone SPD eigensolve with the same distributed Cholesky + Jacobi,
+// one workgroup per matrix.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_eigh_spd(const double *Am, int m, double tol,
+                                                       int max_sweeps, double *Q, double *lam_out,
+                                                       int32_t *sweeps_out) {
+  __shared__ double smem_s[S_TOTAL];
+  __shared__ double tb_s[kWaves * kTbWave > kXchBytes / 8 ? kWaves * kTbWave : kXchBytes / 8];
+  const int tid = threadIdx.x, q = tid >> 6, r = tid & 63;
   const double *Ab = Am + (int64_t)blockIdx.x * m * m;
-  double x[64];
+  double X[8], Y[8];
 #pragma unroll
-  for (int k = 0; k < 64; ++k) {
-    double v;
-    if (lane < m && k < m) v = Ab[lane * m + k];
-    else v = (k == lane) ? 1.0 : 0.0;
-    x[k] = v;
+  for (int j = 0; j < 8; ++j) {
+    const int px = pos_x(q, j), py = pos_y(q, j);
+    X[j] = (r < m && px < m) ? Ab[r * m + px] : (r == px ? 1.0 : 0.0);
+    Y[j] = (r < m && py < m) ? Ab[r * m + py] : (r == py ? 1.0 : 0.0);
   }
-  double *rot = tbuf + 64 * 33;
-  double *col = rot + 64;
-  cholesky64(x, col, nullptr, lane);
-  const int sw = jacobi64(x, tbuf, rot, tol, max_sweeps, lane);
-  const double lam = colsum64([&](int k) { return x[k] * x[k]; }, tbuf, lane);
-  col[lane] = 1.0 / sqrt(lam);
+  double *sm = smem_s;
+  double *tb = tb_s + q * kTbWave;
+  cholesky_dist(X, Y, sm, q, r);
+  const int sw = jacobi_dist(X, Y, sm, tb, tb_s, tol, max_sweeps, q, r);
+  column_sums(X, Y, [](double v) { return v * v; }, tb, sm + S_LAM, q, r);
   __syncthreads();
-  if (lane < m) {
+  if (r < m) {
     double *Qb = Q + (int64_t)blockIdx.x * m * m;
 #pragma unroll
-    for (int k = 0; k < 64; ++k)
-      if (k < m) Qb[lane * m + k] = x[k] * col[k];
-    lam_out[(int64_t)blockIdx.x * m + lane] = lam;
+    for (int j = 0; j < 8; ++j) {
+      const int px = pos_x(q, j), py = pos_y(q, j);
+      if (px < m) Qb[r * m + px] = X[j] / sqrt(sm[S_LAM + px]);
+      if (py < m) Qb[r * m + py] = Y[j] / sqrt(sm[S_LAM + py]);
+    }
+    if (q == 0) lam_out[(int64_t)blockIdx.x * m + r] = sm[S_LAM + r];
   }
-  if (lane == 0 && sweeps_out) sweeps_out[blockIdx.x] = sw;
+  if (tid == 0 && sweeps_out) sweeps_out[blockIdx.x] = sw;
 }
 
 }  // namespace letkf
@@ -600,9 +829,9 @@ extern "C" hipError_t letkf_launch_analysis_f32(const void *args, int fused, int
                                                 size_t lds, hipStream_t s) {
   const AnaArgs<float> &A = *(const AnaArgs<float> *)args;
   if (fused)
-    hipLaunchKernelGGL((k_analysis<float, true>), dim3(grid), dim3(64), lds, s, A);
+    hipLaunchKernelGGL((k_analysis<float, true>), dim3(grid), dim3(kThreads), lds, s, A);
   else
-    hipLaunchKernelGGL((k_analysis<float, false>), dim3(grid), dim3(64), lds, s, A);
+    hipLaunchKernelGGL((k_analysis<float, false>), dim3(grid), dim3(kThreads), lds, s, A);
   return hipGetLastError();
 }
 
@@ -610,15 +839,23 @@ extern "C" hipError_t letkf_launch_analysis_f64(const void *args, int fused, int
                                                 size_t lds, hipStream_t s) {
   const AnaArgs<double> &A = *(const AnaArgs<double> *)args;
   if (fused)
-    hipLaunchKernelGGL((k_analysis<double, true>), dim3(grid), dim3(64), lds, s, A);
+    hipLaunchKernelGGL((k_analysis<double, true>), dim3(grid), dim3(kThreads), lds, s, A);
   else
-    hipLaunchKernelGGL((k_analysis<double, false>), dim3(grid), dim3(64), lds, s, A);
+    hipLaunchKernelGGL((k_analysis<double, false>), dim3(grid), dim3(kThreads), lds, s, A);
   return hipGetLastError();
 }
 
 extern "C" const void *letkf_analysis_kernel(int fp64, int fused) {
   if (fp64) return fused ? (const void *)k_analysis<double, true> : (const void *)k_analysis<double, false>;
   return fused ? (const void *)k_analysis<float, true> : (const void *)k_analysis<float, false>;
+}
+
+extern "C" int letkf_analysis_threads(void) { return kThreads; }
+
+extern "C" size_t letkf_analysis_scratch_doubles(void) { return S_TOTAL; }
+
+extern "C" size_t letkf_analysis_tb_bytes(void) {
+  return (size_t)kWaves * kTbWave * 8 > (size_t)kXchBytes ? (size_t)kWaves * kTbWave * 8 : (size_t)kXchBytes;
 }
 
 extern "C" hipError_t letkf_launch_forecast(int fp64, const InstDesc *insts, int n_inst,
@@ -673,7 +910,8 @@ extern "C" hipError_t letkf_launch_mean(int fp64, const InstDesc *insts, int n_i
 
 extern "C" hipError_t letkf_launch_eigh(const double *A, int m, int batch, double tol, int max_sweeps,
                                         double *Q, double *lam, int32_t *sweeps, hipStream_t s) {
-  hipLaunchKernelGGL(k_eigh_spd, dim3(batch), dim3(64), 0, s, A, m, tol, max_sweeps, Q, lam, sweeps);
+  hipLaunchKernelGGL(k_eigh_spd, dim3(batch), dim3(kThreads), 0, s, A, m, tol, max_sweeps, Q, lam,
+                     sweeps);
   return hipGetLastError();
 }
 
