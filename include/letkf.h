@@ -204,6 +204,43 @@ int letkf_eigh_spd(const double *A_dev, int32_t m, int32_t batch, double tol,
                    int32_t max_sweeps, double *Q_dev, double *lam_dev, int32_t *sweeps_dev,
                    void *stream);
 
+/* ---------------------------------------------------------------- adjoint
+ * Gradient of a loss of the analysis ensembles with respect to each
+ * instance's (rho, r_scale, taper_c): the inflation, the noise scale s of
+ * Sigma_w = s diag(r) (Sec. 3.1.1) and the Gaspari-Cohn half width of the
+ * localisation taper (Sec. 4.1).  The loss provided here is the residual-phase
+ * variance of the analysis mean behind the coherent energy of Sec. 5:
+ *   var_i = mean over nodes of (e - mean(e))^2,  e = X_a 1 / m - phi,
+ * phi the true phase at the nodes ([node] per instance, instances
+ * concatenated, element type of the handle).  A caller runs the frames
+ * forward, keeps the analysis ensembles it needs (or checkpoints and
+ * recomputes them), then walks back one frame at a time.  All pointers are
+ * device pointers; all calls are asynchronous on `stream`. */
+
+/* acc_dev[i] += weights_dev[i] * var_i for the analysis ensemble xa_dev
+ * (NULL: the handle's current one); weights_dev NULL = 1 for every
+ * instance.  acc_dev: n_instances doubles. */
+int letkf_residual_variance(letkf_handle *h, const void *xa_dev, const void *truth_dev,
+                            const double *weights_dev, double *acc_dev, void *stream);
+
+/* xbar_dev += weights_dev[i] * d var_i / d X_a (ensemble layout). */
+int letkf_residual_variance_adjoint(letkf_handle *h, const void *xa_dev, const void *truth_dev,
+                                    const double *weights_dev, void *xbar_dev, void *stream);
+
+/* Reverse of the frame that turned xa_prev_dev into the analysis ensemble
+ * whose adjoint is in xbar_dev: the forecast a X_prev + V (V_dev, or the
+ * instance's noise bank drawn at frame number `frame` when V_dev is NULL) and
+ * the analysis with the slopes y_dev are recomputed, then
+ *   xbar_dev      <- adjoint of xa_prev_dev (overwritten in place),
+ *   theta_bar_dev[3 i + {0, 1, 2}] += d loss / d (rho, r_scale, taper_c) of
+ *                    instance i through this frame.
+ * Deterministic: slope adjoints of overlapping observation regions are summed
+ * in a fixed order.  A domain whose analysis kept its forecast (non-finite
+ * input or no convergence) is differentiated as the identity.  Returns
+ * LETKF_E_INVAL when the device cannot give the adjoint kernel its LDS. */
+int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, uint32_t frame,
+                  const void *y_dev, void *xbar_dev, double *theta_bar_dev, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

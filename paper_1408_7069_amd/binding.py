@@ -96,6 +96,9 @@ _SIGS = {
     "letkf_get_schedule": (C.c_int, [_P, _I32P, _I32P]),
     "letkf_autotune": (C.c_int, [_P, _P, _P, C.c_int32, C.c_char_p, _P]),
     "letkf_eigh_spd": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double, C.c_int32, _P, _P, _P, _P]),
+    "letkf_residual_variance": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "letkf_residual_variance_adjoint": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "letkf_adjoint": (C.c_int, [_P, _P, _P, C.c_uint32, _P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -338,6 +341,45 @@ class Letkf:
                                   cache_path.encode() if cache_path else None, _stream(stream)),
                "letkf_autotune")
         return self.get_schedule()
+
+    # -- loss and adjoint
+    def _check_f64(self, t, n, name):
+        import torch
+        if t is None:
+            return
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < n:
+            raise ValueError(f"{name}: need a contiguous float64 device tensor of >= {n} elements")
+
+    def residual_variance(self, truth, acc, xa=None, weights=None, stream=None):
+        """acc[i] += weights[i] * residual variance of instance i's analysis mean."""
+        n = self.sizes["n_instances"]
+        self._check_tensor(truth, self.sizes["n_nodes"], "truth")
+        self._check_tensor(xa, self.sizes["ensemble_elems"], "xa")
+        self._check_f64(acc, n, "acc")
+        self._check_f64(weights, n, "weights")
+        _check(lib.letkf_residual_variance(self._h, _ptr(xa), _ptr(truth), _ptr(weights), _ptr(acc),
+                                           _stream(stream)), "letkf_residual_variance")
+
+    def residual_variance_adjoint(self, truth, xbar, xa=None, weights=None, stream=None):
+        """xbar += weights[i] * d(residual variance of instance i) / d X_a."""
+        self._check_tensor(truth, self.sizes["n_nodes"], "truth")
+        self._check_tensor(xa, self.sizes["ensemble_elems"], "xa")
+        self._check_tensor(xbar, self.sizes["ensemble_elems"], "xbar")
+        self._check_f64(weights, self.sizes["n_instances"], "weights")
+        _check(lib.letkf_residual_variance_adjoint(self._h, _ptr(xa), _ptr(truth), _ptr(weights),
+                                                   _ptr(xbar), _stream(stream)),
+               "letkf_residual_variance_adjoint")
+
+    def adjoint(self, xa_prev, y, xbar, theta_bar, frame: int, V=None, stream=None):
+        """Reverse of one frame (letkf_adjoint): xbar becomes the adjoint of
+        xa_prev and theta_bar[3 i:3 i + 3] gains d/d(rho, r_scale, taper_c)."""
+        self._check_tensor(xa_prev, self.sizes["ensemble_elems"], "xa_prev")
+        self._check_tensor(y, self.sizes["n_slopes"], "y")
+        self._check_tensor(xbar, self.sizes["ensemble_elems"], "xbar")
+        self._check_tensor(V, self.sizes["ensemble_elems"], "V")
+        self._check_f64(theta_bar, 3 * self.sizes["n_instances"], "theta_bar")
+        _check(lib.letkf_adjoint(self._h, _ptr(xa_prev), _ptr(V), frame, _ptr(y), _ptr(xbar),
+                                 _ptr(theta_bar), _stream(stream)), "letkf_adjoint")
 
 
 def eigh_spd(A, tol: float = 1e-12, max_sweeps: int = 30, stream=None):

@@ -52,6 +52,26 @@ extern "C" size_t letkf_args_size(int fp64);
 extern "C" int letkf_analysis_threads(void);
 extern "C" size_t letkf_analysis_scratch_doubles(void);
 extern "C" size_t letkf_analysis_tb_bytes(void);
+extern "C" const void *letkf_adjoint_kernel(int fp64);
+extern "C" size_t letkf_adjoint_scratch_doubles(void);
+extern "C" size_t letkf_adjoint_args_size(int fp64);
+extern "C" hipError_t letkf_launch_adjoint(int fp64, const void *args, int grid, size_t lds,
+                                           hipStream_t s);
+extern "C" hipError_t letkf_launch_adjoint_nodes(int fp64, const InstDesc *insts, int n_inst,
+                                                 const int32_t *node_adj, const int32_t *slot_off,
+                                                 const int32_t *slots, const void *xpbar,
+                                                 const double *xbbar, const void *ybar,
+                                                 const double *dbar, void *xbar_out, int max_nodes,
+                                                 hipStream_t s);
+extern "C" hipError_t letkf_launch_resvar(int fp64, const InstDesc *insts, int n_inst, const void *x,
+                                          const void *truth, const double *weights, double *stats,
+                                          double *acc, hipStream_t s);
+extern "C" hipError_t letkf_launch_resvar_adjoint(int fp64, const InstDesc *insts, int n_inst,
+                                                  const void *x, const void *truth,
+                                                  const double *weights, const double *stats,
+                                                  void *xbar, int max_nodes, hipStream_t s);
+extern "C" hipError_t letkf_launch_theta_sum(const int32_t *dom_base, int n_inst, const double *theta,
+                                             double *theta_acc, hipStream_t s);
 
 namespace {
 
@@ -90,6 +110,19 @@ template <typename T> struct AnaArgsHost {
   double jtol;
   int32_t max_sweeps;
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u;
+};
+
+// Mirror of AdjArgs<T>.
+template <typename T> struct AdjArgsHost {
+  AnaArgsHost<T> F;
+  const T *xbar;
+  T *xpbar;
+  double *xbbar;
+  T *ybar;
+  double *dbar;
+  double *theta;
+  uint32_t frame;
+  int32_t off_q, off_wb, off_sa;
 };
 
 struct InstGeom {
@@ -148,6 +181,15 @@ struct letkf_handle {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipGraphNode_t gnode[2] = {nullptr, nullptr};
   std::vector<unsigned char> gargs[2];
+  // adjoint: node -> subaperture roles, per-subaperture slot lists, item
+  // ranges per instance, LDS layout, and buffers allocated on first use
+  size_t adj_lds = 0;
+  int32_t adj_off[3] = {0, 0, 0};
+  bool adj_ok = false;
+  int32_t *d_node_adj = nullptr, *d_slot_off = nullptr, *d_slots = nullptr, *d_dom_base = nullptr;
+  double *d_ones = nullptr, *d_stats = nullptr;
+  void *d_xpbar = nullptr, *d_ybar = nullptr;
+  double *d_xbbar = nullptr, *d_dbar = nullptr, *d_theta = nullptr;
 };
 
 namespace {
@@ -318,7 +360,9 @@ void free_handle(letkf_handle *h) {
   }
   void *ptrs[] = {h->d_desc, h->d_items, h->d_patch, h->d_obs_sub, h->d_node_ij, h->d_subap_nodes,
                   h->d_obs_corner, h->d_obs_dist, h->d_bank, h->d_r, h->d_xa[0], h->d_xa[1],
-                  h->d_xb, h->d_tmp, h->d_frame, h->d_flags};
+                  h->d_xb, h->d_tmp, h->d_frame, h->d_flags, h->d_node_adj, h->d_slot_off,
+                  h->d_slots, h->d_dom_base, h->d_ones, h->d_stats, h->d_xpbar, h->d_ybar,
+                  h->d_xbbar, h->d_dbar, h->d_theta};
   for (void *p : ptrs)
     if (p) hipFree(p);
   delete h;
@@ -569,6 +613,55 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   size_t u = std::max({p4 * kYsStride * T, (size_t)64 * kXsStride * T, letkf_analysis_tb_bytes(),
                        (size_t)64 * kYsStride * T});
   h->lds = align16(o + u);
+  {  // the adjoint kernel: a larger U area (FP64 64 x 64), Q, a second matrix, scratch
+    size_t oa = align16(o + std::max(u, (size_t)64 * 65 * 8));
+    h->adj_off[0] = (int32_t)oa; oa = align16(oa + (size_t)64 * 65 * 8);
+    h->adj_off[1] = (int32_t)oa; oa = align16(oa + (size_t)64 * 65 * 8);
+    h->adj_off[2] = (int32_t)oa; oa = align16(oa + letkf_adjoint_scratch_doubles() * 8);
+    h->adj_lds = oa;
+  }
+  // adjoint maps: node -> (subaperture for corner roles a, b, c, d), the slots
+  // (item, local slope) of each subaperture in item order, item ranges
+  std::vector<int32_t> node_adj, slot_off, slots, dom_base(h->dom_base);
+  dom_base.push_back((int32_t)h->items.size());
+  {
+    const int64_t total_sub = h->total_y / 2;
+    std::vector<std::vector<int32_t>> lists((size_t)total_sub);
+    int64_t sb = 0;
+    std::vector<int64_t> sub_base;
+    for (int i = 0; i < n_instances; ++i) {
+      sub_base.push_back(sb);
+      const InstGeom &g = h->geom[i];
+      const int N = g.N;
+      std::vector<int32_t> sid((size_t)N * N, -1);
+      for (int q = 0; q < g.n_subaps; ++q) sid[g.subaps[2 * q] * N + g.subaps[2 * q + 1]] = q;
+      for (int n = 0; n < g.n_nodes; ++n) {
+        const int ni = g.node_ij[2 * n], nj = g.node_ij[2 * n + 1];
+        const int si[4] = {ni, ni, ni - 1, ni - 1}, sj[4] = {nj, nj - 1, nj, nj - 1};
+        for (int r = 0; r < 4; ++r) {
+          int v = -1;
+          if (si[r] >= 0 && si[r] < N && sj[r] >= 0 && sj[r] < N && sid[si[r] * N + sj[r]] >= 0)
+            v = (int32_t)(sb + sid[si[r] * N + sj[r]]);
+          node_adj.push_back(v);
+        }
+      }
+      sb += g.n_subaps;
+    }
+    // pairs (x slot, n_obs): the y slope of a slot sits n_obs slots later
+    for (const DomItem &it : h->items) {
+      const InstGeom &g = h->geom[it.inst];
+      for (int o = 0; o < it.n_obs; ++o) {
+        auto &l = lists[(size_t)(sub_base[it.inst] + g.obs_sub[it.dom][o])];
+        l.push_back(2 * it.obs_off + o);
+        l.push_back(it.n_obs);
+      }
+    }
+    slot_off.push_back(0);
+    for (int64_t k = 0; k < total_sub; ++k) {
+      slots.insert(slots.end(), lists[(size_t)k].begin(), lists[(size_t)k].end());
+      slot_off.push_back((int32_t)(slots.size() / 2));
+    }
+  }
 
   int rc = LETKF_OK;
   hipError_t e = hipSetDevice(device);
@@ -579,12 +672,25 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   for (int fused = 0; fused < 2; ++fused)
     hipFuncSetAttribute(letkf_analysis_kernel(h->fp64, fused),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
+  {
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+        h->adj_lds <= (size_t)max_lds) {
+      h->adj_ok = hipFuncSetAttribute(letkf_adjoint_kernel(h->fp64),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)h->adj_lds) == hipSuccess;
+    }
+  }
   (void)hipGetLastError();
   if ((rc = to_device(&h->d_desc, h->desc)) || (rc = to_device(&h->d_items, h->items)) ||
       (rc = to_device(&h->d_patch, patch)) || (rc = to_device(&h->d_obs_sub, obs_sub)) ||
       (rc = to_device(&h->d_obs_corner, obs_corner)) || (rc = to_device(&h->d_obs_dist, obs_dist)) ||
       (rc = to_device(&h->d_node_ij, node_ij)) || (rc = to_device(&h->d_subap_nodes, subap_nodes)) ||
-      (rc = to_device(&h->d_r, r)) || (rc = to_device(&h->d_bank, bank))) {
+      (rc = to_device(&h->d_r, r)) || (rc = to_device(&h->d_bank, bank)) ||
+      (rc = to_device(&h->d_node_adj, node_adj)) || (rc = to_device(&h->d_slot_off, slot_off)) ||
+      (rc = to_device(&h->d_slots, slots)) || (rc = to_device(&h->d_dom_base, dom_base)) ||
+      (rc = to_device(&h->d_ones, std::vector<double>((size_t)n_instances, 1.0))) ||
+      (rc = to_device(&h->d_stats, std::vector<double>(2 * (size_t)n_instances, 0.0)))) {
     free_handle(h);
     return rc;
   }
@@ -947,6 +1053,101 @@ int letkf_eigh_spd(const double *A_dev, int32_t m, int32_t batch, double tol, in
   if (batch == 0) return LETKF_OK;
   HIPCHK(letkf_launch_eigh(A_dev, m, batch, tol > 0 ? tol : 1e-12, max_sweeps > 0 ? max_sweeps : 30,
                            Q_dev, lam_dev, sweeps_dev, (hipStream_t)stream));
+  return LETKF_OK;
+}
+
+
+// ------------------------------------------------------------------ adjoint
+extern "C++" {
+static int ensure_adjoint(letkf_handle *h) {
+  if (!h->adj_ok)
+    return fail(LETKF_E_INVAL, "the adjoint needs " + std::to_string(h->adj_lds) +
+                                   " bytes of LDS per workgroup, more than the device allows");
+  if (h->d_theta) return LETKF_OK;
+  const size_t T = h->esize;
+  const size_t items = std::max<size_t>(h->items.size(), 1);
+  if (hipMalloc(&h->d_xpbar, std::max<size_t>((size_t)h->total_x * T, 16)) != hipSuccess ||
+      hipMalloc((void **)&h->d_xbbar, std::max<size_t>((size_t)h->total_nodes * 8, 16)) != hipSuccess ||
+      hipMalloc(&h->d_ybar, std::max<size_t>((size_t)h->total_obs * kLanes * T, 16)) != hipSuccess ||
+      hipMalloc((void **)&h->d_dbar, std::max<size_t>((size_t)h->total_obs * 8, 16)) != hipSuccess ||
+      hipMalloc((void **)&h->d_theta, items * 4 * 8) != hipSuccess)
+    return fail(LETKF_E_NOMEM, "hipMalloc of the adjoint buffers failed");
+  return LETKF_OK;
+}
+}  // extern "C++"
+
+int letkf_residual_variance(letkf_handle *h, const void *xa_dev, const void *truth_dev,
+                            const double *weights_dev, double *acc_dev, void *stream) {
+  if (!h || !truth_dev || !acc_dev) return fail(LETKF_E_INVAL, "NULL argument");
+  hipSetDevice(h->device);
+  const void *x = xa_dev ? xa_dev : h->d_xa[h->cur];
+  HIPCHK(letkf_launch_resvar(h->fp64, h->d_desc, h->n_inst, x, truth_dev,
+                             weights_dev ? weights_dev : h->d_ones, h->d_stats, acc_dev,
+                             (hipStream_t)stream));
+  return LETKF_OK;
+}
+
+int letkf_residual_variance_adjoint(letkf_handle *h, const void *xa_dev, const void *truth_dev,
+                                    const double *weights_dev, void *xbar_dev, void *stream) {
+  if (!h || !truth_dev || !xbar_dev) return fail(LETKF_E_INVAL, "NULL argument");
+  hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const void *x = xa_dev ? xa_dev : h->d_xa[h->cur];
+  const double *w = weights_dev ? weights_dev : h->d_ones;
+  HIPCHK(letkf_launch_resvar(h->fp64, h->d_desc, h->n_inst, x, truth_dev, w, h->d_stats, nullptr, s));
+  HIPCHK(letkf_launch_resvar_adjoint(h->fp64, h->d_desc, h->n_inst, x, truth_dev, w, h->d_stats,
+                                     xbar_dev, h->max_nodes, s));
+  return LETKF_OK;
+}
+
+extern "C++" {
+template <typename T>
+static AdjArgsHost<T> make_adj_args(letkf_handle *h, const void *xa_prev, const void *V,
+                                    uint32_t frame, const void *y, void *xbar) {
+  AdjArgsHost<T> D;
+  std::memset(&D, 0, sizeof(D));
+  D.F = make_args<T>(h, true, V, y, 0, 0);
+  D.F.x_in = (const T *)xa_prev;
+  D.F.x_out = nullptr;
+  D.F.xcd_order = 0;
+  D.F.frame = nullptr;
+  D.xbar = (const T *)xbar;
+  D.xpbar = (T *)h->d_xpbar;
+  D.xbbar = h->d_xbbar;
+  D.ybar = (T *)h->d_ybar;
+  D.dbar = h->d_dbar;
+  D.theta = h->d_theta;
+  D.frame = frame;
+  D.off_q = h->adj_off[0];
+  D.off_wb = h->adj_off[1];
+  D.off_sa = h->adj_off[2];
+  return D;
+}
+}  // extern "C++"
+
+int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, uint32_t frame,
+                  const void *y_dev, void *xbar_dev, double *theta_bar_dev, void *stream) {
+  if (!h || !xa_prev_dev || !y_dev || !xbar_dev || !theta_bar_dev)
+    return fail(LETKF_E_INVAL, "NULL argument");
+  int rc = check_noise(h, V_dev);
+  if (rc) return rc;
+  hipSetDevice(h->device);
+  if ((rc = ensure_adjoint(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int grid = (int)h->items.size();
+  if (h->fp64) {
+    auto D = make_adj_args<double>(h, xa_prev_dev, V_dev, frame, y_dev, xbar_dev);
+    if (sizeof(D) != letkf_adjoint_args_size(1)) return fail(LETKF_E_DEVICE, "argument layout mismatch");
+    HIPCHK(letkf_launch_adjoint(1, &D, grid, h->adj_lds, s));
+  } else {
+    auto D = make_adj_args<float>(h, xa_prev_dev, V_dev, frame, y_dev, xbar_dev);
+    if (sizeof(D) != letkf_adjoint_args_size(0)) return fail(LETKF_E_DEVICE, "argument layout mismatch");
+    HIPCHK(letkf_launch_adjoint(0, &D, grid, h->adj_lds, s));
+  }
+  HIPCHK(letkf_launch_adjoint_nodes(h->fp64, h->d_desc, h->n_inst, h->d_node_adj, h->d_slot_off,
+                                    h->d_slots, h->d_xpbar, h->d_xbbar, h->d_ybar, h->d_dbar,
+                                    xbar_dev, h->max_nodes, s));
+  HIPCHK(letkf_launch_theta_sum(h->d_dom_base, h->n_inst, h->d_theta, theta_bar_dev, s));
   return LETKF_OK;
 }
 

@@ -19,12 +19,18 @@
 //      written straight into the global analysis ensemble (the gather).
 //
 // Layout of the 64 x 64 FP64 factor during stages 4-6: lane = row; the 64
-// columns sit on 64 "positions" of a round-robin tournament, wave q holding
-// positions 8q..8q+7 (lo[j]) and 63-8q-j (hi[j]), so pair k = (k, 63-k) is
-// (lo[j], hi[j]) of one wave.  After each round every position p >= 1 hands
-// its column to p+1 (63 -> 1, 0 fixed): two columns per wave cross to the
-// neighbouring wave through LDS, 63 rounds visit every pair once and bring
-// every column home.
+// columns form 8 blocks of 8, wave q holding block q and block 7 - q in
+// registers.  A Jacobi sweep pairs the columns inside each held block (7
+// rounds of a round robin on 8), then runs 7 block-rounds of 8 rounds that
+// pair every column of one held block with every column of the other, moving
+// the blocks between waves through LDS after each block-round (block slot 0
+// fixed, slots 1..7 rotating): every pair of columns meets once per sweep and
+// only the block moves need a workgroup barrier.
+//
+// k_adjoint recomputes stages 1-6 with the same code and then runs the reverse
+// of stage 7 and of the transform (see the comment above it); k_adjoint_nodes
+// sums the per-domain slope adjoints per slope, applies D^T and hands the
+// adjoint of the previous analysis ensemble back.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -169,7 +175,8 @@ constexpr int S_ROT = 512;     // 4 waves x 8 pairs x (c, s, t gamma, pad)
 constexpr int S_MAX = 640;     // 4 waves (+ pad)
 constexpr int S_XN = 648;      // 4 waves x 16: norms in flight between waves
 constexpr int S_B = 712;       // 64: b = Y^T sqrt(g) d
-constexpr int S_TOTAL = 776;
+constexpr int S_LAMV = 776;    // 64: lambda
+constexpr int S_TOTAL = 840;
 constexpr int kTbStride = 9;   // per-wave 64 x 9 transpose buffer for column sums
 constexpr int kTbWave = 64 * kTbStride;
 constexpr int kXchBytes = kWaves * 8 * 64 * 8;   // one block of every wave in flight
@@ -558,16 +565,22 @@ __device__ inline int xcd_item(int b, int grid) {
   return (b & 7) * per + (b >> 3);
 }
 
+// Stages 1-6 of one work item, shared by the analysis and its adjoint.  On
+// return: the forecast patch in xs (rows = patch nodes, lane = member) with its
+// member means in xm, the scaled innovation in dd, the slope means in yb, the
+// weights sqrt(g) in sg, w in sm[S_WV], lambda in sm[S_LAMV], the factor
+// U = L J of the Jacobi (lane = row) in X / Y, and W (row-major, stride
+// kYsStride) at the start of the U area.
+struct CoreStatus {
+  bool bad, conv, lam_ok;
+};
+
 template <typename T, bool FUSED>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_analysis(const AnaArgs<T> A) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ CoreStatus analysis_core(const AnaArgs<T> &A, const DomItem &it,
+                                                     const InstDesc &in, uint32_t frame,
+                                                     unsigned char *smem, double X[8], double Y[8]) {
   const int tid = threadIdx.x;
   const int q = tid >> 6, lane = tid & 63;
-  int item = A.xcd_order ? xcd_item((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
-  item += A.item_base;
-  if (item >= A.n_items) return;
-  const DomItem it = A.items[item];
-  const InstDesc in = A.inst[it.inst];
   const int m = in.m;
   const int np = it.n_patch, nown = it.n_own, nobs = it.n_obs;
   const int p = 2 * nobs, p4 = (p + 3) & ~3;
@@ -585,7 +598,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   if (q == 0) pn[lane] = lane < np ? A.patch_node[it.patch_off + lane] : 0;
   BankDraw bd{};
   const bool use_bank = FUSED && A.noise_bank;
-  if (use_bank && lane < m) bd = bank_draw(in, *A.frame, lane);
+  if (use_bank && lane < m) bd = bank_draw(in, frame, lane);
   __syncthreads();
   const T a = (T)in.a;
   for (int r = q; r < np; r += kWaves) {
@@ -665,7 +678,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   syrk_store<T>(acc, gram, kXsStride, (T)1, q, lane);
   __syncthreads();
   const double c = (double)(m - 1) / in.rho;
-  double X[8], Y[8];
   load_dist(gram, kXsStride, c, X, Y, q, lane);
   __syncthreads();
 
@@ -681,7 +693,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   __syncthreads();
   const double lam_l = sm[S_LAM + lane];
   const bool lam_ok = __syncthreads_and(isfinite(lam_l) && lam_l > 0.0);
-  if (q == 0) sm[S_LAM + lane] = 1.0 / sqrt(lam_l * sqrt(lam_l));
+  if (q == 0) {
+    sm[S_LAM + lane] = 1.0 / sqrt(lam_l * sqrt(lam_l));
+    sm[S_LAMV + lane] = lam_l;
+  }
   __syncthreads();
   T *ut = (T *)U;  // [64][kYsStride]: (U Lambda^{-3/4})^T, K-major
 #pragma unroll
@@ -696,6 +711,30 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   T *wmat = ut;  // W row-major [64][kYsStride]
   syrk_store<T>(acc, wmat, kYsStride, (T)sqrt(c), q, lane);
   __syncthreads();
+  return CoreStatus{bad != 0, conv, lam_ok};
+}
+
+template <typename T, bool FUSED>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_analysis(const AnaArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+  const int q = tid >> 6, lane = tid & 63;
+  int item = A.xcd_order ? xcd_item((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  item += A.item_base;
+  if (item >= A.n_items) return;
+  const DomItem it = A.items[item];
+  const InstDesc in = A.inst[it.inst];
+  const int m = in.m;
+  const int nown = it.n_own;
+  T *xs = (T *)(smem + A.off_xs);
+  T *xm = (T *)(smem + A.off_xm);
+  int *pn = (int *)(smem + A.off_pn);
+  double *sm = (double *)(smem + A.off_s);
+  T *wmat = (T *)(smem + A.off_u);
+  double X[8], Y[8];
+  const uint32_t frame = (FUSED && A.noise_bank) ? *A.frame : 0u;
+  const CoreStatus st = analysis_core<T, FUSED>(A, it, in, frame, smem, X, Y);
+  const bool bad = st.bad, conv = st.conv, lam_ok = st.lam_ok;
 
   // ---- 7. owned rows: X_a = (x_b + X' w) 1^T + sqrt(rho) X' W ----
   const bool keep_forecast = bad || !conv || !lam_ok;
@@ -729,6 +768,460 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       }
     }
   }
+}
+
+// ------------------------------------------------------------------ adjoint
+// Reverse of one frame for the gradient of a loss of the analysis ensembles
+// with respect to (rho, s, c): inflation, noise scale and taper width (Sec.
+// 3.1.1 transform, Sec. 4.1 localisation, Sec. 4.2 local analyses).  Per work
+// item the forward stages are recomputed by the same code, then
+//   owned rows:  xa_bar = Xa_bar 1,  X'_bar = sqrt(rho) Xa_bar W + xa_bar w^T,
+//                W_bar = sqrt(rho) X'^T Xa_bar,  w_bar = X'^T xa_bar;
+//   w = A~^{-1} b:  b_bar = Q Lambda^{-1} Q^T w_bar,  A_bar = -b_bar w^T;
+//   W = sqrt(k) A~^{-1/2}:  A_bar += sqrt(k) Q (F o (Q^T sym(W_bar) Q)) Q^T with
+//                F_ij = -1 / (s_i s_j (s_i + s_j)), s = sqrt(lambda), the
+//                divided differences of l^{-1/2} (its derivative on the
+//                diagonal and inside degenerate clusters);
+//   A~ = k I + Yt^T Yt, b = Yt^T dt:  S = sym(A_bar),
+//                Yt_bar = 2 Yt S + dt b_bar^T,  dt_bar = Yt b_bar;
+// and the slope-space adjoints sqrt(g) Yt_bar, sqrt(g) dt_bar go to one slot
+// per (item, local slope), summed per slope by the node pass that follows.
+
+constexpr int kQStride = 65;   // FP64 64 x 64 matrices in LDS (row stride)
+// adjoint scratch (doubles)
+constexpr int A_XAB = 0;       // 64: xa_bar of the owned rows
+constexpr int A_WBB = 64;      // 64: w_bar
+constexpr int A_TV = 128;      // 64: Lambda^{-1} Q^T w_bar
+constexpr int A_BB = 192;      // 64: b_bar
+constexpr int A_KAP = 256;     // 128: (df/dc) / sqrt(s r) per local slope
+constexpr int A_DIN = 384;     // 128: unscaled innovation per local slope
+constexpr int A_RED = 512;     // 4 waves x 8 partial sums
+constexpr int A_TOTAL = 544;
+
+// d GC / d z of the Gaspari-Cohn function above (its piecewise derivative).
+__device__ inline double gaspari_cohn_dz(double z) {
+  z = fabs(z);
+  if (z >= 2.0) return 0.0;
+  if (z <= 1.0) return (((-1.25 * z + 2.0) * z + 1.875) * z - 10.0 / 3.0) * z;
+  return (((5.0 / 12.0 * z - 2.0) * z + 1.875) * z + 10.0 / 3.0) * z - 5.0 + 2.0 / (3.0 * z * z);
+}
+
+// One 16 x 16 output tile (I, J) of a 64 x 64 x 64 FP64 product on the matrix
+// cores; a(i, k), b(k, j) load the operands.
+template <typename FA, typename FB>
+__device__ inline f64x4 mm64_tile(FA a, FB b, int I, int J, int lane) {
+  const int c16 = lane & 15, k4 = lane >> 4;
+  f64x4 acc = Mfma<double>::zero();
+#pragma unroll 4
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = 4 * kk + k4;
+    acc = Mfma<double>::mac(a(16 * I + c16, k), b(k, 16 * J + c16), acc);
+  }
+  return acc;
+}
+
+template <typename T> struct AdjArgs {
+  AnaArgs<T> F;
+  const T *xbar;     // adjoint of this frame's analysis ensemble [node][m]
+  T *xpbar;          // out: adjoint of X' on the owned rows [node][m]
+  double *xbbar;     // out: adjoint of x_b on the owned nodes [node]
+  T *ybar;           // out: adjoint of Y' per (item, local slope) slot, [slot][64]
+  double *dbar;      // out: adjoint of d per slot
+  double *theta;     // out: (rho, s, c) adjoint per item, [item][4]
+  uint32_t frame;    // frame number of the bank draws
+  int32_t off_q, off_wb, off_sa;
+};
+
+__device__ inline double block_sum4(double v, double *red, int slot, int q, int lane) {
+  v = wave_sum(v);
+  if (lane == 0) red[q * 8 + slot] = v;
+  return v;
+}
+
+template <typename T, bool FUSED>
+__global__ __launch_bounds__(kThreads) void k_adjoint(const AdjArgs<T> D) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const AnaArgs<T> &A = D.F;
+  const int tid = threadIdx.x;
+  const int q = tid >> 6, lane = tid & 63;
+  const int c16 = lane & 15, k4 = lane >> 4;
+  const int item = A.item_base + (int)blockIdx.x;
+  if (item >= A.n_items) return;
+  const DomItem it = A.items[item];
+  const InstDesc in = A.inst[it.inst];
+  const int m = in.m, nown = it.n_own, nobs = it.n_obs, p = 2 * nobs;
+  T *xs = (T *)(smem + A.off_xs);
+  T *xm = (T *)(smem + A.off_xm);
+  double *sg = (double *)(smem + A.off_sg);
+  double *dd = (double *)(smem + A.off_dd);
+  T *yb = (T *)(smem + A.off_yb);
+  int *pn = (int *)(smem + A.off_pn);
+  double *sm = (double *)(smem + A.off_s);
+  unsigned char *U = smem + A.off_u;
+  double *Ub = (double *)U;
+  double *Qs = (double *)(smem + D.off_q);
+  double *Wb = (double *)(smem + D.off_wb);
+  double *sa = (double *)(smem + D.off_sa);
+  const int64_t slot0 = 2 * (int64_t)it.obs_off;
+
+  double X[8], Y[8];
+  const CoreStatus st = analysis_core<T, FUSED>(A, it, in, D.frame, smem, X, Y);
+
+  if (st.bad || !st.conv || !st.lam_ok) {
+    // the forward kept the forecast on the owned rows: X_a = X' + x_b 1^T
+    for (int i = q; i < nown; i += kWaves) {
+      const int64_t e = in.x_off + (int64_t)pn[i] * m + lane;
+      const double v = lane < m ? (double)D.xbar[e] : 0.0;
+      if (lane < m) D.xpbar[e] = (T)v;
+      const double s = wave_sum(v);
+      if (lane == 0) D.xbbar[in.node_off + pn[i]] = s;
+    }
+    for (int e = tid; e < p * kLanes; e += kThreads) D.ybar[slot0 * kLanes + e] = (T)0;
+    if (tid < p) D.dbar[slot0 + tid] = 0.0;
+    if (tid < 4) D.theta[(int64_t)item * 4 + tid] = 0.0;
+    return;
+  }
+  const double kc = (double)(m - 1) / in.rho;
+
+  // ---- A1. Q = U Lambda^{-1/2} into LDS ----
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int px = pos_x(q, j), py = pos_y(q, j);
+    Qs[lane * kQStride + px] = X[j] / sqrt(sm[S_LAMV + px]);
+    Qs[lane * kQStride + py] = Y[j] / sqrt(sm[S_LAMV + py]);
+  }
+  // ---- A2. adjoint of the owned rows (in the Wb area until the DK stage) ----
+  double *xab = Wb;
+  for (int i = q; i < nown; i += kWaves)
+    xab[i * kQStride + lane] = lane < m ? (double)D.xbar[in.x_off + (int64_t)pn[i] * m + lane] : 0.0;
+  __syncthreads();
+  if (tid < nown) {
+    double s = 0.0;
+    for (int j = 0; j < m; ++j) s += xab[tid * kQStride + j];
+    sa[A_XAB + tid] = s;
+  }
+  __syncthreads();
+
+  // ---- A3. X' W and Xa_bar W on the owned rows (matrix cores, T) ----
+  const T *wmat = (const T *)U;
+  const double srho = sqrt(in.rho);
+  double rho1 = 0.0;
+  for (int I = 0; I * 16 < nown; ++I) {
+    typename Mfma<T>::V oP = Mfma<T>::zero(), oR = Mfma<T>::zero();
+    const int ia = 16 * I + c16;
+    const T mu = ia < nown ? xm[ia] : (T)0;
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 4 * kk + k4;
+      const bool ok = ia < nown && k < m;
+      const T av = ok ? xs[ia * kXsStride + k] - mu : (T)0;
+      const T rv = ok ? (T)xab[ia * kQStride + k] : (T)0;
+      const T bv = wmat[k * kYsStride + 16 * q + c16];
+      oP = Mfma<T>::mac(av, bv, oP);
+      oR = Mfma<T>::mac(rv, bv, oR);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + Mfma<T>::row(lane, r), j = 16 * q + c16;
+      if (i < nown && j < m) {
+        rho1 += xab[i * kQStride + j] * (double)oP[r];
+        const double v = srho * (double)oR[r] + sa[A_XAB + i] * sm[S_WV + j];
+        D.xpbar[in.x_off + (int64_t)pn[i] * m + j] = (T)v;
+      }
+    }
+  }
+  if (tid < nown) D.xbbar[in.node_off + pn[tid]] = sa[A_XAB + tid];
+
+  // ---- A4. W_bar = sqrt(rho) X'^T Xa_bar (FP64 matrix cores), w_bar ----
+  f64x4 wbt[4];
+  double kb1 = 0.0;
+  {
+    const int i = 16 * q + c16;  // row of W_bar = member of X'
+#pragma unroll
+    for (int J = 0; J < 4; ++J) {
+      f64x4 acc = Mfma<double>::zero();
+      for (int kk = 0; 4 * kk < nown; ++kk) {
+        const int k = 4 * kk + k4;
+        const bool ok = k < nown;
+        const double av = (ok && i < m) ? (double)(xs[k * kXsStride + i] - xm[k]) : 0.0;
+        const double bv = ok ? xab[k * kQStride + 16 * J + c16] : 0.0;
+        acc = Mfma<double>::mac(av, bv, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        acc[r] *= srho;
+        const int ii = 16 * q + Mfma<double>::row(lane, r), jj = 16 * J + c16;
+        kb1 += acc[r] * (double)wmat[ii * kYsStride + jj];
+      }
+      wbt[J] = acc;
+    }
+  }
+  if (q == 0) {
+    double s = 0.0;
+    if (lane < m)
+      for (int k = 0; k < nown; ++k) s += (double)(xs[k * kXsStride + lane] - xm[k]) * sa[A_XAB + k];
+    sa[A_WBB + lane] = s;
+  }
+  __syncthreads();  // W (in U) and Xa_bar (in Wb) are no longer read
+#pragma unroll
+  for (int J = 0; J < 4; ++J)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      Ub[(16 * q + Mfma<double>::row(lane, r)) * kQStride + 16 * J + c16] = wbt[J][r];
+  // ---- A5. b_bar = Q Lambda^{-1} Q^T w_bar ----
+  if (q == 0) {
+    double t = 0.0;
+    for (int r = 0; r < 64; ++r) t = fma(Qs[r * kQStride + lane], sa[A_WBB + r], t);
+    sa[A_TV + lane] = t / sm[S_LAMV + lane];
+  }
+  __syncthreads();
+  if (q == 0) {
+    double bb = 0.0;
+    for (int c = 0; c < 64; ++c) bb = fma(Qs[lane * kQStride + c], sa[A_TV + c], bb);
+    sa[A_BB + lane] = bb;
+  }
+
+  // ---- A6. A_bar of the transform through the eigenpairs (Daleckii-Krein) ----
+  f64x4 t4[4];
+#pragma unroll
+  for (int J = 0; J < 4; ++J)  // P1 = sym(W_bar) Q
+    t4[J] = mm64_tile([&](int i, int k) { return 0.5 * (Ub[i * kQStride + k] + Ub[k * kQStride + i]); },
+                      [&](int k, int j) { return Qs[k * kQStride + j]; }, q, J, lane);
+#pragma unroll
+  for (int J = 0; J < 4; ++J)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Wb[(16 * q + Mfma<double>::row(lane, r)) * kQStride + 16 * J + c16] = t4[J][r];
+  __syncthreads();
+  const double skc = sqrt(kc);
+#pragma unroll
+  for (int J = 0; J < 4; ++J) {  // M = F o (Q^T P1), times sqrt(k)
+    t4[J] = mm64_tile([&](int i, int k) { return Qs[k * kQStride + i]; },
+                      [&](int k, int j) { return Wb[k * kQStride + j]; }, q, J, lane);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * q + Mfma<double>::row(lane, r), j = 16 * J + c16;
+      const double si = sqrt(sm[S_LAMV + i]), sj = sqrt(sm[S_LAMV + j]);
+      t4[J][r] *= -skc / (si * sj * (si + sj));
+    }
+  }
+#pragma unroll
+  for (int J = 0; J < 4; ++J)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ub[(16 * q + Mfma<double>::row(lane, r)) * kQStride + 16 * J + c16] = t4[J][r];
+  __syncthreads();
+#pragma unroll
+  for (int J = 0; J < 4; ++J)  // P2 = Q M
+    t4[J] = mm64_tile([&](int i, int k) { return Qs[i * kQStride + k]; },
+                      [&](int k, int j) { return Ub[k * kQStride + j]; }, q, J, lane);
+#pragma unroll
+  for (int J = 0; J < 4; ++J)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Wb[(16 * q + Mfma<double>::row(lane, r)) * kQStride + 16 * J + c16] = t4[J][r];
+  __syncthreads();
+#pragma unroll
+  for (int J = 0; J < 4; ++J)  // P2 Q^T
+    t4[J] = mm64_tile([&](int i, int k) { return Wb[i * kQStride + k]; },
+                      [&](int k, int j) { return Qs[j * kQStride + k]; }, q, J, lane);
+#pragma unroll
+  for (int J = 0; J < 4; ++J)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ub[(16 * q + Mfma<double>::row(lane, r)) * kQStride + 16 * J + c16] = t4[J][r];
+  __syncthreads();
+  // S = sym(A_bar) into Wb
+  double tr = 0.0;
+  for (int e = tid; e < 64 * 64; e += kThreads) {
+    const int i = e >> 6, j = e & 63;
+    const double v = 0.5 * (Ub[i * kQStride + j] + Ub[j * kQStride + i]) -
+                     0.5 * (sa[A_BB + i] * sm[S_WV + j] + sm[S_WV + i] * sa[A_BB + j]);
+    Wb[i * kQStride + j] = v;
+    if (i == j) tr += v;
+  }
+  __syncthreads();
+
+  // ---- A7. unscaled local slope anomalies (U), taper derivative, innovation ----
+  T *yu = (T *)U;
+  for (int o = q; o < nobs; o += kWaves) {
+    const uint32_t cw = A.obs_corner[it.obs_off + o];
+    const int ca = cw & 255, cb = (cw >> 8) & 255, cc = (cw >> 16) & 255, cd = cw >> 24;
+    const T pa = xs[ca * kXsStride + lane], pb = xs[cb * kXsStride + lane];
+    const T pc = xs[cc * kXsStride + lane], pd = xs[cd * kXsStride + lane];
+    const T sx = (T)0.5 * ((pb - pa) + (pd - pc)) - yb[o];
+    const T sy = (T)0.5 * ((pc - pa) + (pd - pb)) - yb[nobs + o];
+    yu[o * kYsStride + lane] = lane < m ? sx : (T)0;
+    yu[(nobs + o) * kYsStride + lane] = lane < m ? sy : (T)0;
+  }
+  if (tid < nobs) {
+    const int k = A.obs_sub[it.obs_off + tid];
+    const double rx = A.r_diag[in.y_off + k], ry = A.r_diag[in.y_off + in.n_subaps + k];
+    double dfdc = 0.0;
+    if (in.taper_c > 0.0) {
+      const double dist = A.obs_dist[it.obs_off + tid];
+      const double z = dist / in.taper_c;
+      dfdc = -gaspari_cohn_dz(z) * z / in.taper_c;
+    }
+    sa[A_KAP + tid] = dfdc / sqrt(in.r_scale * rx);
+    sa[A_KAP + nobs + tid] = dfdc / sqrt(in.r_scale * ry);
+    sa[A_DIN + tid] = (double)A.y[in.y_off + k] - (double)yb[tid];
+    sa[A_DIN + nobs + tid] = (double)A.y[in.y_off + in.n_subaps + k] - (double)yb[nobs + tid];
+  }
+  __syncthreads();
+
+  // ---- A8. Yt_bar = 2 Yt S + dt b_bar^T (FP64 matrix cores), slots ----
+  double sacc = 0.0, cacc = 0.0;
+  for (int I = 0; 16 * I < p; ++I) {
+    f64x4 acc = Mfma<double>::zero();
+    const int ia = 16 * I + c16;
+    const double sgi = ia < p ? sg[ia] : 0.0;
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 4 * kk + k4;
+      const double av = ia < p ? sgi * (double)yu[ia * kYsStride + k] : 0.0;
+      acc = Mfma<double>::mac(av, Wb[k * kQStride + 16 * q + c16], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + Mfma<double>::row(lane, r), j = 16 * q + c16;
+      if (i < p) {
+        double out = 0.0;
+        if (j < m) {
+          const double yij = (double)yu[i * kYsStride + j];
+          const double ytb = 2.0 * acc[r] + dd[i] * sa[A_BB + j];
+          sacc += ytb * sg[i] * yij;
+          cacc += ytb * yij * sa[A_KAP + i];
+          out = sg[i] * ytb;
+        }
+        D.ybar[(slot0 + i) * kLanes + j] = (T)out;
+      }
+    }
+  }
+  // ---- A9. dt_bar = Yt b_bar ----
+  if (tid < p) {
+    double t = 0.0;
+    for (int j = 0; j < m; ++j) t = fma((double)yu[tid * kYsStride + j], sa[A_BB + j], t);
+    const double dtb = sg[tid] * t;
+    sacc += dtb * dd[tid];
+    cacc += dtb * sa[A_DIN + tid] * sa[A_KAP + tid];
+    D.dbar[slot0 + tid] = sg[tid] * dtb;
+  }
+  // ---- A10. (rho, s, c) adjoints of this item ----
+  double *red = sa + A_RED;
+  block_sum4(rho1, red, 0, q, lane);
+  block_sum4(kb1, red, 1, q, lane);
+  block_sum4(tr, red, 2, q, lane);
+  block_sum4(sacc, red, 3, q, lane);
+  block_sum4(cacc, red, 4, q, lane);
+  __syncthreads();
+  if (tid == 0) {
+    double v[5];
+    for (int s = 0; s < 5; ++s) v[s] = (red[s] + red[8 + s]) + (red[16 + s] + red[24 + s]);
+    const double kbar = v[1] / (2.0 * kc) + v[2];
+    double *th = D.theta + (int64_t)item * 4;
+    th[0] = v[0] / (2.0 * srho) - kbar * (double)(m - 1) / (in.rho * in.rho);
+    th[1] = -v[3] / (2.0 * in.r_scale);
+    th[2] = v[4];
+    th[3] = 0.0;
+  }
+}
+
+// Node pass of the frame adjoint (blockIdx.y = instance, one wavefront per
+// node, lane = member): the per-slot slope adjoints summed per slope and sent
+// through D^T (each node is corner a, b, c or d of up to four subapertures),
+// then the anomaly and mean adjoints combined into X_b's and scaled by the AR
+// coefficient: the adjoint of the previous analysis ensemble.
+template <typename T>
+__global__ void k_adjoint_nodes(const InstDesc *insts, const int32_t *node_adj,
+                                const int32_t *slot_off, const int32_t *slots, const T *xpbar,
+                                const double *xbbar, const T *ybar, const double *dbar, T *xbar_out) {
+  const InstDesc in = insts[blockIdx.y];
+  const int g = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= in.n_nodes) return;
+  const int m = in.m;
+  const int64_t gn = in.node_off + g;
+  const int64_t e = in.x_off + (int64_t)g * m + lane;
+  double acc = lane < m ? (double)xpbar[e] : 0.0;
+  double xb = xbbar[gn];
+  for (int role = 0; role < 4; ++role) {
+    const int sidx = node_adj[4 * gn + role];
+    if (sidx < 0) continue;
+    const double cx = (role & 1) ? 0.5 : -0.5;
+    const double cy = (role & 2) ? 0.5 : -0.5;
+    for (int t = slot_off[sidx]; t < slot_off[sidx + 1]; ++t) {
+      const int64_t sx = slots[2 * t], sy = sx + slots[2 * t + 1];
+      if (lane < m) acc += cx * (double)ybar[sx * kLanes + lane] + cy * (double)ybar[sy * kLanes + lane];
+      xb -= cx * dbar[sx] + cy * dbar[sy];
+    }
+  }
+  const double mean = wave_sum(acc) / (double)m;
+  if (lane < m) xbar_out[e] = (T)(in.a * (acc - mean + xb / (double)m));
+}
+
+// Sum over the threads of a 256-thread block (result in every thread).
+__device__ inline double block_sum(double v, double *red) {
+  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[q] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Residual variance of the analysis mean against the true phase, one block per
+// instance: stats[2 i] = mean error, stats[2 i + 1] = variance; acc[i] +=
+// weights[i] * variance when acc is given.
+template <typename T>
+__global__ __launch_bounds__(256) void k_resvar(const InstDesc *insts, const T *x, const T *truth,
+                                               const double *weights, double *stats, double *acc) {
+  __shared__ double red[4];
+  const InstDesc in = insts[blockIdx.x];
+  const int n = in.n_nodes, m = in.m;
+  double s1 = 0.0;
+  for (int g = threadIdx.x; g < n; g += 256) {
+    double s = 0.0;
+    for (int j = 0; j < m; ++j) s += (double)x[in.x_off + (int64_t)g * m + j];
+    s1 += s / (double)m - (double)truth[in.node_off + g];
+  }
+  const double ebar = block_sum(s1, red) / (double)n;
+  double s2 = 0.0;
+  for (int g = threadIdx.x; g < n; g += 256) {
+    double s = 0.0;
+    for (int j = 0; j < m; ++j) s += (double)x[in.x_off + (int64_t)g * m + j];
+    const double e = s / (double)m - (double)truth[in.node_off + g] - ebar;
+    s2 += e * e;
+  }
+  const double var = block_sum(s2, red) / (double)n;
+  if (threadIdx.x == 0) {
+    stats[2 * blockIdx.x] = ebar;
+    stats[2 * blockIdx.x + 1] = var;
+    if (acc) acc[blockIdx.x] += weights[blockIdx.x] * var;
+  }
+}
+
+// xbar += weights[i] d var / d X_a (blockIdx.y = instance, a wavefront per node).
+template <typename T>
+__global__ void k_resvar_adjoint(const InstDesc *insts, const T *x, const T *truth,
+                                 const double *weights, const double *stats, T *xbar) {
+  const InstDesc in = insts[blockIdx.y];
+  const int g = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= in.n_nodes) return;
+  const int m = in.m;
+  const int64_t e = in.x_off + (int64_t)g * m + lane;
+  const double v = lane < m ? (double)x[e] : 0.0;
+  const double err = wave_sum(v) / (double)m - (double)truth[in.node_off + g] - stats[2 * blockIdx.y];
+  const double coef = weights[blockIdx.y] * 2.0 * err / ((double)in.n_nodes * (double)m);
+  if (lane < m) xbar[e] = (T)((double)xbar[e] + coef);
+}
+
+// theta_acc[3 i + t] += sum over the items of instance i of theta[4 item + t],
+// in item order.
+__global__ void k_theta_sum(const int32_t *dom_base, int n_inst, const double *theta,
+                            double *theta_acc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * n_inst) return;
+  const int inst = i / 3, t = i % 3;
+  double s = 0.0;
+  for (int k = dom_base[inst]; k < dom_base[inst + 1]; ++k) s += theta[4 * (int64_t)k + t];
+  theta_acc[i] += s;
 }
 
 // Forecast X_b = a X_a + V over every instance (blockIdx.y = instance).
@@ -917,4 +1410,77 @@ extern "C" hipError_t letkf_launch_eigh(const double *A, int m, int batch, doubl
 
 extern "C" size_t letkf_args_size(int fp64) {
   return fp64 ? sizeof(AnaArgs<double>) : sizeof(AnaArgs<float>);
+}
+
+extern "C" const void *letkf_adjoint_kernel(int fp64) {
+  return fp64 ? (const void *)k_adjoint<double, true> : (const void *)k_adjoint<float, true>;
+}
+
+extern "C" size_t letkf_adjoint_scratch_doubles(void) { return A_TOTAL; }
+
+extern "C" hipError_t letkf_launch_adjoint(int fp64, const void *args, int grid, size_t lds,
+                                           hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL((k_adjoint<double, true>), dim3(grid), dim3(kThreads), lds, s,
+                       *(const AdjArgs<double> *)args);
+  else
+    hipLaunchKernelGGL((k_adjoint<float, true>), dim3(grid), dim3(kThreads), lds, s,
+                       *(const AdjArgs<float> *)args);
+  return hipGetLastError();
+}
+
+extern "C" size_t letkf_adjoint_args_size(int fp64) {
+  return fp64 ? sizeof(AdjArgs<double>) : sizeof(AdjArgs<float>);
+}
+
+extern "C" hipError_t letkf_launch_adjoint_nodes(int fp64, const InstDesc *insts, int n_inst,
+                                                 const int32_t *node_adj, const int32_t *slot_off,
+                                                 const int32_t *slots, const void *xpbar,
+                                                 const double *xbbar, const void *ybar,
+                                                 const double *dbar, void *xbar_out, int max_nodes,
+                                                 hipStream_t s) {
+  const int gx = (max_nodes + kWaves - 1) / kWaves;
+  if (fp64)
+    hipLaunchKernelGGL(k_adjoint_nodes<double>, dim3(gx, n_inst), dim3(kThreads), 0, s, insts,
+                       node_adj, slot_off, slots, (const double *)xpbar, xbbar,
+                       (const double *)ybar, dbar, (double *)xbar_out);
+  else
+    hipLaunchKernelGGL(k_adjoint_nodes<float>, dim3(gx, n_inst), dim3(kThreads), 0, s, insts,
+                       node_adj, slot_off, slots, (const float *)xpbar, xbbar, (const float *)ybar,
+                       dbar, (float *)xbar_out);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t letkf_launch_resvar(int fp64, const InstDesc *insts, int n_inst, const void *x,
+                                          const void *truth, const double *weights, double *stats,
+                                          double *acc, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_resvar<double>, dim3(n_inst), dim3(256), 0, s, insts, (const double *)x,
+                       (const double *)truth, weights, stats, acc);
+  else
+    hipLaunchKernelGGL(k_resvar<float>, dim3(n_inst), dim3(256), 0, s, insts, (const float *)x,
+                       (const float *)truth, weights, stats, acc);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t letkf_launch_resvar_adjoint(int fp64, const InstDesc *insts, int n_inst,
+                                                  const void *x, const void *truth,
+                                                  const double *weights, const double *stats,
+                                                  void *xbar, int max_nodes, hipStream_t s) {
+  const int gx = (max_nodes + kWaves - 1) / kWaves;
+  if (fp64)
+    hipLaunchKernelGGL(k_resvar_adjoint<double>, dim3(gx, n_inst), dim3(kThreads), 0, s, insts,
+                       (const double *)x, (const double *)truth, weights, stats, (double *)xbar);
+  else
+    hipLaunchKernelGGL(k_resvar_adjoint<float>, dim3(gx, n_inst), dim3(kThreads), 0, s, insts,
+                       (const float *)x, (const float *)truth, weights, stats, (float *)xbar);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t letkf_launch_theta_sum(const int32_t *dom_base, int n_inst, const double *theta,
+                                             double *theta_acc, hipStream_t s) {
+  const int n = 3 * n_inst;
+  hipLaunchKernelGGL(k_theta_sum, dim3((n + 255) / 256), dim3(256), 0, s, dom_base, n_inst, theta,
+                     theta_acc);
+  return hipGetLastError();
 }
