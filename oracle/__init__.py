@@ -14,5 +14,6 @@ Modules
   kalman      brute-force Kalman update (the exact limit the ETKF must reach)
   philox      Philox4x32-10 counter-based generator and the noise-bank lookup
   accounting  the paper's operation counts (App. B, Tables 1, 3, 4)
+  piston      least-squares differential-piston removal after the gather
   adjoint     hand-written reverse-mode gradient of the residual-variance loss
 """

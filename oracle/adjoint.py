@@ -46,6 +46,8 @@ ensemble (the loss term plus what the next forecast sends back):
   F2       X'_bar += D^T Y'_bar,  xb_bar -= D^T d_bar,
            Xb_bar = X'_bar - (X'_bar 1 / m) 1^T + xb_bar 1^T / m;
   F1       the previous analysis ensemble receives a Xb_bar.
+With the differential-piston removal switched on, its adjoint (`piston`
+module) is applied to Xa_bar first.
 
 A domain whose forward analysis failed would keep its forecast; the oracle
 has no such failure path (LAPACK eigh), so none is modelled here.
@@ -56,6 +58,7 @@ import numpy as np
 
 from . import geometry as geo
 from . import letkf as lk
+from . import piston
 
 
 def loss(geom, doms, Xa0, V_seq, y_seq, truth, r_diag, params: lk.Params) -> float:
@@ -86,6 +89,8 @@ def frame_adjoint(geom, doms, Xa_prev, V, y, r_diag, params: lk.Params, Xa_bar):
     """Reverse of one frame: returns (a Xb_bar, (rho_bar, s_bar, c_bar)) for the
     adjoint Xa_bar of this frame's analysis ensemble."""
     p = params
+    if p.piston:  # the piston removal came last in the frame
+        Xa_bar = piston.remove_adjoint(geom, doms, Xa_bar)
     r_diag = np.asarray(r_diag, dtype=np.float64)
     Xb = lk.forecast(Xa_prev, V, p.a)
     n, m = Xb.shape
@@ -139,9 +144,8 @@ def frame_adjoint(geom, doms, Xa_prev, V, y, r_diag, params: lk.Params, Xa_bar):
         np.add.at(d_bar, dom.obs, sg * dt_bar)
     rho_bar += -k_bar * (m - 1) / p.rho ** 2
     # F2
-    D = geo.slope_matrix(geom)
-    Xp_bar += D.T @ Yp_bar
-    xb_bar -= D.T @ d_bar
+    Xp_bar += geo.apply_slopes_adjoint(geom, Yp_bar)
+    xb_bar -= geo.apply_slopes_adjoint(geom, d_bar)
     Xb_bar = Xp_bar - Xp_bar.mean(axis=1, keepdims=True) + xb_bar[:, None] / m
     return p.a * Xb_bar, np.array([rho_bar, s_bar, c_bar])
 

@@ -144,6 +144,22 @@ def apply_slopes(geom: Geometry, phase: np.ndarray) -> np.ndarray:
     return np.concatenate([sx, sy], axis=0)
 
 
+def apply_slopes_adjoint(geom: Geometry, s: np.ndarray) -> np.ndarray:
+    """D^T s: the transpose of G4 applied to slope vectors (p,) or (p, m),
+    each subaperture scattering its two slopes back onto its four corners."""
+    s = np.asarray(s, dtype=np.float64)
+    ps = geom.n_subaps
+    sx, sy = s[:ps], s[ps:]
+    idx = geom.node_index
+    i, j = geom.subaps[:, 0], geom.subaps[:, 1]
+    out = np.zeros((geom.n_nodes,) + s.shape[1:])
+    np.add.at(out, idx[i, j], -0.5 * sx - 0.5 * sy)
+    np.add.at(out, idx[i, j + 1], 0.5 * sx - 0.5 * sy)
+    np.add.at(out, idx[i + 1, j], -0.5 * sx + 0.5 * sy)
+    np.add.at(out, idx[i + 1, j + 1], 0.5 * sx + 0.5 * sy)
+    return out
+
+
 @dataclass
 class Domain:
     block: tuple            # (I, J)
@@ -245,6 +261,6 @@ def geometry_for(n_sub: int, obscuration: float | None) -> Geometry:
     return Geometry(pupil_mask(n_sub, obscuration))
 
 
-__all__ = ["pupil_mask", "square_mask", "Geometry", "slope_matrix", "apply_slopes",
+__all__ = ["pupil_mask", "square_mask", "Geometry", "slope_matrix", "apply_slopes", "apply_slopes_adjoint",
            "Domain", "domains", "owner_map", "gaspari_cohn", "gaspari_cohn_deriv",
            "taper", "taper_dist", "geometry_for"]

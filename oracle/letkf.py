@@ -45,6 +45,7 @@ class Params:
     b: int = 4                 # domain size in subapertures
     h: int = 1                 # halo in subapertures
     taper_c: float = 0.0       # Gaspari-Cohn half width in pitches, 0 = off
+    piston: bool = False       # differential-piston removal after the gather (Sec. 4.4)
 
 
 def forecast(Xa: np.ndarray, V: np.ndarray, a: float) -> np.ndarray:
@@ -154,8 +155,13 @@ def analysis(geom, doms, Xb, y, r_diag, params: Params, keep=None):
 
 
 def step(geom, doms, Xa_prev, V, y, r_diag, params: Params):
-    """One frame: forecast then analysis."""
-    return analysis(geom, doms, forecast(Xa_prev, V, params.a), y, r_diag, params)
+    """One frame: forecast, analysis and, when params.piston is set, the
+    differential-piston removal (the `piston` module)."""
+    Xa = analysis(geom, doms, forecast(Xa_prev, V, params.a), y, r_diag, params)
+    if params.piston:
+        from . import piston
+        Xa = piston.remove(geom, doms, Xa, y)
+    return Xa
 
 
 def residual_variance(xa_mean: np.ndarray, truth: np.ndarray) -> float:

@@ -133,3 +133,17 @@ def test_taper_off_is_one_and_on_is_local():
         f = geo.taper(d, 4, 2.0)
         dist = geo.taper_dist(d, 4)
         assert np.all((f > 0) == (dist < 4.0))
+
+
+@pytest.mark.parametrize("N,eps", [(6, None), (10, 0.3)])
+def test_slope_adjoint_is_the_transpose(N, eps):
+    # D^T by scatter against the dense matrix, and <D x, s> = <x, D^T s>
+    G = geo.geometry_for(N, eps)
+    rng = np.random.default_rng(N)
+    D = geo.slope_matrix(G)
+    s = rng.standard_normal((G.n_slopes, 3))
+    assert np.allclose(geo.apply_slopes_adjoint(G, s), D.T @ s, atol=1e-14)
+    x = rng.standard_normal(G.n_nodes)
+    s1 = s[:, 0]
+    assert np.dot(geo.apply_slopes(G, x), s1) == pytest.approx(np.dot(x, geo.apply_slopes_adjoint(G, s1)),
+                                                                rel=1e-13)
