@@ -93,6 +93,12 @@ typedef struct letkf_config {
                                   diagonal measure is <= tol; 0 = 1e-5 (FP32),
                                   1e-10 (FP64)                                     */
   int32_t max_sweeps;          /* 0 = 30                                           */
+  int32_t piston_removal;      /* 1: after the gather, remove one piston per domain
+                                  fitted by least squares to the slopes of the
+                                  subapertures that straddle domains (Sec. 4.4:
+                                  local estimates are blind to their own piston);
+                                  every member of the domain is shifted. Needs at
+                                  most 4096 domains in the instance.              */
 } letkf_config;
 
 /* Sizes of one instance (or totals when instance = -1). */

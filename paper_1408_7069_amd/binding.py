@@ -50,6 +50,7 @@ class Config(C.Structure):
         ("precision", C.c_int32),
         ("jacobi_tol", C.c_double),
         ("max_sweeps", C.c_int32),
+        ("piston_removal", C.c_int32),
     ]
 
 
@@ -140,6 +141,7 @@ class InstanceSpec:
     precision: int = FP32
     jacobi_tol: float = 0.0
     max_sweeps: int = 0
+    piston: bool = False                  # differential-piston removal after the gather
 
 
 def _config(spec: InstanceSpec, keep: list) -> Config:
@@ -172,6 +174,7 @@ def _config(spec: InstanceSpec, keep: list) -> Config:
     c.precision = spec.precision
     c.jacobi_tol = spec.jacobi_tol
     c.max_sweeps = spec.max_sweeps
+    c.piston_removal = 1 if spec.piston else 0
     return c
 
 

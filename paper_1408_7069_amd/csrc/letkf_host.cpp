@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <sstream>
 #include <string>
@@ -70,6 +71,12 @@ extern "C" hipError_t letkf_launch_resvar_adjoint(int fp64, const InstDesc *inst
                                                   const void *x, const void *truth,
                                                   const double *weights, const double *stats,
                                                   void *xbar, int max_nodes, hipStream_t s);
+extern "C" const void *letkf_piston_kernel(int fp64, int which);
+extern "C" size_t letkf_piston_args_size(int fp64);
+extern "C" void letkf_piston_grid(int which, int n_items, int n_inst, int max_nodes, int64_t max_elems,
+                                  int *gx, int *gy);
+extern "C" hipError_t letkf_launch_piston(int fp64, int which, const void *args, int gx, int gy,
+                                          hipStream_t s);
 extern "C" hipError_t letkf_launch_theta_sum(const int32_t *dom_base, int n_inst, const double *theta,
                                              double *theta_acc, hipStream_t s);
 
@@ -105,11 +112,31 @@ template <typename T> struct AnaArgsHost {
   const float *bank;
   const T *y;
   T *x_out;
+  T *x_mean;
   int32_t *flags;
   const uint32_t *frame;
   double jtol;
   int32_t max_sweeps;
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u;
+};
+
+// Mirror of PistonArgs<T>.
+template <typename T> struct PistonArgsHost {
+  const InstDesc *inst;
+  const DomItem *items;
+  int32_t n_items, pad0;
+  const int32_t *patch_node;
+  const int32_t *node_adj;
+  const int32_t *subap_nodes;
+  const int32_t *owner_item;
+  const int32_t *dom_base;
+  const int64_t *minv_off;
+  const double *minv;
+  const T *x_mean;
+  const T *y;
+  double *rhs;
+  double *pi;
+  T *x;
 };
 
 // Mirror of AdjArgs<T>.
@@ -190,6 +217,14 @@ struct letkf_handle {
   double *d_ones = nullptr, *d_stats = nullptr;
   void *d_xpbar = nullptr, *d_ybar = nullptr;
   double *d_xbbar = nullptr, *d_dbar = nullptr, *d_theta = nullptr;
+  // differential pistons: per-instance M^+ and the work buffers
+  bool any_piston = false;
+  int32_t *d_owner_item = nullptr;
+  int64_t *d_minv_off = nullptr;
+  double *d_minv = nullptr, *d_prhs = nullptr, *d_pi = nullptr;
+  void *d_xmean = nullptr;
+  std::vector<unsigned char> gpargs[2][2];  // graph: rhs args, solve/apply args
+  hipGraphNode_t gpnode[2][3] = {};
 };
 
 namespace {
@@ -320,6 +355,89 @@ int plan_instance(const letkf_config &c, InstGeom &g, std::string &err) {
   return LETKF_OK;
 }
 
+// M^+ of the differential-piston fit of one instance, row-major nd x nd:
+// M = P^T D^T D P (P: node -> owning domain), made definite by adding mu on
+// every connected set of domains (the common piston of a set is not
+// measurable; the right-hand sides are orthogonal to it, so the solution is
+// the minimum-norm least-squares one), then inverted through its Cholesky
+// factor.
+int piston_minv(const InstGeom &g, std::vector<double> &out, std::string &err) {
+  const int nd = (int)g.owned.size();
+  if (nd > 4096) {
+    err = "differential-piston removal supports at most 4096 domains per instance";
+    return LETKF_E_INVAL;
+  }
+  std::vector<double> M((size_t)nd * nd, 0.0);
+  const double cx[4] = {-0.5, 0.5, -0.5, 0.5}, cy[4] = {-0.5, -0.5, 0.5, 0.5};
+  for (int q = 0; q < g.n_subaps; ++q) {
+    const int32_t *cn = &g.subap_nodes[4 * q];
+    for (int comp = 0; comp < 2; ++comp) {
+      int dl[4];
+      double cv[4];
+      int n = 0;
+      for (int t = 0; t < 4; ++t) {
+        const int d = g.owner[cn[t]];
+        int k = 0;
+        while (k < n && dl[k] != d) ++k;
+        if (k == n) {
+          dl[n] = d;
+          cv[n++] = 0.0;
+        }
+        cv[k] += comp ? cy[t] : cx[t];
+      }
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) M[(size_t)dl[a] * nd + dl[b]] += cv[a] * cv[b];
+    }
+  }
+  std::vector<int> comp(nd);
+  for (int d = 0; d < nd; ++d) comp[d] = d;
+  std::function<int(int)> root = [&](int d) { return comp[d] == d ? d : (comp[d] = root(comp[d])); };
+  for (int d = 0; d < nd; ++d)
+    for (int e = d + 1; e < nd; ++e)
+      if (M[(size_t)d * nd + e] != 0.0) comp[root(d)] = root(e);
+  std::map<int, std::vector<int>> sets;
+  for (int d = 0; d < nd; ++d) sets[root(d)].push_back(d);
+  for (auto &kv : sets) {
+    double dmax = 0.0;
+    for (int d : kv.second) dmax = std::max(dmax, M[(size_t)d * nd + d]);
+    const double mu = dmax > 0.0 ? dmax / (double)kv.second.size() : 1.0;
+    for (int d : kv.second)
+      for (int e : kv.second) M[(size_t)d * nd + e] += mu;
+  }
+  // Cholesky M = L L^T (lower, in place)
+  for (int j = 0; j < nd; ++j) {
+    double djj = M[(size_t)j * nd + j];
+    for (int k = 0; k < j; ++k) djj -= M[(size_t)j * nd + k] * M[(size_t)j * nd + k];
+    if (!(djj > 0.0)) {
+      err = "differential-piston normal matrix is not definite";
+      return LETKF_E_INVAL;
+    }
+    const double ljj = std::sqrt(djj);
+    M[(size_t)j * nd + j] = ljj;
+    for (int i = j + 1; i < nd; ++i) {
+      double v = M[(size_t)i * nd + j];
+      for (int k = 0; k < j; ++k) v -= M[(size_t)i * nd + k] * M[(size_t)j * nd + k];
+      M[(size_t)i * nd + j] = v / ljj;
+    }
+  }
+  // inverse column by column: L z = e_c, L^T x = z
+  out.assign((size_t)nd * nd, 0.0);
+  std::vector<double> z(nd);
+  for (int c = 0; c < nd; ++c) {
+    for (int i = 0; i < nd; ++i) {
+      double v = i == c ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) v -= M[(size_t)i * nd + k] * z[k];
+      z[i] = v / M[(size_t)i * nd + i];
+    }
+    for (int i = nd - 1; i >= 0; --i) {
+      double v = z[i];
+      for (int k = i + 1; k < nd; ++k) v -= M[(size_t)k * nd + i] * out[(size_t)k * nd + c];
+      out[(size_t)i * nd + c] = v / M[(size_t)i * nd + i];
+    }
+  }
+  return LETKF_OK;
+}
+
 int validate(const letkf_config &c, int idx, std::string &err) {
   std::ostringstream o;
   o << "instance " << idx << ": ";
@@ -362,7 +480,8 @@ void free_handle(letkf_handle *h) {
                   h->d_obs_corner, h->d_obs_dist, h->d_bank, h->d_r, h->d_xa[0], h->d_xa[1],
                   h->d_xb, h->d_tmp, h->d_frame, h->d_flags, h->d_node_adj, h->d_slot_off,
                   h->d_slots, h->d_dom_base, h->d_ones, h->d_stats, h->d_xpbar, h->d_ybar,
-                  h->d_xbbar, h->d_dbar, h->d_theta};
+                  h->d_xbbar, h->d_dbar, h->d_theta, h->d_owner_item, h->d_minv_off, h->d_minv,
+                  h->d_prhs, h->d_pi, h->d_xmean};
   for (void *p : ptrs)
     if (p) hipFree(p);
   delete h;
@@ -390,6 +509,7 @@ AnaArgsHost<T> make_args(letkf_handle *h, bool fused, const void *V, const void 
   A.bank = h->d_bank;
   A.y = (const T *)y;
   A.x_out = (T *)h->d_xa[xa_out];
+  A.x_mean = h->any_piston ? (T *)h->d_xmean : nullptr;
   A.flags = h->d_flags;
   A.frame = h->d_frame;
   A.jtol = h->jtol;
@@ -403,6 +523,52 @@ AnaArgsHost<T> make_args(letkf_handle *h, bool fused, const void *V, const void 
   A.off_s = h->off[6];
   A.off_u = h->off[7];
   return A;
+}
+
+template <typename T>
+PistonArgsHost<T> make_piston_args(letkf_handle *h, const void *y, void *x) {
+  PistonArgsHost<T> P;
+  std::memset(&P, 0, sizeof(P));
+  P.inst = h->d_desc;
+  P.items = h->d_items;
+  P.n_items = (int32_t)h->items.size();
+  P.patch_node = h->d_patch;
+  P.node_adj = h->d_node_adj;
+  P.subap_nodes = h->d_subap_nodes;
+  P.owner_item = h->d_owner_item;
+  P.dom_base = h->d_dom_base;
+  P.minv_off = h->d_minv_off;
+  P.minv = h->d_minv;
+  P.x_mean = (const T *)h->d_xmean;
+  P.y = (const T *)y;
+  P.rhs = h->d_prhs;
+  P.pi = h->d_pi;
+  P.x = (T *)x;
+  return P;
+}
+
+std::vector<unsigned char> piston_blob(letkf_handle *h, const void *y, void *x) {
+  if (h->fp64) {
+    auto P = make_piston_args<double>(h, y, x);
+    return std::vector<unsigned char>((unsigned char *)&P, (unsigned char *)&P + sizeof(P));
+  }
+  auto P = make_piston_args<float>(h, y, x);
+  return std::vector<unsigned char>((unsigned char *)&P, (unsigned char *)&P + sizeof(P));
+}
+
+// Kernels `which` in order on `s`, all with one argument block.
+int launch_piston_seq(letkf_handle *h, std::initializer_list<int> which, const void *y, void *x,
+                      hipStream_t s) {
+  if (!h->any_piston) return LETKF_OK;
+  std::vector<unsigned char> blob = piston_blob(h, y, x);
+  if (blob.size() != letkf_piston_args_size(h->fp64))
+    return fail(LETKF_E_DEVICE, "piston argument layout mismatch");
+  for (int w : which) {
+    int gx, gy;
+    letkf_piston_grid(w, (int)h->items.size(), h->n_inst, h->max_nodes, h->max_elems, &gx, &gy);
+    HIPCHK(letkf_launch_piston(h->fp64, w, blob.data(), gx, gy, s));
+  }
+  return LETKF_OK;
 }
 
 int grid_for(const letkf_handle *h) {
@@ -428,7 +594,8 @@ int check_noise(letkf_handle *h, const void *V) {
   return LETKF_OK;
 }
 
-// Build (once per parity) or refresh the graph of the fused frame.
+// Build (once per parity) or refresh the graph of the fused frame: the
+// analysis, the differential-piston kernels when enabled, the frame counter.
 int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
   const int p = h->cur;
   std::vector<unsigned char> args;
@@ -444,6 +611,25 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
   kp.gridDim = dim3(grid_for(h));
   kp.func = (void *)letkf_analysis_kernel(h->fp64, 1);
   kp.sharedMemBytes = (unsigned)h->lds;
+  // piston nodes: the right-hand side reads y; solve and apply do not
+  std::vector<unsigned char> prhs, pfix;
+  if (h->any_piston) {
+    prhs = piston_blob(h, y, h->d_xa[1 - p]);
+    pfix = piston_blob(h, nullptr, h->d_xa[1 - p]);
+  }
+  auto piston_params = [&](int which, std::vector<unsigned char> &blob, void **slot) {
+    hipKernelNodeParams q{};
+    int gx, gy;
+    letkf_piston_grid(which, (int)h->items.size(), h->n_inst, h->max_nodes, h->max_elems, &gx, &gy);
+    q.blockDim = dim3(letkf_analysis_threads());
+    q.gridDim = dim3(gx, gy);
+    q.func = (void *)letkf_piston_kernel(h->fp64, which);
+    slot[0] = blob.data();
+    q.kernelParams = slot;
+    q.extra = nullptr;
+    q.sharedMemBytes = 0;
+    return q;
+  };
   if (!h->gexec[p]) {
     h->gargs[p] = args;
     void *kargs[] = {h->gargs[p].data()};
@@ -451,6 +637,19 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
     kp.extra = nullptr;
     HIPCHK(hipGraphCreate(&h->graph[p], 0));
     HIPCHK(hipGraphAddKernelNode(&h->gnode[p], h->graph[p], nullptr, 0, &kp));
+    hipGraphNode_t last = h->gnode[p];
+    if (h->any_piston) {
+      h->gpargs[p][0] = prhs;
+      h->gpargs[p][1] = pfix;
+      void *s0[1], *s1[1], *s2[1];
+      hipKernelNodeParams q0 = piston_params(0, h->gpargs[p][0], s0);
+      hipKernelNodeParams q1 = piston_params(1, h->gpargs[p][1], s1);
+      hipKernelNodeParams q2 = piston_params(2, h->gpargs[p][1], s2);
+      HIPCHK(hipGraphAddKernelNode(&h->gpnode[p][0], h->graph[p], &last, 1, &q0));
+      HIPCHK(hipGraphAddKernelNode(&h->gpnode[p][1], h->graph[p], &h->gpnode[p][0], 1, &q1));
+      HIPCHK(hipGraphAddKernelNode(&h->gpnode[p][2], h->graph[p], &h->gpnode[p][1], 1, &q2));
+      last = h->gpnode[p][2];
+    }
     // then the frame counter of the bank draws
     hipKernelNodeParams kp2{};
     void *a2[] = {&h->d_frame};
@@ -461,14 +660,22 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
     kp2.extra = nullptr;
     kp2.sharedMemBytes = 0;
     hipGraphNode_t adv;
-    HIPCHK(hipGraphAddKernelNode(&adv, h->graph[p], &h->gnode[p], 1, &kp2));
+    HIPCHK(hipGraphAddKernelNode(&adv, h->graph[p], &last, 1, &kp2));
     HIPCHK(hipGraphInstantiate(&h->gexec[p], h->graph[p], nullptr, nullptr, 0));
-  } else if (args != h->gargs[p]) {
-    h->gargs[p] = args;
-    void *kargs[] = {h->gargs[p].data()};
-    kp.kernelParams = kargs;
-    kp.extra = nullptr;
-    HIPCHK(hipGraphExecKernelNodeSetParams(h->gexec[p], h->gnode[p], &kp));
+  } else {
+    if (args != h->gargs[p]) {
+      h->gargs[p] = args;
+      void *kargs[] = {h->gargs[p].data()};
+      kp.kernelParams = kargs;
+      kp.extra = nullptr;
+      HIPCHK(hipGraphExecKernelNodeSetParams(h->gexec[p], h->gnode[p], &kp));
+    }
+    if (h->any_piston && prhs != h->gpargs[p][0]) {
+      h->gpargs[p][0] = prhs;
+      void *s0[1];
+      hipKernelNodeParams q0 = piston_params(0, h->gpargs[p][0], s0);
+      HIPCHK(hipGraphExecKernelNodeSetParams(h->gexec[p], h->gpnode[p][0], &q0));
+    }
   }
   HIPCHK(hipGraphLaunch(h->gexec[p], s));
   return LETKF_OK;
@@ -543,6 +750,8 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     d.seed_lo = (uint32_t)(c.seed & 0xffffffffu);
     d.seed_hi = (uint32_t)(c.seed >> 32);
     d.instance = (uint32_t)i;
+    d.piston = c.piston_removal ? 1 : 0;
+    h->any_piston = h->any_piston || d.piston;
     d.a = c.ar_coeff;
     d.rho = c.rho;
     d.r_scale = c.r_scale;
@@ -663,6 +872,26 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     }
   }
 
+  // differential pistons: owning item of every node, M^+ per instance
+  std::vector<int32_t> owner_item((size_t)std::max<int64_t>(h->total_nodes, 1), 0);
+  std::vector<int64_t> minv_off;
+  std::vector<double> minv;
+  for (size_t k = 0; k < h->items.size(); ++k) {
+    const DomItem &it = h->items[k];
+    const InstGeom &g = h->geom[it.inst];
+    for (int32_t nd_ : g.owned[it.dom]) owner_item[(size_t)(h->desc[it.inst].node_off + nd_)] = (int32_t)k;
+  }
+  for (int i = 0; i < n_instances; ++i) {
+    minv_off.push_back((int64_t)minv.size());
+    if (!h->desc[i].piston) continue;
+    std::vector<double> mi;
+    if (piston_minv(h->geom[i], mi, err) != LETKF_OK) {
+      free_handle(h);
+      return fail(LETKF_E_INVAL, "instance " + std::to_string(i) + ": " + err);
+    }
+    minv.insert(minv.end(), mi.begin(), mi.end());
+  }
+
   int rc = LETKF_OK;
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) {
@@ -690,7 +919,11 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
       (rc = to_device(&h->d_node_adj, node_adj)) || (rc = to_device(&h->d_slot_off, slot_off)) ||
       (rc = to_device(&h->d_slots, slots)) || (rc = to_device(&h->d_dom_base, dom_base)) ||
       (rc = to_device(&h->d_ones, std::vector<double>((size_t)n_instances, 1.0))) ||
-      (rc = to_device(&h->d_stats, std::vector<double>(2 * (size_t)n_instances, 0.0)))) {
+      (rc = to_device(&h->d_stats, std::vector<double>(2 * (size_t)n_instances, 0.0))) ||
+      (rc = to_device(&h->d_owner_item, owner_item)) || (rc = to_device(&h->d_minv_off, minv_off)) ||
+      (rc = to_device(&h->d_minv, minv)) ||
+      (rc = to_device(&h->d_prhs, std::vector<double>(std::max<size_t>(h->items.size(), 1), 0.0))) ||
+      (rc = to_device(&h->d_pi, std::vector<double>(std::max<size_t>(h->items.size(), 1), 0.0)))) {
     free_handle(h);
     return rc;
   }
@@ -703,6 +936,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     hipMemset(*p, 0, std::max<size_t>(xbytes, 16));
   }
   if (hipMalloc(&h->d_tmp, std::max<size_t>((size_t)h->total_nodes * T, 16)) != hipSuccess ||
+      hipMalloc(&h->d_xmean, std::max<size_t>((size_t)h->total_nodes * T, 16)) != hipSuccess ||
       hipMalloc((void **)&h->d_frame, 16) != hipSuccess ||
       hipMalloc((void **)&h->d_flags, std::max<size_t>(h->items.size(), 1) * 4) != hipSuccess) {
     free_handle(h);
@@ -825,6 +1059,7 @@ int letkf_analyse(letkf_handle *h, const void *y_dev, void *stream) {
   hipSetDevice(h->device);
   int rc = launch_analysis(h, false, nullptr, y_dev, h->cur, h->cur, (hipStream_t)stream);
   if (rc) return rc;
+  if ((rc = launch_piston_seq(h, {0, 1, 2}, y_dev, h->d_xa[h->cur], (hipStream_t)stream))) return rc;
   h->have_xb = false;
   return LETKF_OK;
 }
@@ -841,6 +1076,7 @@ int letkf_step(letkf_handle *h, const void *V_dev, const void *y_dev, void *stre
   } else {
     rc = launch_analysis(h, true, V_dev, y_dev, h->cur, 1 - h->cur, s);
     if (rc) return rc;
+    if ((rc = launch_piston_seq(h, {0, 1, 2}, y_dev, h->d_xa[1 - h->cur], s))) return rc;
     HIPCHK(letkf_launch_frame_advance(h->d_frame, s));
   }
   h->cur = 1 - h->cur;
@@ -868,6 +1104,7 @@ int letkf_step_plain(letkf_handle *h, const void *V_dev, const void *y_dev, void
       HIPCHK(letkf_launch_analysis_f32(&A, 1, 1, h->lds, s));
     }
   }
+  if ((rc = launch_piston_seq(h, {0, 1, 2}, y_dev, h->d_xa[1 - h->cur], s))) return rc;
   HIPCHK(letkf_launch_frame_advance(h->d_frame, s));
   h->cur = 1 - h->cur;
   h->have_xb = false;
@@ -1109,6 +1346,7 @@ static AdjArgsHost<T> make_adj_args(letkf_handle *h, const void *xa_prev, const 
   D.F = make_args<T>(h, true, V, y, 0, 0);
   D.F.x_in = (const T *)xa_prev;
   D.F.x_out = nullptr;
+  D.F.x_mean = nullptr;
   D.F.xcd_order = 0;
   D.F.frame = nullptr;
   D.xbar = (const T *)xbar;
@@ -1135,6 +1373,8 @@ int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, u
   if ((rc = ensure_adjoint(h))) return rc;
   hipStream_t s = (hipStream_t)stream;
   const int grid = (int)h->items.size();
+  // the piston removal came last in the frame: its adjoint first
+  if ((rc = launch_piston_seq(h, {3, 1, 4}, nullptr, xbar_dev, s))) return rc;
   if (h->fp64) {
     auto D = make_adj_args<double>(h, xa_prev_dev, V_dev, frame, y_dev, xbar_dev);
     if (sizeof(D) != letkf_adjoint_args_size(1)) return fail(LETKF_E_DEVICE, "argument layout mismatch");

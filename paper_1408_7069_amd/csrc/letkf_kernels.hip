@@ -551,6 +551,7 @@ template <typename T> struct AnaArgs {
   const float *bank;
   const T *y;
   T *x_out;
+  T *x_mean;           // analysis mean of every node (NULL: not written)
   int32_t *flags;
   const uint32_t *frame;  // frame counter of the bank draws (device)
   double jtol;
@@ -744,6 +745,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     double s = mu;
     for (int k = 0; k < m; ++k) s = fma((double)xs[tid * kXsStride + k] - mu, sm[S_WV + k], s);
     sm[S_XAM + tid] = s;
+    if (A.x_mean) A.x_mean[in.node_off + pn[tid]] = keep_forecast ? xm[tid] : (T)s;
   }
   __syncthreads();
   const T srho = (T)sqrt(in.rho);
@@ -1224,6 +1226,129 @@ __global__ void k_theta_sum(const int32_t *dom_base, int n_inst, const double *t
   theta_acc[i] += s;
 }
 
+// ------------------------------------------------- differential pistons
+// Least-squares removal of one piston per domain after the gather (Sec.
+// 4.4): pi = M^+ P^T D^T (y - D x_a) with P the node-to-domain indicator and
+// M = P^T D^T D P (only subapertures with corners in two or more domains
+// contribute); M^+ is precomputed per instance.  Then every member of a node
+// gets the piston of its domain.  One wavefront per domain or node.
+template <typename T> struct PistonArgs {
+  const InstDesc *inst;
+  const DomItem *items;
+  int32_t n_items, pad0;
+  const int32_t *patch_node;   // owned nodes first
+  const int32_t *node_adj;     // per global node: subaperture of corner role a, b, c, d (-1)
+  const int32_t *subap_nodes;  // per global subaperture: its 4 corner nodes (instance-local)
+  const int32_t *owner_item;   // per global node: the work item owning it
+  const int32_t *dom_base;     // first item of each instance (+ total)
+  const int64_t *minv_off;     // offset of each instance's M^+ (nd x nd, row-major)
+  const double *minv;
+  const T *x_mean;             // analysis mean per global node
+  const T *y;                  // slopes
+  double *rhs;                 // per item (forward: P^T D^T residual; adjoint: P^T Z_bar 1)
+  double *pi;                  // per item (forward: pistons; adjoint: M^+ of the sums)
+  T *x;                        // ensemble updated in place
+};
+
+// rhs[item] = sum over the owned nodes of (D^T (y - D x_mean))_node.
+template <typename T> __global__ void k_piston_rhs(const PistonArgs<T> P) {
+  const int item = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (item >= P.n_items) return;
+  const DomItem it = P.items[item];
+  const InstDesc in = P.inst[it.inst];
+  double v = 0.0;
+  if (in.piston && lane < it.n_own) {
+    const int64_t gn = in.node_off + P.patch_node[it.patch_off + lane];
+    const int64_t sub0 = in.y_off / 2;
+    for (int role = 0; role < 4; ++role) {
+      const int s = P.node_adj[4 * gn + role];
+      if (s < 0) continue;
+      const int32_t *c = P.subap_nodes + 4 * (int64_t)s;
+      const double xa = (double)P.x_mean[in.node_off + c[0]], xb = (double)P.x_mean[in.node_off + c[1]];
+      const double xc = (double)P.x_mean[in.node_off + c[2]], xd = (double)P.x_mean[in.node_off + c[3]];
+      const int64_t k = s - sub0;
+      const double ex = (double)P.y[in.y_off + k] - 0.5 * ((xb - xa) + (xd - xc));
+      const double ey = (double)P.y[in.y_off + in.n_subaps + k] - 0.5 * ((xc - xa) + (xd - xb));
+      v += ((role & 1) ? 0.5 : -0.5) * ex + ((role & 2) ? 0.5 : -0.5) * ey;
+    }
+  }
+  v = wave_sum(v);
+  if (lane == 0) P.rhs[item] = v;
+}
+
+// pi[item] = row of M^+ times rhs over the items of the same instance.
+template <typename T> __global__ void k_piston_solve(const PistonArgs<T> P) {
+  const int item = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (item >= P.n_items) return;
+  const int inst = P.items[item].inst;
+  if (!P.inst[inst].piston) {
+    if (lane == 0) P.pi[item] = 0.0;
+    return;
+  }
+  const int b0 = P.dom_base[inst], nd = P.dom_base[inst + 1] - b0;
+  const double *row = P.minv + P.minv_off[inst] + (int64_t)(item - b0) * nd;
+  double v = 0.0;
+  for (int e = lane; e < nd; e += 64) v = fma(row[e], P.rhs[b0 + e], v);
+  v = wave_sum(v);
+  if (lane == 0) P.pi[item] = v;
+}
+
+// x[node][j] += pi[owner(node)] (blockIdx.y = instance).
+template <typename T> __global__ void k_piston_apply(const PistonArgs<T> P) {
+  const InstDesc in = P.inst[blockIdx.y];
+  if (!in.piston) return;
+  const int64_t n = (int64_t)in.n_nodes * in.m;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t node = e / in.m;
+    const double pv = P.pi[P.owner_item[in.node_off + node]];
+    P.x[in.x_off + e] = (T)((double)P.x[in.x_off + e] + pv);
+  }
+}
+
+// Adjoint: rhs[item] = sum over the owned nodes and members of Z_bar.
+template <typename T> __global__ void k_piston_adj_sum(const PistonArgs<T> P) {
+  const int item = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (item >= P.n_items) return;
+  const DomItem it = P.items[item];
+  const InstDesc in = P.inst[it.inst];
+  double v = 0.0;
+  if (in.piston && lane < in.m)
+    for (int i = 0; i < it.n_own; ++i)
+      v += (double)P.x[in.x_off + (int64_t)P.patch_node[it.patch_off + i] * in.m + lane];
+  v = wave_sum(v);
+  if (lane == 0) P.rhs[item] = v;
+}
+
+// Adjoint: x[node][j] -= (D^T D P t)_node / m with t = pi (blockIdx.y =
+// instance, one wavefront per node).
+template <typename T> __global__ void k_piston_adj_apply(const PistonArgs<T> P) {
+  const InstDesc in = P.inst[blockIdx.y];
+  if (!in.piston) return;
+  const int g = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= in.n_nodes) return;
+  const int64_t gn = in.node_off + g;
+  double v = 0.0;
+  for (int role = 0; role < 4; ++role) {
+    const int s = P.node_adj[4 * gn + role];
+    if (s < 0) continue;
+    const int32_t *c = P.subap_nodes + 4 * (int64_t)s;
+    const double ta = P.pi[P.owner_item[in.node_off + c[0]]], tb = P.pi[P.owner_item[in.node_off + c[1]]];
+    const double tc = P.pi[P.owner_item[in.node_off + c[2]]], td = P.pi[P.owner_item[in.node_off + c[3]]];
+    const double rx = 0.5 * ((tb - ta) + (td - tc));
+    const double ry = 0.5 * ((tc - ta) + (td - tb));
+    v += ((role & 1) ? 0.5 : -0.5) * rx + ((role & 2) ? 0.5 : -0.5) * ry;
+  }
+  if (lane < in.m) {
+    const int64_t e = in.x_off + (int64_t)g * in.m + lane;
+    P.x[e] = (T)((double)P.x[e] - v / (double)in.m);
+  }
+}
+
 // Forecast X_b = a X_a + V over every instance (blockIdx.y = instance).
 template <typename T>
 __global__ void k_forecast(const InstDesc *insts, const int32_t *node_ij, const T *xa, const T *v,
@@ -1483,4 +1608,45 @@ extern "C" hipError_t letkf_launch_theta_sum(const int32_t *dom_base, int n_inst
   hipLaunchKernelGGL(k_theta_sum, dim3((n + 255) / 256), dim3(256), 0, s, dom_base, n_inst, theta,
                      theta_acc);
   return hipGetLastError();
+}
+
+// Differential pistons: which = 0 rhs, 1 solve, 2 apply, 3 adjoint sums,
+// 4 adjoint apply; the kernel and its launch shape for graph nodes too.
+extern "C" const void *letkf_piston_kernel(int fp64, int which) {
+  if (fp64) {
+    const void *k[5] = {(const void *)k_piston_rhs<double>, (const void *)k_piston_solve<double>,
+                        (const void *)k_piston_apply<double>, (const void *)k_piston_adj_sum<double>,
+                        (const void *)k_piston_adj_apply<double>};
+    return k[which];
+  }
+  const void *k[5] = {(const void *)k_piston_rhs<float>, (const void *)k_piston_solve<float>,
+                      (const void *)k_piston_apply<float>, (const void *)k_piston_adj_sum<float>,
+                      (const void *)k_piston_adj_apply<float>};
+  return k[which];
+}
+
+extern "C" size_t letkf_piston_args_size(int fp64) {
+  return fp64 ? sizeof(PistonArgs<double>) : sizeof(PistonArgs<float>);
+}
+
+// Grid of piston kernel `which` (block = kThreads).
+extern "C" void letkf_piston_grid(int which, int n_items, int n_inst, int max_nodes,
+                                  int64_t max_elems, int *gx, int *gy) {
+  if (which == 0 || which == 1 || which == 3) {
+    *gx = (n_items + kWaves - 1) / kWaves;
+    *gy = 1;
+  } else if (which == 2) {
+    int64_t b = (max_elems + kThreads - 1) / kThreads;
+    *gx = (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+    *gy = n_inst;
+  } else {
+    *gx = (max_nodes + kWaves - 1) / kWaves;
+    *gy = n_inst;
+  }
+}
+
+extern "C" hipError_t letkf_launch_piston(int fp64, int which, const void *args, int gx, int gy,
+                                          hipStream_t s) {
+  void *kargs[] = {(void *)args};
+  return hipLaunchKernel(letkf_piston_kernel(fp64, which), dim3(gx, gy), dim3(kThreads), kargs, 0, s);
 }

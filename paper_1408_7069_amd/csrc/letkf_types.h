@@ -20,7 +20,8 @@ struct InstDesc {
   int32_t n_nodes, n_slopes, n_subaps, m;
   int32_t bank_screens, bank_side;
   uint32_t seed_lo, seed_hi;
-  uint32_t instance, pad0;
+  uint32_t instance;
+  int32_t piston;      // 1: differential-piston removal after the gather
   double a, rho, r_scale, taper_c;
 };
 

@@ -10,12 +10,12 @@ from paper_1408_7069_amd import workload as wl
 
 class Case:
     def __init__(self, N, eps, b, h, m, seed=0, taper_c=0.0, rho=1.05, a=0.99, sigma=0.1,
-                 r0=0.15, pitch=0.5, fp64=False, r_scale=1.0, bank_screens=8):
+                 r0=0.15, pitch=0.5, fp64=False, r_scale=1.0, bank_screens=8, piston=False):
         self.N, self.eps, self.b, self.h, self.m = N, eps, b, h, m
         self.rng = np.random.default_rng(seed)
         self.G = geo.geometry_for(N, eps)
         self.doms = geo.domains(self.G, b, h)
-        self.prm = ol.Params(a=a, rho=rho, r_scale=r_scale, b=b, h=h, taper_c=taper_c)
+        self.prm = ol.Params(a=a, rho=rho, r_scale=r_scale, b=b, h=h, taper_c=taper_c, piston=piston)
         self.sigma, self.r0, self.pitch, self.fp64 = sigma, r0, pitch, fp64
         self.ij = self.G.node_coords()
         self.r = np.full(self.G.n_slopes, sigma * sigma) * self.rng.uniform(0.8, 1.25, self.G.n_slopes)
@@ -32,7 +32,7 @@ class Case:
                  mask=geo.square_mask(self.N) if self.eps is None else None,
                  rho=self.prm.rho, r_diag=self.r, r_scale=self.prm.r_scale, ar_coeff=self.prm.a,
                  taper_c=self.prm.taper_c, noise_bank=self.bank, seed=self.seed,
-                 precision=B.FP64 if self.fp64 else B.FP32)
+                 precision=B.FP64 if self.fp64 else B.FP32, piston=self.prm.piston)
         d.update(kw)
         return B.InstanceSpec(**d)
 
@@ -55,8 +55,13 @@ class Case:
         return philox.bank_noise(self.bank, self.ij, self.m, self.seed, instance, frame)
 
     def oracle_analysis(self, Xb, y, **kw):
-        return ol.analysis(self.G, self.doms, np.asarray(Xb, np.float64), np.asarray(y, np.float64),
-                           self.r, self.prm, **kw)
+        """The analysis (and the piston removal when the case has it on)."""
+        Xa = ol.analysis(self.G, self.doms, np.asarray(Xb, np.float64), np.asarray(y, np.float64),
+                         self.r, self.prm, **kw)
+        if self.prm.piston:
+            from oracle import piston
+            Xa = piston.remove(self.G, self.doms, Xa, y)
+        return Xa
 
 
 def rel_err(got, ref):
