@@ -10,7 +10,8 @@ noise, and model noise drawn on the device from a bank of von Karman screens.
 All inputs are resident in HBM before timing starts.
 
 One step = one letkf_step: the fused forecast, all local analyses in one
-launch (graph replay) and the gather.  Prints one JSON line.
+launch, the gather and the least-squares differential-piston removal (graph
+replay).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -26,6 +27,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "LETKF frames/sec and local analyses/sec at 80×80 SH, m=64; batched vs plain"
+COPY_BYTES = 256 << 20       # calibration copy of the profile run (read and written once)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_analysis_80x80_m64_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1408_7069_amd", "csrc", "letkf_kernels.hip")
+
+
+def kernel_hash() -> str:
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per analysis launch from the committed counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
@@ -58,9 +82,11 @@ def make_inputs(f, wl_mod, w, frames: int, rng):
     return y, truth, ij
 
 
-def time_steps(f, y, K, W, plain=False, per_step=False):
+def time_steps(f, y, K, W, plain=False, per_step=False, offset=0):
+    """W untimed then K timed steps on slopes y[offset + W + k]."""
     import torch
     step = f.step_plain if plain else f.step
+    y = y[offset:] if offset else y
     for k in range(W):
         step(y[k % y.shape[0]])
     torch.cuda.synchronize()
@@ -72,6 +98,9 @@ def time_steps(f, y, K, W, plain=False, per_step=False):
             ev[k][1].record()
         torch.cuda.synchronize()
         return np.array([a.elapsed_time(b) for a, b in ev])
+    if K == 0:
+        torch.cuda.synchronize()
+        return None
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for k in range(K):
@@ -92,7 +121,7 @@ def cpu_baseline(w, bank, seed, truth, sigma_noise, budget_s=12.0):
     ij0 = G.node_coords()
     y_host = [og.apply_slopes(G, truth[k][ij0[:, 0], ij0[:, 1]]) + sigma_noise[k] for k in range(len(truth))]
     doms = og.domains(G, w.b, w.h)
-    prm = ol.Params(a=w.a, rho=w.rho, b=w.b, h=w.h)
+    prm = ol.Params(a=w.a, rho=w.rho, b=w.b, h=w.h, piston=True)
     r = np.full(G.n_slopes, w.sigma ** 2)
     ij = G.node_coords()
     Xa = np.zeros((G.n_nodes, w.m))
@@ -110,6 +139,37 @@ def cpu_baseline(w, bank, seed, truth, sigma_noise, budget_s=12.0):
                       f"NumPy FP64 with LAPACK eigh, one thread, {dt:.1f} s"}
 
 
+def gradient_timing(B, w, bank, seed, y, truth, ij, T):
+    """The tuning run's gradient: T frames of the 80x80 workload with a
+    Gaspari-Cohn taper (c = 2 pitches), loss = mean residual variance, gradient
+    in (rho, r_scale, taper_c) through the hand-written adjoint, checkpoints
+    every 20 frames."""
+    import torch
+    from paper_1408_7069_amd import tuning
+    spec = B.InstanceSpec(n_sub=w.n_sub, m=w.m, domain_size=w.b, halo=w.h, obscuration=w.obscuration,
+                          rho=w.rho, r_sigma2=w.sigma ** 2, ar_coeff=w.a, noise_bank=bank, seed=seed,
+                          taper_c=2.0, precision=B.FP32, piston=True)
+    f = B.Letkf([spec])
+    T = min(T, y.shape[0])
+    ts = [torch.from_numpy(np.ascontiguousarray(truth[k][ij[:, 0], ij[:, 1]], dtype=np.float32)).cuda()
+          for k in range(T)]
+    ys = [y[k] for k in range(T)]
+    theta = torch.tensor([w.rho, 1.0, 2.0], dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = tuning.residual_variance_loss(f, theta, ys, ts, checkpoint_every=20)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.sum().backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f.close()
+    return {"frames": T, "checkpoint_every": 20, "forward_s": round(t1 - t0, 4),
+            "backward_s": round(t2 - t1, 4), "loss": loss.item(),
+            "d_loss_d_rho_rscale_taper": [float(v) for v in theta.grad],
+            "note": "80x80 m=64 with taper c=2; FP32 state, FP64 eigensolve and its adjoint"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +179,7 @@ def main():
     ap.add_argument("--copies", type=int, default=4, help="instances of the workload in one launch (batched throughput line)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: timed steps only")
+    ap.add_argument("--grad-frames", type=int, default=200, help="frames of the gradient timing (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the frame is not sharded "
@@ -136,7 +197,7 @@ def main():
     seed = 0x5EED0000 + w.seed
     spec = B.InstanceSpec(n_sub=w.n_sub, m=w.m, domain_size=w.b, halo=w.h, obscuration=w.obscuration,
                           rho=w.rho, r_sigma2=w.sigma ** 2, ar_coeff=w.a, noise_bank=bank, seed=seed,
-                          precision=B.FP32)
+                          precision=B.FP32, piston=True)
     f = B.Letkf([spec])
     K, W = args.steps, args.warmup
     frames = min(K + W, 600)
@@ -144,22 +205,50 @@ def main():
     print(f"# inputs ready: {frames} frames of slopes on the GPU", file=sys.stderr, flush=True)
 
     if args.profile:
+        # direct launches (the same kernel the graph replays), then a plain
+        # copy of known size that calibrates the HBM byte counters
+        f.set_schedule(False, True)
         time_steps(f, y, K, W)
-        print(json.dumps({"profile_run": True, "steps": K}))
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "steps": K, "copy_bytes": COPY_BYTES}))
         return
 
     sched = f.autotune(y[0], frames=10)
+    f.set_ensemble(torch.zeros(f.sizes["ensemble_elems"], dtype=torch.float32, device="cuda"))
+    f.set_frame(0)
     ms = time_steps(f, y, K, W)
     fps = 1000.0 / ms
+    # the filter is tracking: residual variance of the last analysis mean
+    last = (W + K - 1) % y.shape[0]
+    t_last = truth[last][ij[:, 0], ij[:, 1]].astype(np.float64)
+    e = f.get_mean().cpu().numpy().astype(np.float64) - t_last
+    filt = {"frame": last, "residual_variance": float(np.mean((e - e.mean()) ** 2)),
+            "phase_variance": float(np.mean((t_last - t_last.mean()) ** 2))}
     n_dom = f.sizes["n_domains"]
-    # per-step distribution and the analysis kernel's launch duration (direct
-    # launches, no graph: one analysis launch plus the one-thread frame counter)
+    # per-step distribution (graph replay), then the analysis kernel's own
+    # launch duration from HIP events around it (direct launches, same kernel)
+    f.set_ensemble(torch.zeros(f.sizes["ensemble_elems"], dtype=torch.float32, device="cuda"))
+    f.set_frame(0)
+    per = time_steps(f, y, K, W, per_step=True)
+    f.set_ensemble(torch.zeros(f.sizes["ensemble_elems"], dtype=torch.float32, device="cuda"))
+    f.set_frame(0)
     f.set_schedule(False, sched[1])
-    per = time_steps(f, y, min(K, 200), 5, per_step=True)
+    time_steps(f, y, 0, W)
+    f.set_timing(True)
+    time_steps(f, y, K, 0, offset=W)
+    kt = f.analysis_times()
+    f.set_timing(False)
     f.set_schedule(*sched)
-    kernel_ms = float(np.mean(per))
-    # plain form: one launch per domain, no graph
-    plain_ms = time_steps(f, y, args.plain_steps, 1, plain=True)
+    kernel_ms = float(np.mean(kt))
+    # plain form: one launch per domain, no graph, on the same frames
+    f.set_ensemble(torch.zeros(f.sizes["ensemble_elems"], dtype=torch.float32, device="cuda"))
+    f.set_frame(0)
+    time_steps(f, y, 0, W)
+    plain_ms = time_steps(f, y, args.plain_steps, 0, plain=True, offset=W)
 
     g = f.geometry(0)
     p_list = np.diff(g["obs_off"])
@@ -168,7 +257,7 @@ def main():
     total = sum(fl.values())
     achieved = total / (kernel_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
             "kernel": "k_analysis<float,true>", "kernel_ms": round(kernel_ms, 4),
             "flops_per_launch": total, "flops_breakdown": fl}
 
@@ -177,11 +266,15 @@ def main():
     if args.copies > 1:
         fc = B.Letkf([spec] * args.copies)
         yc = y[:, :].repeat(1, args.copies)
-        msc = time_steps(fc, yc, min(K, 200), 10)
+        msc = time_steps(fc, yc, min(K, 200), W)
         copies = {"instances": args.copies, "ms_per_step": round(msc, 4),
                   "local_analyses_per_s": round(args.copies * n_dom * 1000.0 / msc, 1),
                   "frac_of_fp64_peak": round(args.copies * total / (msc * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
         fc.close()
+
+    grad = None
+    if args.grad_frames > 0:
+        grad = gradient_timing(B, w, bank, seed, y, truth, ij, args.grad_frames)
 
     out = {
         "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": K,
@@ -197,6 +290,8 @@ def main():
         "step_ms_p50": round(float(np.percentile(per, 50)), 4),
         "step_ms_p99": round(float(np.percentile(per, 99)), 4),
         "batched_copies": copies,
+        "filter_check": filt,
+        "gradient": grad,
         "roofline": roof,
     }
     if not args.no_cpu:

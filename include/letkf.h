@@ -210,6 +210,14 @@ int letkf_eigh_spd(const double *A_dev, int32_t m, int32_t batch, double tol,
                    int32_t max_sweeps, double *Q_dev, double *lam_dev, int32_t *sweeps_dev,
                    void *stream);
 
+/* Timing of the analysis kernel: with enable != 0, every letkf_step that
+ * launches directly (schedule without the graph) records a HIP event pair
+ * around its analysis launch on its stream.  letkf_analysis_times waits for
+ * them, writes up to `max` durations (ms) in launch order, sets *count to the
+ * number recorded and clears the record. */
+int letkf_set_timing(letkf_handle *h, int32_t enable);
+int letkf_analysis_times(letkf_handle *h, float *ms, int32_t max, int32_t *count);
+
 /* ---------------------------------------------------------------- adjoint
  * Gradient of a loss of the analysis ensembles with respect to each
  * instance's (rho, r_scale, taper_c): the inflation, the noise scale s of

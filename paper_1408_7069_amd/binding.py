@@ -100,6 +100,8 @@ _SIGS = {
     "letkf_residual_variance": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "letkf_residual_variance_adjoint": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "letkf_adjoint": (C.c_int, [_P, _P, _P, C.c_uint32, _P, _P, _P, _P]),
+    "letkf_set_timing": (C.c_int, [_P, C.c_int32]),
+    "letkf_analysis_times": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int32, _I32P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -344,6 +346,18 @@ class Letkf:
                                   cache_path.encode() if cache_path else None, _stream(stream)),
                "letkf_autotune")
         return self.get_schedule()
+
+    # -- timing
+    def set_timing(self, enable: bool):
+        _check(lib.letkf_set_timing(self._h, int(enable)), "letkf_set_timing")
+
+    def analysis_times(self, max_n: int = 100000) -> np.ndarray:
+        """Durations (ms) of the analysis launches recorded since set_timing."""
+        buf = np.zeros(max_n, dtype=np.float32)
+        n = C.c_int32()
+        _check(lib.letkf_analysis_times(self._h, buf.ctypes.data_as(C.POINTER(C.c_float)), max_n,
+                                        C.byref(n)), "letkf_analysis_times")
+        return buf[:min(n.value, max_n)].copy()
 
     # -- loss and adjoint
     def _check_f64(self, t, n, name):

@@ -225,6 +225,10 @@ struct letkf_handle {
   void *d_xmean = nullptr;
   std::vector<unsigned char> gpargs[2][2];  // graph: rhs args, solve/apply args
   hipGraphNode_t gpnode[2][3] = {};
+  // optional HIP-event timing of the analysis launches of direct steps
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
+  size_t tev_used = 0;
 };
 
 namespace {
@@ -484,6 +488,10 @@ void free_handle(letkf_handle *h) {
                   h->d_prhs, h->d_pi, h->d_xmean};
   for (void *p : ptrs)
     if (p) hipFree(p);
+  for (auto &e : h->tev) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
   delete h;
 }
 
@@ -1074,8 +1082,20 @@ int letkf_step(letkf_handle *h, const void *V_dev, const void *y_dev, void *stre
     rc = graph_step(h, V_dev, y_dev, s);  // analysis + frame advance
     if (rc) return rc;
   } else {
+    std::pair<hipEvent_t, hipEvent_t> *ev = nullptr;
+    if (h->timing) {
+      if (h->tev_used == h->tev.size()) {
+        std::pair<hipEvent_t, hipEvent_t> e;
+        HIPCHK(hipEventCreate(&e.first));
+        HIPCHK(hipEventCreate(&e.second));
+        h->tev.push_back(e);
+      }
+      ev = &h->tev[h->tev_used++];
+      HIPCHK(hipEventRecord(ev->first, s));
+    }
     rc = launch_analysis(h, true, V_dev, y_dev, h->cur, 1 - h->cur, s);
     if (rc) return rc;
+    if (ev) HIPCHK(hipEventRecord(ev->second, s));
     if ((rc = launch_piston_seq(h, {0, 1, 2}, y_dev, h->d_xa[1 - h->cur], s))) return rc;
     HIPCHK(letkf_launch_frame_advance(h->d_frame, s));
   }
@@ -1388,6 +1408,27 @@ int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, u
                                     h->d_slots, h->d_xpbar, h->d_xbbar, h->d_ybar, h->d_dbar,
                                     xbar_dev, h->max_nodes, s));
   HIPCHK(letkf_launch_theta_sum(h->d_dom_base, h->n_inst, h->d_theta, theta_bar_dev, s));
+  return LETKF_OK;
+}
+
+
+int letkf_set_timing(letkf_handle *h, int32_t enable) {
+  if (!h) return fail(LETKF_E_INVAL, "NULL handle");
+  h->timing = enable != 0;
+  h->tev_used = 0;
+  return LETKF_OK;
+}
+
+int letkf_analysis_times(letkf_handle *h, float *ms, int32_t max, int32_t *count) {
+  if (!h || !count || (max > 0 && !ms)) return fail(LETKF_E_INVAL, "NULL argument");
+  hipSetDevice(h->device);
+  const int n = (int)std::min<size_t>(h->tev_used, (size_t)std::max(max, 0));
+  for (int i = 0; i < n; ++i) {
+    HIPCHK(hipEventSynchronize(h->tev[i].second));
+    HIPCHK(hipEventElapsedTime(&ms[i], h->tev[i].first, h->tev[i].second));
+  }
+  *count = (int32_t)h->tev_used;
+  h->tev_used = 0;
   return LETKF_OK;
 }
 
