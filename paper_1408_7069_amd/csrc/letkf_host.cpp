@@ -52,7 +52,7 @@ extern "C" hipError_t letkf_launch_eigh(const double *A, int m, int batch, doubl
 extern "C" size_t letkf_args_size(int fp64);
 extern "C" int letkf_analysis_threads(void);
 extern "C" size_t letkf_analysis_scratch_doubles(void);
-extern "C" size_t letkf_analysis_tb_bytes(void);
+extern "C" size_t letkf_analysis_xch_bytes(void);
 extern "C" const void *letkf_adjoint_kernel(int fp64);
 extern "C" size_t letkf_adjoint_scratch_doubles(void);
 extern "C" size_t letkf_adjoint_args_size(int fp64);
@@ -827,7 +827,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   h->off[5] = (int32_t)o; o = align16(o + 64 * 4);
   h->off[6] = (int32_t)o; o = align16(o + letkf_analysis_scratch_doubles() * 8);
   h->off[7] = (int32_t)o;
-  size_t u = std::max({p4 * kYsStride * T, (size_t)64 * kXsStride * T, letkf_analysis_tb_bytes(),
+  size_t u = std::max({p4 * kYsStride * T, (size_t)64 * kXsStride * T, letkf_analysis_xch_bytes(),
                        (size_t)64 * kYsStride * T});
   h->lds = align16(o + u);
   {  // the adjoint kernel: a larger U area (FP64 64 x 64), Q, a second matrix, scratch

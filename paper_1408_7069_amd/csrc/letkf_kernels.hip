@@ -171,14 +171,11 @@ constexpr int S_WV = 256;      // 64: w
 constexpr int S_LAM = 320;     // 64: lambda^{-3/4}
 constexpr int S_NRM = 384;     // 4 waves x 16: column norms by register slot
 constexpr int S_XAM = 448;     // 64: analysis mean of the owned rows
-constexpr int S_ROT = 512;     // 4 waves x 8 pairs x (c, s, t gamma, pad)
 constexpr int S_MAX = 640;     // 4 waves (+ pad)
 constexpr int S_XN = 648;      // 4 waves x 16: norms in flight between waves
 constexpr int S_B = 712;       // 64: b = Y^T sqrt(g) d
 constexpr int S_LAMV = 776;    // 64: lambda
 constexpr int S_TOTAL = 840;
-constexpr int kTbStride = 9;   // per-wave 64 x 9 transpose buffer for column sums
-constexpr int kTbWave = 64 * kTbStride;
 constexpr int kXchBytes = kWaves * 8 * 64 * 8;   // one block of every wave in flight
 
 // The 64 columns form 8 blocks of 8; wave q holds block q in X[0..7] and
@@ -202,31 +199,52 @@ __device__ inline double sum8_dpp(double v) {
   return v;
 }
 
+// a + b after swapping the upper half-wave of a with the lower half of b
+// (v_permlane32_swap): lanes 0..31 get a_l + a_{l+32}, lanes 32..63 get
+// b_{l-32} + b_l.
+__device__ inline double swap_sum32(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a),
+                                                   (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a),
+                                                   (unsigned)__double2hiint(b), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// The same between neighbouring 16-lane rows (v_permlane16_swap): rows 0 and
+// 2 get a_l + a_{l+16}, rows 1 and 3 get b_{l-16} + b_l.
+__device__ inline double swap_sum16(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a),
+                                                   (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a),
+                                                   (unsigned)__double2hiint(b), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
 // Sums over the 64 rows (lanes) of 8 per-lane values f(j) of this wave:
-// returns the sum of value (lane >> 3) in the 8 lanes of each group.
-template <typename F>
-__device__ inline double group_sums8(F f, double *tb, int r) {
+// returns the sum of value (lane >> 3) in the 8 lanes of each group.  A
+// reduce-scatter in registers: lane bit 5 keeps j or j + 4, bit 4 one of the
+// remaining pairs, bit 3 (lane ^ 8 by DPP row_ror:8) the last one, then the
+// sum over the group of 8 lanes.
+template <typename F> __device__ inline double group_sums8(F f, int r) {
+  double v[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) tb[r * kTbStride + j] = f(j);
-  wave_sync();
-  const int g = r >> 3, r0 = (r & 7) * 8;
-  const double a0 = tb[(r0 + 0) * kTbStride + g] + tb[(r0 + 1) * kTbStride + g];
-  const double a1 = tb[(r0 + 2) * kTbStride + g] + tb[(r0 + 3) * kTbStride + g];
-  const double a2 = tb[(r0 + 4) * kTbStride + g] + tb[(r0 + 5) * kTbStride + g];
-  const double a3 = tb[(r0 + 6) * kTbStride + g] + tb[(r0 + 7) * kTbStride + g];
-  const double s = sum8_dpp((a0 + a1) + (a2 + a3));
-  wave_sync();
-  return s;
+  for (int j = 0; j < 8; ++j) v[j] = f(j);
+  const double w0 = swap_sum32(v[0], v[4]), w1 = swap_sum32(v[1], v[5]);
+  const double w2 = swap_sum32(v[2], v[6]), w3 = swap_sum32(v[3], v[7]);
+  const double u0 = swap_sum16(w0, w2), u1 = swap_sum16(w1, w3);
+  const bool odd = (r & 8) != 0;
+  const double send = odd ? u0 : u1, keep = odd ? u1 : u0;
+  return sum8_dpp(keep + dpp_f64<0x128>(send));
 }
 
 // Column sums of the distributed 64 x 64 block (f applied to each element)
 // written to out[column].
 template <typename F>
-__device__ inline void column_sums(const double X[8], const double Y[8], F f, double *tb,
-                                   double *out, int q, int r) {
-  const double a = group_sums8([&](int j) { return f(X[j]); }, tb, r);
+__device__ inline void column_sums(const double X[8], const double Y[8], F f, double *out, int q,
+                                   int r) {
+  const double a = group_sums8([&](int j) { return f(X[j]); }, r);
   if ((r & 7) == 0) out[pos_x(q, r >> 3)] = a;
-  const double b = group_sums8([&](int j) { return f(Y[j]); }, tb, r);
+  const double b = group_sums8([&](int j) { return f(Y[j]); }, r);
   if ((r & 7) == 0) out[pos_y(q, r >> 3)] = b;
 }
 
@@ -311,47 +329,46 @@ __device__ inline void cholesky_solve_dist(const double X[8], const double Y[8],
 
 // Rotation of one pair: zero the inner product gam of columns with squared
 // norms alp, bet.  t = sign(z) / (|z| + sqrt(1 + z^2)), z = (bet - alp) /
-// (2 gam), taken in FP32 (it only steers convergence); c = (1 + t^2)^{-1/2}
-// in FP64, so (c, s = c t) is orthogonal to working precision.
+// (2 gam), from the hardware reciprocal and square root (t only steers
+// convergence; a large |z| gives t -> 0, the right limit); c = (1 + t^2)^{-1/2}
+// in FP64 from that t, so (c, s = c t) is orthogonal to working precision.
+// Pairs with a relative inner product below 1e-30 are left alone: their
+// rotation would not change a column by one FP64 unit.
 __device__ inline void rotation(double alp, double bet, double gam, double &cs, double &sn,
                                 double &tg, double &off) {
-  cs = 1.0;
-  sn = 0.0;
-  tg = 0.0;
-  off = 0.0;
-  if (gam != 0.0) {
-    off = fabs(gam) * rsq_nr(alp * bet, 1);
-    const float z = (float)(bet - alp) / (float)(2.0 * gam);
-    const float az = fabsf(z);
-    const float tf = copysignf(1.0f / (az + sqrtf(fmaf(az, az, 1.0f))), z);
-    const double t = (double)tf;
-    cs = rsq_nr(fma(t, t, 1.0), 2);
-    sn = cs * t;
-    tg = t * gam;
-  }
+  off = fabs(gam) * rsq_nr(alp * bet, 1);
+  const float z = (float)((bet - alp) * __builtin_amdgcn_rcp(2.0 * gam));
+  const float az = fabsf(z);
+  const float tf =
+      copysignf(__builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(fmaf(az, az, 1.0f))), z);
+  const bool on = off > 1e-30;  // branch-free: the select drops the NaN of gam = 0
+  const double t = on ? (double)tf : 0.0;
+  const double c0 = rsq_nr(fma(t, t, 1.0), 2);
+  cs = on ? c0 : 1.0;
+  sn = cs * t;
+  tg = t * gam;
 }
 
-// One round of 8 pairs (A[j], B[j]) of this wave; norms of A at nA[j], of B
-// at nB[j] (LDS, this wave's slots).  x_p <- c x_p - s x_q, x_q <- s x_p + c x_q.
+// One round of 8 pairs (A[j], B[j]) of this wave; the norms of pair j's
+// columns at nrm[ia], nrm[ib] of group j's lanes (LDS, this wave's slots), read
+// before the inner products are summed so that their latency overlaps.
+// x_p <- c x_p - s x_q, x_q <- s x_p + c x_q.
 template <typename PA, typename PB>
-__device__ inline void jacobi_round(PA pa, PB pb, int ia, int ib, double *nrm, double *rot,
-                                    double *tb, double &maxoff, int r) {
-  const int g = r >> 3;
-  const double gam = group_sums8([&](int j) { return pa(j) * pb(j); }, tb, r);
+__device__ inline void jacobi_round(PA pa, PB pb, int ia, int ib, double *nrm, double &maxoff,
+                                    int r) {
   const double alp = nrm[ia], bet = nrm[ib];
+  const double gam = group_sums8([&](int j) { return pa(j) * pb(j); }, r);
   double cs, sn, tg, off;
   rotation(alp, bet, gam, cs, sn, tg, off);
   maxoff = fmax(maxoff, off);
   if ((r & 7) == 0) {
-    rot[4 * g] = cs;
-    rot[4 * g + 1] = sn;
     nrm[ia] = alp - tg;
     nrm[ib] = bet + tg;
   }
-  wave_sync();
+  // every lane of group j holds pair j's rotation: read it from lane 8 j
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const double c_ = rot[4 * j], s_ = rot[4 * j + 1];
+    const double c_ = bcast_lane(cs, 8 * j), s_ = bcast_lane(sn, 8 * j);
     const double xp = pa(j), xq = pb(j);
     pa(j) = fma(c_, xp, -s_ * xq);
     pb(j) = fma(s_, xp, c_ * xq);
@@ -417,10 +434,9 @@ __host__ __device__ constexpr int intra_slot(int t, int i) {
 // Y[(j + t) mod 8].  Stops after the first sweep whose largest
 // |x_p.x_q| / (|x_p| |x_q|) is <= tol; returns the sweeps used, negative when
 // max_sweeps was reached first.
-__device__ inline int jacobi_dist(double X[8], double Y[8], double *sm, double *tb, double *xch,
+__device__ inline int jacobi_dist(double X[8], double Y[8], double *sm, double *xch,
                                   double tol, int max_sweeps, int q, int r) {
   double *nrm = sm + S_NRM + q * 16;
-  double *rot = sm + S_ROT + q * 32;
   int sweep = 0;
   bool done = false;
   while (!done && sweep < max_sweeps) {
@@ -429,8 +445,8 @@ __device__ inline int jacobi_dist(double X[8], double Y[8], double *sm, double *
     // nearly equal columns (a degenerate cluster) instead of their inner
     // products, stalling convergence.
     {
-      const double a = group_sums8([&](int j) { return X[j] * X[j]; }, tb, r);
-      const double b = group_sums8([&](int j) { return Y[j] * Y[j]; }, tb, r);
+      const double a = group_sums8([&](int j) { return X[j] * X[j]; }, r);
+      const double b = group_sums8([&](int j) { return Y[j] * Y[j]; }, r);
       if ((r & 7) == 0) {
         nrm[r >> 3] = a;
         nrm[8 + (r >> 3)] = b;
@@ -447,14 +463,14 @@ __device__ inline int jacobi_dist(double X[8], double Y[8], double *sm, double *
           [&](int j) -> double & {
             return j < 4 ? X[intra_slot(t, 7 - j)] : Y[intra_slot(t, 7 - (j - 4))];
           },
-          gy + intra_slot(t, gu), gy + intra_slot(t, 7 - gu), nrm, rot, tb, maxoff, r);
+          gy + intra_slot(t, gu), gy + intra_slot(t, 7 - gu), nrm, maxoff, r);
     }
     for (int br = 0; br < 7; ++br) {
 #pragma unroll
       for (int t = 0; t < 8; ++t)
         jacobi_round([&](int j) -> double & { return X[j]; },
-                     [&](int j) -> double & { return Y[(j + t) & 7]; }, g, 8 + ((g + t) & 7), nrm, rot,
-                     tb, maxoff, r);
+                     [&](int j) -> double & { return Y[(j + t) & 7]; }, g, 8 + ((g + t) & 7), nrm,
+                     maxoff, r);
       exchange_blocks(X, Y, sm, xch, q, r);
     }
     ++sweep;
@@ -685,12 +701,11 @@ __device__ __forceinline__ CoreStatus analysis_core(const AnaArgs<T> &A, const D
   // ---- 4./5. FP64 Cholesky, w, one-sided Jacobi ----
   cholesky_dist(X, Y, sm, q, lane);
   cholesky_solve_dist(X, Y, sm, q, lane);
-  double *tb = (double *)U + q * kTbWave;
-  const int sweeps = jacobi_dist(X, Y, sm, tb, (double *)U, A.jtol, A.max_sweeps, q, lane);
+  const int sweeps = jacobi_dist(X, Y, sm, (double *)U, A.jtol, A.max_sweeps, q, lane);
   const bool conv = sweeps > 0;
 
   // ---- 6. lambda and W = sqrt(c) (U Lambda^{-3/4}) (U Lambda^{-3/4})^T ----
-  column_sums(X, Y, [](double v) { return v * v; }, tb, sm + S_LAM, q, lane);
+  column_sums(X, Y, [](double v) { return v * v; }, sm + S_LAM, q, lane);
   __syncthreads();
   const double lam_l = sm[S_LAM + lane];
   const bool lam_ok = __syncthreads_and(isfinite(lam_l) && lam_l > 0.0);
@@ -1404,11 +1419,11 @@ __global__ void k_mean(const InstDesc *insts, const T *x, T *mean) {
 
 // Stand-alone SPD eigensolve with the same distributed Cholesky + Jacobi,
 // one workgroup per matrix.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_eigh_spd(const double *Am, int m, double tol,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_eigh_spd(const double *Am, int m, double tol,
                                                        int max_sweeps, double *Q, double *lam_out,
                                                        int32_t *sweeps_out) {
   __shared__ double smem_s[S_TOTAL];
-  __shared__ double tb_s[kWaves * kTbWave > kXchBytes / 8 ? kWaves * kTbWave : kXchBytes / 8];
+  __shared__ double xch_s[kXchBytes / 8];
   const int tid = threadIdx.x, q = tid >> 6, r = tid & 63;
   const double *Ab = Am + (int64_t)blockIdx.x * m * m;
   double X[8], Y[8];
@@ -1419,10 +1434,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     Y[j] = (r < m && py < m) ? Ab[r * m + py] : (r == py ? 1.0 : 0.0);
   }
   double *sm = smem_s;
-  double *tb = tb_s + q * kTbWave;
   cholesky_dist(X, Y, sm, q, r);
-  const int sw = jacobi_dist(X, Y, sm, tb, tb_s, tol, max_sweeps, q, r);
-  column_sums(X, Y, [](double v) { return v * v; }, tb, sm + S_LAM, q, r);
+  const int sw = jacobi_dist(X, Y, sm, xch_s, tol, max_sweeps, q, r);
+  column_sums(X, Y, [](double v) { return v * v; }, sm + S_LAM, q, r);
   __syncthreads();
   if (r < m) {
     double *Qb = Q + (int64_t)blockIdx.x * m * m;
@@ -1472,8 +1486,8 @@ extern "C" int letkf_analysis_threads(void) { return kThreads; }
 
 extern "C" size_t letkf_analysis_scratch_doubles(void) { return S_TOTAL; }
 
-extern "C" size_t letkf_analysis_tb_bytes(void) {
-  return (size_t)kWaves * kTbWave * 8 > (size_t)kXchBytes ? (size_t)kWaves * kTbWave * 8 : (size_t)kXchBytes;
+extern "C" size_t letkf_analysis_xch_bytes(void) {
+  return (size_t)kXchBytes;
 }
 
 extern "C" hipError_t letkf_launch_forecast(int fp64, const InstDesc *insts, int n_inst,
