@@ -90,8 +90,9 @@ typedef struct letkf_config {
   uint64_t seed;               /* Philox4x32-10 key for the bank draws             */
   int32_t precision;           /* LETKF_FP32 or LETKF_FP64 (same for all instances) */
   double jacobi_tol;           /* stop after a sweep whose largest relative off-
-                                  diagonal measure is <= tol; 0 = 1e-5 (FP32),
-                                  1e-10 (FP64)                                     */
+                                  diagonal measure is <= tol; 0 = 1e-4 (FP32:
+                                  W then within ~5e-6 relative, below FP32
+                                  state rounding), 1e-10 (FP64)                    */
   int32_t max_sweeps;          /* 0 = 30                                           */
   int32_t piston_removal;      /* 1: after the gather, remove one piston per domain
                                   fitted by least squares to the slopes of the
@@ -250,8 +251,11 @@ int letkf_residual_variance_adjoint(letkf_handle *h, const void *xa_dev, const v
  *                    instance i through this frame.
  * Deterministic: slope adjoints of overlapping observation regions are summed
  * in a fixed order.  A domain whose analysis kept its forecast (non-finite
- * input or no convergence) is differentiated as the identity.  Returns
- * LETKF_E_INVAL when the device cannot give the adjoint kernel its LDS. */
+ * input or no convergence) is differentiated as the identity.  The adjoint
+ * passes through the eigenvectors themselves, so in FP32 mode its recompute
+ * runs the Jacobi to min(jacobi_tol, 1e-6) (the forward's transform W only
+ * needs the looser default).  Returns LETKF_E_INVAL when the device cannot
+ * give the adjoint kernel its LDS. */
 int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, uint32_t frame,
                   const void *y_dev, void *xbar_dev, double *theta_bar_dev, void *stream);
 

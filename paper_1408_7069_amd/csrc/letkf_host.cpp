@@ -726,7 +726,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   h->fp64 = cfgs[0].precision == LETKF_FP64;
   h->esize = h->fp64 ? 8 : 4;
   h->n_inst = n_instances;
-  h->jtol = cfgs[0].jacobi_tol > 0 ? cfgs[0].jacobi_tol : (h->fp64 ? 1e-10 : 1e-5);
+  h->jtol = cfgs[0].jacobi_tol > 0 ? cfgs[0].jacobi_tol : (h->fp64 ? 1e-10 : 1e-4);
   h->max_sweeps = cfgs[0].max_sweeps > 0 ? cfgs[0].max_sweeps : 30;
   h->geom.resize(n_instances);
   std::vector<int32_t> patch, obs_sub, node_ij, subap_nodes;
@@ -1368,6 +1368,9 @@ static AdjArgsHost<T> make_adj_args(letkf_handle *h, const void *xa_prev, const 
   D.F.x_out = nullptr;
   D.F.x_mean = nullptr;
   D.F.xcd_order = 0;
+  // the adjoint goes through the eigenvectors themselves: converge them further
+  // than the forward's transform needs
+  D.F.jtol = h->fp64 ? h->jtol : std::min(h->jtol, 1e-6);
   D.F.frame = nullptr;
   D.xbar = (const T *)xbar;
   D.xpbar = (T *)h->d_xpbar;

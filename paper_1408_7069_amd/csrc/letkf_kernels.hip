@@ -184,9 +184,10 @@ __device__ inline int pos_x(int q, int j) { return 8 * q + j; }
 __device__ inline int pos_y(int q, int j) { return 56 - 8 * q + j; }
 __device__ inline int block_owner(int b) { return b < 4 ? b : 7 - b; }
 
+// Lane permutation within 16-lane rows (every source lane valid).
 template <int CTRL> __device__ inline double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
@@ -336,7 +337,7 @@ __device__ inline void cholesky_solve_dist(const double X[8], const double Y[8],
 // rotation would not change a column by one FP64 unit.
 __device__ inline void rotation(double alp, double bet, double gam, double &cs, double &sn,
                                 double &tg, double &off) {
-  off = fabs(gam) * rsq_nr(alp * bet, 1);
+  off = fabs(gam) * rsq_nr(alp * bet, 0);  // a convergence measure: the estimate suffices
   const float z = (float)((bet - alp) * __builtin_amdgcn_rcp(2.0 * gam));
   const float az = fabsf(z);
   const float tf =
