@@ -249,83 +249,83 @@ __device__ inline void column_sums(const double X[8], const double Y[8], F f, do
   if ((r & 7) == 0) out[pos_y(q, r >> 3)] = b;
 }
 
-// Right-looking Cholesky of the distributed SPD matrix (in place: column k of
-// L in its slot, zero above the diagonal); 1/L_kk into sm[S_INVD].  The wave
-// holding column k publishes it (updated) in LDS before step k; at step k
-// every wave forms L's column k from it and updates its columns > k.  All
-// register choices are selects on wave-uniform conditions.
-__device__ inline void cholesky_dist(double X[8], double Y[8], double *sm, int q, int r) {
-  if (q == 0) sm[S_COL + r] = X[0];
-  for (int k = 0; k < 64; ++k) {
-    __syncthreads();
-    const double *raw = sm + S_COL + (k & 1) * 64;
-    double *nxt = sm + S_COL + ((k + 1) & 1) * 64;
-    const double lkk = sqrt(raw[k]);
-    const double il = 1.0 / lkk;
-    const double lr = r > k ? raw[r] * il : 0.0;
-    const double own = r > k ? lr : (r == k ? lkk : 0.0);
-    if (q == 0 && r == 0) sm[S_INVD + k] = il;
-    double pub = 0.0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int px = pos_x(q, j), py = pos_y(q, j);
-      const double fx = px > k ? raw[px] * il : 0.0;
-      const double fy = py > k ? raw[py] * il : 0.0;
-      X[j] = px == k ? own : fma(-lr, fx, X[j]);
-      Y[j] = py == k ? own : fma(-lr, fy, Y[j]);
-      pub = px == k + 1 ? X[j] : pub;
-      pub = py == k + 1 ? Y[j] : pub;
-    }
-    if (k + 1 < 64 && q == block_owner((k + 1) >> 3)) nxt[r] = pub;
-  }
-  __syncthreads();
-}
+constexpr int kLaStride = 65;  // FP64 64 x 64 matrix in LDS (row stride)
 
-// Forward substitution over one block of 8 columns (k0..k0+7 = cols[0..7]).
-__device__ inline void fwd_block(int k0, const double cols[8], double *sm, int r) {
-  double rv = sm[S_VEC + r];
-#pragma unroll
-  for (int jj = 0; jj < 8; ++jj) {
-    const int k = k0 + jj;
-    const double zk = bcast_lane(rv, k) * sm[S_INVD + k];
-    rv = r == k ? zk : (r > k ? fma(-cols[jj], zk, rv) : rv);
-  }
-  sm[S_VEC + r] = rv;
-}
-
-// Backward substitution over one block of 8 columns (descending).
-__device__ inline void bwd_block(int k0, const double cols[8], double *sm, int r) {
-  double wl = sm[S_WV + r];
-  const double z = sm[S_VEC + r];
-#pragma unroll
-  for (int jj = 7; jj >= 0; --jj) {
-    const int k = k0 + jj;
-    const double s = wave_sum(r > k ? cols[jj] * wl : 0.0);
-    const double wk = (bcast_lane(z, k) - s) * sm[S_INVD + k];
-    wl = r == k ? wk : wl;
-  }
-  sm[S_WV + r] = wl;
-}
-
-// Solve L L^T w = b (b in sm[S_VEC] on entry, w in sm[S_WV] on exit).
-__device__ inline void cholesky_solve_dist(const double X[8], const double Y[8], double *sm, int q,
-                                           int r) {
+// Right-looking blocked Cholesky A = L L^T of the SPD matrix in LDS (row-major,
+// stride kLaStride; the lower triangle is read).  Each panel of 8 columns is
+// factored by wave 0 in registers (lane = row; pivots and multipliers taken
+// from their lanes with readlane, 1/sqrt by a hardware estimate and two
+// Newton steps); the trailing lower tiles are then updated by all four waves on
+// the FP64 matrix cores (16x16x4, K = 8).  On return the LDS matrix is L
+// (zero above the diagonal) and sm[S_INVD + k] = 1 / L_kk.
+__device__ inline void cholesky_lds(double *La, double *sm, int q, int lane) {
   for (int kb = 0; kb < 8; ++kb) {
-    if (q == block_owner(kb)) {
-      if (kb < 4) fwd_block(8 * kb, X, sm, r);
-      else fwd_block(8 * kb, Y, sm, r);
+    const int k0 = 8 * kb;
+    if (q == 0) {
+      double v[8];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) v[jj] = lane >= k0 ? La[lane * kLaStride + k0 + jj] : 0.0;
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const int k = k0 + jj;
+        const double d = bcast_lane(v[jj], k);
+        const double il = rsq_nr(d, 2);
+        v[jj] = lane > k ? v[jj] * il : (lane == k ? d * il : 0.0);
+        if (lane == 0) sm[S_INVD + k] = il;
+#pragma unroll
+        for (int j2 = jj + 1; j2 < 8; ++j2) v[j2] = fma(-v[jj], bcast_lane(v[jj], k0 + j2), v[j2]);
+      }
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) La[lane * kLaStride + k0 + jj] = v[jj];
     }
     __syncthreads();
-  }
-  if (q == 0) sm[S_WV + r] = 0.0;
-  __syncthreads();
-  for (int kb = 7; kb >= 0; --kb) {
-    if (q == block_owner(kb)) {
-      if (kb < 4) bwd_block(8 * kb, X, sm, r);
-      else bwd_block(8 * kb, Y, sm, r);
-    }
+    if (kb == 7) break;
+    // A[i][j] -= sum over the panel of L[i][k] L[j][k] for i, j >= s: the lower
+    // 16x16 tiles that reach past s, dealt to the waves in turn
+    const int s = k0 + 8, t0 = s >> 4;
+    const int c16 = lane & 15, k4 = lane >> 4;
+    int t = 0;
+    for (int I = t0; I < 4; ++I)
+      for (int J = t0; J <= I; ++J, ++t) {
+        if ((t & 3) != q) continue;
+        f64x4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc[r] = La[(16 * I + Mfma<double>::row(lane, r)) * kLaStride + 16 * J + c16];
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+          const int kc = k0 + 4 * kk + k4;
+          acc = Mfma<double>::mac(-La[(16 * I + c16) * kLaStride + kc], La[(16 * J + c16) * kLaStride + kc],
+                                  acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * I + Mfma<double>::row(lane, r), j = 16 * J + c16;
+          if (i >= s && j >= s) La[i * kLaStride + j] = acc[r];
+        }
+      }
     __syncthreads();
   }
+}
+
+// Solve L L^T w = b with the factor in LDS (b in sm[S_VEC], w into sm[S_WV]):
+// column-oriented forward and backward substitution in wave 0, lane = row.
+__device__ inline void cholesky_solve_lds(const double *La, double *sm, int q, int lane) {
+  if (q != 0) return;
+  double z = sm[S_VEC + lane];
+#pragma unroll 8
+  for (int k = 0; k < 64; ++k) {
+    const double zk = bcast_lane(z, k) * sm[S_INVD + k];
+    const double l = La[lane * kLaStride + k];
+    z = lane == k ? zk : (lane > k ? fma(-l, zk, z) : z);
+  }
+#pragma unroll 8
+  for (int k = 63; k >= 0; --k) {
+    const double wk = bcast_lane(z, k) * sm[S_INVD + k];
+    const double l = La[k * kLaStride + lane];
+    z = lane == k ? wk : (lane < k ? fma(-l, wk, z) : z);
+  }
+  sm[S_WV + lane] = z;
 }
 
 // Rotation of one pair: zero the inner product gam of columns with squared
@@ -485,14 +485,12 @@ __device__ inline int jacobi_dist(double X[8], double Y[8], double *sm, double *
   return done ? sweep : -sweep;
 }
 
-// Load the distributed matrix M (row-major, leading dimension ld) + c I.
-template <typename T>
-__device__ inline void load_dist(const T *M, int ld, double c, double X[8], double Y[8], int q, int r) {
+// Load the columns this wave holds of the FP64 matrix in LDS (lane = row).
+__device__ inline void load_dist(const double *M, double X[8], double Y[8], int q, int r) {
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int px = pos_x(q, j), py = pos_y(q, j);
-    X[j] = (double)M[r * ld + px] + (r == px ? c : 0.0);
-    Y[j] = (double)M[r * ld + py] + (r == py ? c : 0.0);
+    X[j] = M[r * kLaStride + pos_x(q, j)];
+    Y[j] = M[r * kLaStride + pos_y(q, j)];
   }
 }
 
@@ -549,6 +547,27 @@ __device__ inline void syrk_store(const typename Mfma<T>::V acc[3], T *out, int 
       const T v = alpha * acc[u][r];
       out[i * ld + j] = v;
       if (I != J) out[j * ld + i] = v;
+    }
+  }
+}
+
+// The same product into the FP64 LDS matrix (stride kLaStride) plus c I.
+template <typename T>
+__device__ inline void syrk_store_f64(const typename Mfma<T>::V acc[3], double *out, double c, int q,
+                                      int lane) {
+  const int c16 = lane & 15;
+  const int nt = q < 2 ? 3 : 2;
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    if (u >= nt) continue;
+    int I, J;
+    tile_of(q + 4 * u, I, J);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + Mfma<T>::row(lane, r), j = 16 * J + c16;
+      const double v = (double)acc[u][r] + (i == j ? c : 0.0);
+      out[i * kLaStride + j] = v;
+      if (I != J) out[j * kLaStride + i] = v;
     }
   }
 }
@@ -692,16 +711,16 @@ __device__ __forceinline__ CoreStatus analysis_core(const AnaArgs<T> &A, const D
   typename Mfma<T>::V acc[3];
   syrk_share<T>(ys, kYsStride, p4 / 4, acc, q, lane);
   __syncthreads();
-  T *gram = (T *)U;  // [64][kXsStride]
-  syrk_store<T>(acc, gram, kXsStride, (T)1, q, lane);
-  __syncthreads();
   const double c = (double)(m - 1) / in.rho;
-  load_dist(gram, kXsStride, c, X, Y, q, lane);
+  double *La = (double *)U;  // A~ = c I + Y^T Y in FP64, then its Cholesky factor
+  syrk_store_f64<T>(acc, La, c, q, lane);
   __syncthreads();
 
   // ---- 4./5. FP64 Cholesky, w, one-sided Jacobi ----
-  cholesky_dist(X, Y, sm, q, lane);
-  cholesky_solve_dist(X, Y, sm, q, lane);
+  cholesky_lds(La, sm, q, lane);
+  cholesky_solve_lds(La, sm, q, lane);
+  load_dist(La, X, Y, q, lane);
+  __syncthreads();
   const int sweeps = jacobi_dist(X, Y, sm, (double *)U, A.jtol, A.max_sweeps, q, lane);
   const bool conv = sweeps > 0;
 
@@ -1424,19 +1443,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                                                        int max_sweeps, double *Q, double *lam_out,
                                                        int32_t *sweeps_out) {
   __shared__ double smem_s[S_TOTAL];
-  __shared__ double xch_s[kXchBytes / 8];
+  __shared__ double la_s[64 * kLaStride];  // the matrix, then the exchange area
   const int tid = threadIdx.x, q = tid >> 6, r = tid & 63;
   const double *Ab = Am + (int64_t)blockIdx.x * m * m;
-  double X[8], Y[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int px = pos_x(q, j), py = pos_y(q, j);
-    X[j] = (r < m && px < m) ? Ab[r * m + px] : (r == px ? 1.0 : 0.0);
-    Y[j] = (r < m && py < m) ? Ab[r * m + py] : (r == py ? 1.0 : 0.0);
+  for (int e = tid; e < 64 * 64; e += kThreads) {
+    const int i = e >> 6, j = e & 63;
+    la_s[i * kLaStride + j] = (i < m && j < m) ? Ab[i * m + j] : (i == j ? 1.0 : 0.0);
   }
+  __syncthreads();
+  double X[8], Y[8];
   double *sm = smem_s;
-  cholesky_dist(X, Y, sm, q, r);
-  const int sw = jacobi_dist(X, Y, sm, xch_s, tol, max_sweeps, q, r);
+  cholesky_lds(la_s, sm, q, r);
+  load_dist(la_s, X, Y, q, r);
+  __syncthreads();
+  const int sw = jacobi_dist(X, Y, sm, la_s, tol, max_sweeps, q, r);
   column_sums(X, Y, [](double v) { return v * v; }, sm + S_LAM, q, r);
   __syncthreads();
   if (r < m) {
