@@ -73,6 +73,9 @@ extern "C" hipError_t letkf_launch_resvar_adjoint(int fp64, const InstDesc *inst
                                                   void *xbar, int max_nodes, hipStream_t s);
 extern "C" const void *letkf_piston_kernel(int fp64, int which);
 extern "C" size_t letkf_piston_args_size(int fp64);
+extern "C" const void *letkf_piston_finish_kernel(int fp64);
+extern "C" hipError_t letkf_launch_piston_finish(int fp64, const void *args, int n_items,
+                                                 uint32_t *frame, hipStream_t s);
 extern "C" void letkf_piston_grid(int which, int n_items, int n_inst, int max_nodes, int64_t max_elems,
                                   int *gx, int *gy);
 extern "C" hipError_t letkf_launch_piston(int fp64, int which, const void *args, int gx, int gy,
@@ -579,6 +582,21 @@ int launch_piston_seq(letkf_handle *h, std::initializer_list<int> which, const v
   return LETKF_OK;
 }
 
+// The end of a frame after the analysis: the piston fit (right-hand sides,
+// then pistons applied per domain) when enabled, and the frame counter of the
+// bank draws when `frame` is given (folded into the last piston kernel).
+int launch_frame_tail(letkf_handle *h, const void *y, void *x, uint32_t *frame, hipStream_t s) {
+  if (!h->any_piston) {
+    if (frame) HIPCHK(letkf_launch_frame_advance(frame, s));
+    return LETKF_OK;
+  }
+  int rc = launch_piston_seq(h, {0}, y, x, s);
+  if (rc) return rc;
+  std::vector<unsigned char> blob = piston_blob(h, y, x);
+  HIPCHK(letkf_launch_piston_finish(h->fp64, blob.data(), (int)h->items.size(), frame, s));
+  return LETKF_OK;
+}
+
 int grid_for(const letkf_handle *h) {
   const int n = (int)h->items.size();
   return h->xcd_order ? 8 * ((n + 7) / 8) : n;
@@ -647,28 +665,34 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
     HIPCHK(hipGraphAddKernelNode(&h->gnode[p], h->graph[p], nullptr, 0, &kp));
     hipGraphNode_t last = h->gnode[p];
     if (h->any_piston) {
+      // piston right-hand sides, then pistons applied and the frame counter
       h->gpargs[p][0] = prhs;
       h->gpargs[p][1] = pfix;
-      void *s0[1], *s1[1], *s2[1];
+      void *s0[1];
       hipKernelNodeParams q0 = piston_params(0, h->gpargs[p][0], s0);
-      hipKernelNodeParams q1 = piston_params(1, h->gpargs[p][1], s1);
-      hipKernelNodeParams q2 = piston_params(2, h->gpargs[p][1], s2);
       HIPCHK(hipGraphAddKernelNode(&h->gpnode[p][0], h->graph[p], &last, 1, &q0));
+      hipKernelNodeParams q1{};
+      void *s1[] = {h->gpargs[p][1].data(), &h->d_frame};
+      q1.blockDim = dim3(letkf_analysis_threads());
+      q1.gridDim = dim3((unsigned)h->items.size());
+      q1.func = (void *)letkf_piston_finish_kernel(h->fp64);
+      q1.kernelParams = s1;
+      q1.extra = nullptr;
+      q1.sharedMemBytes = 0;
       HIPCHK(hipGraphAddKernelNode(&h->gpnode[p][1], h->graph[p], &h->gpnode[p][0], 1, &q1));
-      HIPCHK(hipGraphAddKernelNode(&h->gpnode[p][2], h->graph[p], &h->gpnode[p][1], 1, &q2));
-      last = h->gpnode[p][2];
+    } else {
+      // the frame counter of the bank draws
+      hipKernelNodeParams kp2{};
+      void *a2[] = {&h->d_frame};
+      kp2.blockDim = dim3(64);
+      kp2.gridDim = dim3(1);
+      kp2.func = (void *)letkf_frame_advance_kernel();
+      kp2.kernelParams = a2;
+      kp2.extra = nullptr;
+      kp2.sharedMemBytes = 0;
+      hipGraphNode_t adv;
+      HIPCHK(hipGraphAddKernelNode(&adv, h->graph[p], &last, 1, &kp2));
     }
-    // then the frame counter of the bank draws
-    hipKernelNodeParams kp2{};
-    void *a2[] = {&h->d_frame};
-    kp2.blockDim = dim3(64);
-    kp2.gridDim = dim3(1);
-    kp2.func = (void *)letkf_frame_advance_kernel();
-    kp2.kernelParams = a2;
-    kp2.extra = nullptr;
-    kp2.sharedMemBytes = 0;
-    hipGraphNode_t adv;
-    HIPCHK(hipGraphAddKernelNode(&adv, h->graph[p], &last, 1, &kp2));
     HIPCHK(hipGraphInstantiate(&h->gexec[p], h->graph[p], nullptr, nullptr, 0));
   } else {
     if (args != h->gargs[p]) {
@@ -1067,7 +1091,7 @@ int letkf_analyse(letkf_handle *h, const void *y_dev, void *stream) {
   hipSetDevice(h->device);
   int rc = launch_analysis(h, false, nullptr, y_dev, h->cur, h->cur, (hipStream_t)stream);
   if (rc) return rc;
-  if ((rc = launch_piston_seq(h, {0, 1, 2}, y_dev, h->d_xa[h->cur], (hipStream_t)stream))) return rc;
+  if ((rc = launch_frame_tail(h, y_dev, h->d_xa[h->cur], nullptr, (hipStream_t)stream))) return rc;
   h->have_xb = false;
   return LETKF_OK;
 }
@@ -1096,8 +1120,7 @@ int letkf_step(letkf_handle *h, const void *V_dev, const void *y_dev, void *stre
     rc = launch_analysis(h, true, V_dev, y_dev, h->cur, 1 - h->cur, s);
     if (rc) return rc;
     if (ev) HIPCHK(hipEventRecord(ev->second, s));
-    if ((rc = launch_piston_seq(h, {0, 1, 2}, y_dev, h->d_xa[1 - h->cur], s))) return rc;
-    HIPCHK(letkf_launch_frame_advance(h->d_frame, s));
+    if ((rc = launch_frame_tail(h, y_dev, h->d_xa[1 - h->cur], h->d_frame, s))) return rc;
   }
   h->cur = 1 - h->cur;
   h->have_xb = false;
@@ -1124,8 +1147,7 @@ int letkf_step_plain(letkf_handle *h, const void *V_dev, const void *y_dev, void
       HIPCHK(letkf_launch_analysis_f32(&A, 1, 1, h->lds, s));
     }
   }
-  if ((rc = launch_piston_seq(h, {0, 1, 2}, y_dev, h->d_xa[1 - h->cur], s))) return rc;
-  HIPCHK(letkf_launch_frame_advance(h->d_frame, s));
+  if ((rc = launch_frame_tail(h, y_dev, h->d_xa[1 - h->cur], h->d_frame, s))) return rc;
   h->cur = 1 - h->cur;
   h->have_xb = false;
   return LETKF_OK;

@@ -1343,6 +1343,35 @@ template <typename T> __global__ void k_piston_apply(const PistonArgs<T> P) {
   }
 }
 
+// pi of each domain (a row of M^+ times rhs) added to every member of its
+// owned nodes: one workgroup per item.  Item 0 also advances the frame counter
+// of the bank draws when `frame` is given (the last step of the frame).
+template <typename T> __global__ void k_piston_finish(const PistonArgs<T> P, uint32_t *frame) {
+  __shared__ double pi_s;
+  const int item = blockIdx.x;
+  const int tid = threadIdx.x, q = tid >> 6, lane = tid & 63;
+  if (frame && item == 0 && tid == 0) *frame += 1u;
+  const DomItem it = P.items[item];
+  const InstDesc in = P.inst[it.inst];
+  if (!in.piston) return;
+  if (q == 0) {
+    const int b0 = P.dom_base[it.inst], nd = P.dom_base[it.inst + 1] - b0;
+    const double *row = P.minv + P.minv_off[it.inst] + (int64_t)(item - b0) * nd;
+    double v = 0.0;
+    for (int e = lane; e < nd; e += 64) v = fma(row[e], P.rhs[b0 + e], v);
+    v = wave_sum(v);
+    if (lane == 0) pi_s = v;
+  }
+  __syncthreads();
+  const double pv = pi_s;
+  const int m = in.m;
+  for (int e = tid; e < it.n_own * m; e += kThreads) {
+    const int i = e / m, j = e - i * m;
+    const int64_t x = in.x_off + (int64_t)P.patch_node[it.patch_off + i] * m + j;
+    P.x[x] = (T)((double)P.x[x] + pv);
+  }
+}
+
 // Adjoint: rhs[item] = sum over the owned nodes and members of Z_bar.
 template <typename T> __global__ void k_piston_adj_sum(const PistonArgs<T> P) {
   const int item = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6);
@@ -1658,6 +1687,16 @@ extern "C" const void *letkf_piston_kernel(int fp64, int which) {
                       (const void *)k_piston_apply<float>, (const void *)k_piston_adj_sum<float>,
                       (const void *)k_piston_adj_apply<float>};
   return k[which];
+}
+
+extern "C" const void *letkf_piston_finish_kernel(int fp64) {
+  return fp64 ? (const void *)k_piston_finish<double> : (const void *)k_piston_finish<float>;
+}
+
+extern "C" hipError_t letkf_launch_piston_finish(int fp64, const void *args, int n_items,
+                                                 uint32_t *frame, hipStream_t s) {
+  void *kargs[] = {(void *)args, (void *)&frame};
+  return hipLaunchKernel(letkf_piston_finish_kernel(fp64), dim3(n_items), dim3(kThreads), kargs, 0, s);
 }
 
 extern "C" size_t letkf_piston_args_size(int fp64) {
