@@ -296,7 +296,7 @@ def main():
     }
     if not args.no_cpu:
         nrng = np.random.default_rng(w.seed + 1)
-        T = min(frames, 40)
+        T = min(frames, 400)   # more frames than the time budget reaches
         out["cpu_baseline"] = cpu_baseline(w, bank, seed, truth[:T],
                                            wl.gaussian_noise((T, f.sizes["n_slopes"]), w.sigma, nrng))
     print(json.dumps(out))
