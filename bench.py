@@ -139,6 +139,45 @@ def cpu_baseline(w, bank, seed, truth, sigma_noise, budget_s=12.0):
                       f"NumPy FP64 with LAPACK eigh, one thread, {dt:.1f} s"}
 
 
+def other_workloads(B, wl, K, W):
+    """Frame time of the other workloads (graph replay, bank noise, piston
+    removal on): the 8x8 FP64 case, the 40x40 frozen-flow case and 64
+    independent instances in one launch."""
+    import torch
+    out = {}
+    for idx, label in ((0, "8x8 square m=20 FP64"), (1, "40x40 eps0.14 m=50 frozen flow"),
+                       (3, "64 instances N~U{16..48}, m in {32,48,64}")):
+        ws = wl.workloads(idx)
+        rng = np.random.default_rng(ws[0].seed)
+        specs, ys = [], []
+        frames = K + W
+        for i, w in enumerate(ws):
+            bank = wl.bank_for(w, rng, n_screens=8)
+            specs.append(B.InstanceSpec(n_sub=w.n_sub, m=w.m, domain_size=w.b, halo=w.h,
+                                        obscuration=0.0 if w.obscuration is None else w.obscuration,
+                                        mask=np.ones((w.n_sub, w.n_sub), bool) if w.obscuration is None else None,
+                                        rho=w.rho, r_sigma2=w.sigma ** 2, ar_coeff=w.a, noise_bank=bank,
+                                        seed=0x5EED0000 + w.seed + i,
+                                        precision=B.FP64 if w.precision == "fp64" else B.FP32, piston=True))
+        f = B.Letkf(specs)
+        dt = torch.float64 if f.fp64 else torch.float32
+        y = torch.empty((frames, f.sizes["n_slopes"]), dtype=dt, device="cuda")
+        phase = torch.empty(f.sizes["n_nodes"], dtype=dt, device="cuda")
+        truths = [wl.truth_for(w, rng, frames=frames) for w in ws]
+        node_ij = [f.geometry(i)["node_ij"] for i in range(len(ws))]
+        for k in range(frames):
+            ph = np.concatenate([truths[i][k][node_ij[i][:, 0], node_ij[i][:, 1]] for i in range(len(ws))])
+            phase.copy_(torch.from_numpy(ph.astype(np.float64 if f.fp64 else np.float32)))
+            f.slopes(phase, out=y[k])
+            y[k] += torch.randn(f.sizes["n_slopes"], dtype=dt, device="cuda") * float(ws[0].sigma)
+        ms = time_steps(f, y, K, W)
+        out[label] = {"instances": len(ws), "domains": int(f.sizes["n_domains"]),
+                      "ms_per_step": round(ms, 4), "frames_per_s": round(1000.0 / ms, 1),
+                      "local_analyses_per_s": round(f.sizes["n_domains"] * 1000.0 / ms, 1)}
+        f.close()
+    return out
+
+
 def gradient_timing(B, w, bank, seed, y, truth, ij, T):
     """The tuning run's gradient: T frames of the 80x80 workload with a
     Gaspari-Cohn taper (c = 2 pitches), loss = mean residual variance, gradient
@@ -180,6 +219,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: timed steps only")
     ap.add_argument("--grad-frames", type=int, default=200, help="frames of the gradient timing (0 = skip)")
+    ap.add_argument("--other-workloads", type=int, default=1, help="also time the 8x8, 40x40 and 64-instance workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the frame is not sharded "
@@ -272,6 +312,8 @@ def main():
                   "frac_of_fp64_peak": round(args.copies * total / (msc * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
         fc.close()
 
+    others = other_workloads(B, wl, 100, 20) if args.other_workloads else None
+
     grad = None
     if args.grad_frames > 0:
         grad = gradient_timing(B, w, bank, seed, y, truth, ij, args.grad_frames)
@@ -291,6 +333,7 @@ def main():
         "step_ms_p99": round(float(np.percentile(per, 99)), 4),
         "batched_copies": copies,
         "filter_check": filt,
+        "other_workloads": others,
         "gradient": grad,
         "roofline": roof,
     }
