@@ -171,7 +171,7 @@ constexpr int S_WV = 256;      // 64: w
 constexpr int S_LAM = 320;     // 64: lambda^{-3/4}
 constexpr int S_NRM = 384;     // 4 waves x 16: column norms by register slot
 constexpr int S_XAM = 448;     // 64: analysis mean of the owned rows
-constexpr int S_MAX = 640;     // 4 waves (+ pad)
+constexpr int S_MAX = 640;     // 2 x 4 waves: last round above tol, by block-move parity
 constexpr int S_XN = 648;      // 4 waves x 16: norms in flight between waves
 constexpr int S_B = 712;       // 64: b = Y^T sqrt(g) d
 constexpr int S_LAMV = 776;    // 64: lambda
@@ -355,13 +355,13 @@ __device__ inline void rotation(double alp, double bet, double gam, double &cs, 
 // before the inner products are summed so that their latency overlaps.
 // x_p <- c x_p - s x_q, x_q <- s x_p + c x_q.
 template <typename PA, typename PB>
-__device__ inline void jacobi_round(PA pa, PB pb, int ia, int ib, double *nrm, double &maxoff,
-                                    int r) {
+__device__ inline void jacobi_round(PA pa, PB pb, int ia, int ib, double *nrm, double tol, int rid,
+                                    int &hi, int r) {
   const double alp = nrm[ia], bet = nrm[ib];
   const double gam = group_sums8([&](int j) { return pa(j) * pb(j); }, r);
   double cs, sn, tg, off;
   rotation(alp, bet, gam, cs, sn, tg, off);
-  maxoff = fmax(maxoff, off);
+  hi = off > tol ? rid : hi;
   if ((r & 7) == 0) {
     nrm[ia] = alp - tg;
     nrm[ib] = bet + tg;
@@ -384,7 +384,7 @@ __device__ inline void jacobi_round(PA pa, PB pb, int ia, int ib, double *nrm, d
 __device__ inline void exchange_blocks(double X[8], double Y[8], double *sm, double *xch, int q,
                                        int r) {
   double *nrm = sm + S_NRM + q * 16;
-  __syncthreads();  // the exchange area overlaps the other waves' round buffers
+  // (the previous move ended with a barrier after its last read of the area)
   // phase 1: every X, and the norms of both blocks
 #pragma unroll
   for (int j = 0; j < 8; ++j) xch[(q * 8 + j) * 64 + r] = X[j];
@@ -430,17 +430,30 @@ __host__ __device__ constexpr int intra_slot(int t, int i) {
   return i == 0 ? 0 : ((i - 1 - t + 70) % 7) + 1;
 }
 
+__device__ inline int wave_max_int(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 // One-sided Jacobi on the distributed factor: per sweep, the 7 rounds of
 // pairs inside each block, then 7 block-rounds of 8 rounds pairing X[j] with
-// Y[(j + t) mod 8].  Stops after the first sweep whose largest
-// |x_p.x_q| / (|x_p| |x_q|) is <= tol; returns the sweeps used, negative when
-// max_sweeps was reached first.
+// Y[(j + t) mod 8].  The pairing repeats every 63 rounds, so any 63
+// consecutive rounds meet every pair once: the rotations stop at the first
+// block move after which 63 rounds have passed without a pair above tol
+// (relative inner product |x_p.x_q| / (|x_p| |x_q|) measured before its
+// rotation).  The blocks may then sit away from their home slots, which only
+// relabels the eigenpairs; with `home` the remaining block moves of the sweep
+// bring every block back (column k at slot k again).  Returns the sweeps
+// begun, negative when max_sweeps sweeps did not converge.
 __device__ inline int jacobi_dist(double X[8], double Y[8], double *sm, double *xch,
-                                  double tol, int max_sweeps, int q, int r) {
+                                  double tol, int max_sweeps, bool home, int q, int r) {
   double *nrm = sm + S_NRM + q * 16;
-  int sweep = 0;
+  const int g = r >> 3, gu = g & 3, gy = g < 4 ? 0 : 8;
+  int rounds = 0, hi = 0, ck = 0, sweep = 0, moves = 0;
   bool done = false;
   while (!done && sweep < max_sweeps) {
+    ++sweep;
     // Fresh squared norms each sweep: the running update alp - t gam is exact
     // only for the exact angle, and its drift would steer the rotations of
     // nearly equal columns (a degenerate cluster) instead of their inner
@@ -454,8 +467,6 @@ __device__ inline int jacobi_dist(double X[8], double Y[8], double *sm, double *
       }
       wave_sync();
     }
-    double maxoff = 0.0;
-    const int g = r >> 3, gu = g & 3, gy = g < 4 ? 0 : 8;
 #pragma unroll
     for (int t = 0; t < 7; ++t) {
       // groups 0..3: pairs inside X; groups 4..7: the same pairs inside Y
@@ -464,24 +475,28 @@ __device__ inline int jacobi_dist(double X[8], double Y[8], double *sm, double *
           [&](int j) -> double & {
             return j < 4 ? X[intra_slot(t, 7 - j)] : Y[intra_slot(t, 7 - (j - 4))];
           },
-          gy + intra_slot(t, gu), gy + intra_slot(t, 7 - gu), nrm, maxoff, r);
+          gy + intra_slot(t, gu), gy + intra_slot(t, 7 - gu), nrm, tol, ++rounds, hi, r);
     }
-    for (int br = 0; br < 7; ++br) {
+    for (moves = 0; moves < 7 && !done; ++moves) {
 #pragma unroll
       for (int t = 0; t < 8; ++t)
         jacobi_round([&](int j) -> double & { return X[j]; },
                      [&](int j) -> double & { return Y[(j + t) & 7]; }, g, 8 + ((g + t) & 7), nrm,
-                     maxoff, r);
+                     tol, ++rounds, hi, r);
+      // post this wave's last round above tol; the block move's barriers
+      // publish it (two slots by parity: a slot is rewritten only after the
+      // next move, which every wave passes after reading it)
+      const int w = wave_max_int(hi);
+      double *slot = sm + S_MAX + (ck & 1) * 4;
+      if (r == 0) slot[q] = (double)w;
       exchange_blocks(X, Y, sm, xch, q, r);
+      const int last = max(max((int)slot[0], (int)slot[1]), max((int)slot[2], (int)slot[3]));
+      ++ck;
+      done = rounds - last >= 63;
     }
-    ++sweep;
-    const double wm = wave_max(maxoff);
-    if (r == 0) sm[S_MAX + q] = wm;
-    __syncthreads();
-    const double all = fmax(fmax(sm[S_MAX + 0], sm[S_MAX + 1]), fmax(sm[S_MAX + 2], sm[S_MAX + 3]));
-    done = all <= tol;
-    __syncthreads();
   }
+  if (home)
+    for (; moves < 7; ++moves) exchange_blocks(X, Y, sm, xch, q, r);
   return done ? sweep : -sweep;
 }
 
@@ -721,7 +736,8 @@ __device__ __forceinline__ CoreStatus analysis_core(const AnaArgs<T> &A, const D
   cholesky_solve_lds(La, sm, q, lane);
   load_dist(La, X, Y, q, lane);
   __syncthreads();
-  const int sweeps = jacobi_dist(X, Y, sm, (double *)U, A.jtol, A.max_sweeps, q, lane);
+  // (W and the adjoint sum over all 64 eigenpairs: their order is free)
+  const int sweeps = jacobi_dist(X, Y, sm, (double *)U, A.jtol, A.max_sweeps, false, q, lane);
   const bool conv = sweeps > 0;
 
   // ---- 6. lambda and W = sqrt(c) (U Lambda^{-3/4}) (U Lambda^{-3/4})^T ----
@@ -1485,7 +1501,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   cholesky_lds(la_s, sm, q, r);
   load_dist(la_s, X, Y, q, r);
   __syncthreads();
-  const int sw = jacobi_dist(X, Y, sm, la_s, tol, max_sweeps, q, r);
+  const int sw = jacobi_dist(X, Y, sm, la_s, tol, max_sweeps, true, q, r);  // columns < m are A's
   column_sums(X, Y, [](double v) { return v * v; }, sm + S_LAM, q, r);
   __syncthreads();
   if (r < m) {
