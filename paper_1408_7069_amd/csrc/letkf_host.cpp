@@ -853,7 +853,8 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   h->off[7] = (int32_t)o;
   size_t u = std::max({p4 * kYsStride * T, (size_t)64 * kXsStride * T, letkf_analysis_xch_bytes(),
                        (size_t)64 * kYsStride * T, (size_t)64 * 65 * 8});
-  h->lds = align16(o + u);
+  // the analysis: A~, then the two FP64 64 x 64 matrices of its inverse square root
+  h->lds = align16(o + std::max(u, (size_t)2 * 64 * 65 * 8));
   {  // the adjoint kernel: a larger U area (FP64 64 x 64), Q, a second matrix, scratch
     size_t oa = align16(o + std::max(u, (size_t)64 * 65 * 8));
     h->adj_off[0] = (int32_t)oa; oa = align16(oa + (size_t)64 * 65 * 8);

@@ -175,7 +175,8 @@ constexpr int S_MAX = 640;     // 2 x 4 waves: last round above tol, by block-mo
 constexpr int S_XN = 648;      // 4 waves x 16: norms in flight between waves
 constexpr int S_B = 712;       // 64: b = Y^T sqrt(g) d
 constexpr int S_LAMV = 776;    // 64: lambda
-constexpr int S_TOTAL = 840;
+constexpr int S_RES = 840;     // 4 waves: partial sums of squares (norm, residual)
+constexpr int S_TOTAL = 848;
 constexpr int kXchBytes = kWaves * 8 * 64 * 8;   // one block of every wave in flight
 
 // The 64 columns form 8 blocks of 8; wave q holds block q in X[0..7] and
@@ -587,6 +588,138 @@ __device__ inline void syrk_store_f64(const typename Mfma<T>::V acc[3], double *
   }
 }
 
+// ------------------------------------------- inverse square root (MFMA)
+// Column block of an FP64 64 x 64 matrix held by one wave: columns
+// 16 q .. 16 q + 15 as four 16x16 accumulator tiles of the FP64 16x16x4 MFMA
+// (tile I, element r: row 16 I + lane / 16 + 4 r, column 16 q + lane % 16).
+// The same registers are the right operand of that MFMA: at K step kk it
+// reads rows 4 kk + lane / 16, which is element kk % 4 of tile kk / 4.
+typedef f64x4 ColBlock[4];
+
+// C = M B for the wave's column block: M (left operand) from LDS, row-major
+// with stride kLaStride; B and C column blocks in registers.
+__device__ inline void mm_colblock(const double *M, const ColBlock &B, ColBlock &C, int lane) {
+  const int c16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+  for (int I = 0; I < 4; ++I) C[I] = Mfma<double>::zero();
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const double b = B[kk >> 2][kk & 3];
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+      C[I] = Mfma<double>::mac(M[(16 * I + c16) * kLaStride + 4 * kk + k4], b, C[I]);
+  }
+}
+
+__device__ inline void store_colblock(double *M, const ColBlock &B, int q, int lane) {
+#pragma unroll
+  for (int I = 0; I < 4; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) M[(16 * I + (lane >> 4) + 4 * r) * kLaStride + 16 * q + (lane & 15)] = B[I][r];
+}
+
+__device__ inline double sum4(const double *v) { return (v[0] + v[1]) + (v[2] + v[3]); }
+
+struct IsqrtStatus {
+  int iters;       // products of the iteration taken (negative: no convergence)
+  bool finite;
+  double s;        // the scale: Z ~ (A / s)^{-1/2}
+};
+
+// Z = (A / s)^{-1/2} of the SPD matrix A in LDS (row-major, stride kLaStride,
+// both triangles, every eigenvalue >= lmin > 0) by the scaled coupled
+// Newton-Schulz iteration (Higham, Numer. Algorithms 15, 1997; Functions of
+// Matrices, 2008, ch. 6):
+//     T_k = (3 I - a_k Z_k Y_k) / 2,  Y_{k+1} = sqrt(a_k) Y_k T_k,
+//     Z_{k+1} = sqrt(a_k) T_k Z_k,    Y_0 = A / s, Z_0 = I,
+// s = ||A||_F >= lambda_max.  Every Z_k Y_k is a polynomial in A whose
+// eigenvalues lie in [l_k, 1]; the step maps mu -> a mu (3 - a mu)^2 / 4,
+// and a_k = 3 / (1 + sqrt(l_k) + l_k) gives the two ends of the interval the
+// same image (l_{k+1}), so l_k grows by up to 27/4 a step while far from 1
+// and converges quadratically near it; a_k -> 1 there.  Z and Y are carried
+// as separate products (the coupled form is numerically stable; folding
+// Y = A Z, or symmetrising the iterates, is not).  The iteration stops once
+// the predicted residual after the step, 3/4 ||a_k Z_k Y_k - I||_F^2, is
+// <= tol.  On return Z is in Zc (this wave's column block) and in Zb (LDS);
+// A's area (Yb) has been overwritten.  Every wave takes the same decisions
+// (the residual is summed over the workgroup).
+__device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, double lmin, double tol,
+                                       int max_it, ColBlock &Zc, int q, int lane) {
+  const int col = 16 * q + (lane & 15), k4 = lane >> 4;
+  ColBlock Yc, Tc;
+  double ss = 0.0;
+#pragma unroll
+  for (int I = 0; I < 4; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double v = Yb[(16 * I + k4 + 4 * r) * kLaStride + col];
+      Yc[I][r] = v;
+      ss = fma(v, v, ss);
+    }
+  ss = wave_sum(ss);
+  if (lane == 0) sm[S_RES + q] = ss;
+  __syncthreads();
+  const double s = sqrt(sum4(sm + S_RES));
+  double l = lmin / s;
+  // k = 0 (Z_0 = I): T_0 = (3 I - a A / s) / 2, Z_1 = sqrt(a) T_0,
+  // Y_1 = sqrt(a) / s A T_0 (A read from LDS)
+  double al = 3.0 / (1.0 + sqrt(l) + l);
+  double sa = sqrt(al);
+#pragma unroll
+  for (int I = 0; I < 4; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const bool dg = 16 * I + k4 + 4 * r == col;
+      Tc[I][r] = 0.5 * ((dg ? 3.0 : 0.0) - (al / s) * Yc[I][r]);
+      Zc[I][r] = sa * Tc[I][r];
+    }
+  mm_colblock(Yb, Tc, Yc, lane);
+#pragma unroll
+  for (int I = 0; I < 4; ++I) Yc[I] *= sa / s;
+  l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
+  int it = 1;
+  bool conv = false, finite = true;
+  for (;;) {
+    __syncthreads();  // every read of Yb and Zb of the last step is done
+    store_colblock(Yb, Yc, q, lane);
+    store_colblock(Zb, Zc, q, lane);
+    __syncthreads();
+    if (conv || !finite || it >= max_it) break;
+    al = 3.0 / (1.0 + sqrt(l) + l);
+    sa = sqrt(al);
+    mm_colblock(Zb, Yc, Tc, lane);  // P = Z Y
+    double e2 = 0.0;
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double d = 16 * I + k4 + 4 * r == col ? 1.0 : 0.0;
+        const double e = fma(al, Tc[I][r], -d);  // a P - I
+        e2 = fma(e, e, e2);
+        Tc[I][r] = d - 0.5 * e;                  // (3 I - a P) / 2
+      }
+    e2 = wave_sum(e2);
+    if (lane == 0) sm[S_RES + q] = e2;
+    __syncthreads();  // every read of Zb (as Z) is done
+    store_colblock(Zb, Tc, q, lane);
+    __syncthreads();
+    const double d2 = sum4(sm + S_RES);
+    ColBlock Zn;
+    mm_colblock(Yb, Tc, Yc, lane);  // Y T
+    mm_colblock(Zb, Zc, Zn, lane);  // T Z
+#pragma unroll
+    for (int I = 0; I < 4; ++I) {
+      Yc[I] *= sa;
+      Zc[I] = Zn[I] * sa;
+    }
+    l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
+    ++it;
+    finite = isfinite(d2);
+    conv = finite && 0.75 * d2 <= tol;
+  }
+  return IsqrtStatus{conv ? it : -it, finite, s};
+}
+
 template <typename T> struct AnaArgs {
   const InstDesc *inst;
   const DomItem *items;
@@ -627,10 +760,12 @@ struct CoreStatus {
   bool bad, conv, lam_ok;
 };
 
+// Stages 1-3: on return A~ = c I + Yt^T Yt (FP64, both triangles) at the start
+// of the U area, b = Yt^T sqrt(g) d in sm[S_VEC]; returns whether an
+// observation was not finite.
 template <typename T, bool FUSED>
-__device__ __forceinline__ CoreStatus analysis_core(const AnaArgs<T> &A, const DomItem &it,
-                                                     const InstDesc &in, uint32_t frame,
-                                                     unsigned char *smem, double X[8], double Y[8]) {
+__device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &it, const InstDesc &in,
+                                           uint32_t frame, unsigned char *smem) {
   const int tid = threadIdx.x;
   const int q = tid >> 6, lane = tid & 63;
   const int m = in.m;
@@ -730,6 +865,21 @@ __device__ __forceinline__ CoreStatus analysis_core(const AnaArgs<T> &A, const D
   double *La = (double *)U;  // A~ = c I + Y^T Y in FP64, then its Cholesky factor
   syrk_store_f64<T>(acc, La, c, q, lane);
   __syncthreads();
+  return bad != 0;
+}
+
+template <typename T, bool FUSED>
+__device__ __forceinline__ CoreStatus analysis_core(const AnaArgs<T> &A, const DomItem &it,
+                                                     const InstDesc &in, uint32_t frame,
+                                                     unsigned char *smem, double X[8], double Y[8]) {
+  const int tid = threadIdx.x;
+  const int q = tid >> 6, lane = tid & 63;
+  const int m = in.m;
+  double *sm = (double *)(smem + A.off_s);
+  unsigned char *U = smem + A.off_u;
+  double *La = (double *)U;
+  const double c = (double)(m - 1) / in.rho;
+  const bool bad = stage_gram<T, FUSED>(A, it, in, frame, smem);
 
   // ---- 4./5. FP64 Cholesky, w, one-sided Jacobi ----
   cholesky_lds(La, sm, q, lane);
@@ -758,16 +908,17 @@ __device__ __forceinline__ CoreStatus analysis_core(const AnaArgs<T> &A, const D
     ut[py * kYsStride + lane] = (T)(Y[j] * sm[S_LAM + py]);
   }
   __syncthreads();
+  typename Mfma<T>::V acc[3];
   syrk_share<T>(ut, kYsStride, 16, acc, q, lane);
   __syncthreads();
   T *wmat = ut;  // W row-major [64][kYsStride]
   syrk_store<T>(acc, wmat, kYsStride, (T)sqrt(c), q, lane);
   __syncthreads();
-  return CoreStatus{bad != 0, conv, lam_ok};
+  return CoreStatus{bad, conv, lam_ok};
 }
 
 template <typename T, bool FUSED>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_analysis(const AnaArgs<T> A) {
+__global__ __launch_bounds__(kThreads) void k_analysis(const AnaArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int q = tid >> 6, lane = tid & 63;
@@ -782,15 +933,34 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   T *xm = (T *)(smem + A.off_xm);
   int *pn = (int *)(smem + A.off_pn);
   double *sm = (double *)(smem + A.off_s);
-  T *wmat = (T *)(smem + A.off_u);
-  double X[8], Y[8];
+  double *Yb = (double *)(smem + A.off_u);  // A~, then the iteration's two matrices
+  double *Zb = Yb + 64 * kLaStride;
   const uint32_t frame = (FUSED && A.noise_bank) ? *A.frame : 0u;
-  const CoreStatus st = analysis_core<T, FUSED>(A, it, in, frame, smem, X, Y);
-  const bool bad = st.bad, conv = st.conv, lam_ok = st.lam_ok;
+  const bool bad = stage_gram<T, FUSED>(A, it, in, frame, smem);
 
-  // ---- 7. owned rows: X_a = (x_b + X' w) 1^T + sqrt(rho) X' W ----
-  const bool keep_forecast = bad || !conv || !lam_ok;
-  if (tid == 0) A.flags[item] = (bad || !lam_ok ? 1 : 0) | (conv ? 0 : 2);
+  // ---- 4. Z = (A~ / s)^{-1/2} on the matrix cores (eigenvalues >= c) ----
+  const double c = (double)(m - 1) / in.rho;
+  ColBlock Zc;
+  const IsqrtStatus st = ns_isqrt(Yb, Zb, sm, c, A.jtol * 0.01, A.max_sweeps, Zc, q, lane);
+  const bool conv = st.iters > 0;
+
+  // ---- 5. w = A~^{-1} b = Z (Z b) / s, wave 0, lane = row ----
+  if (q == 0) {
+    double u = 0.0;
+    for (int j = 0; j < 64; ++j) u = fma(Zb[lane * kLaStride + j], sm[S_VEC + j], u);
+    sm[S_COL + lane] = u;
+    wave_sync();
+    double w = 0.0;
+    for (int j = 0; j < 64; ++j) w = fma(Zb[lane * kLaStride + j], sm[S_COL + j], w);
+    sm[S_WV + lane] = w / st.s;
+  }
+  __syncthreads();
+
+  // ---- 6./7. owned rows: X_a = (x_b + X' w) 1^T + sqrt(rho) X' W with
+  // W = sqrt(c) A~^{-1/2} = sqrt(c / s) Z: this wave's members are Z's column
+  // block, already in the right-operand layout of the update's MFMA ----
+  const bool keep_forecast = bad || !conv;
+  if (tid == 0) A.flags[item] = (bad || !st.finite ? 1 : 0) | (conv || !st.finite ? 0 : 2);
   if (tid < nown) {
     const double mu = (double)xm[tid];
     double s = mu;
@@ -798,6 +968,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     sm[S_XAM + tid] = s;
     if (A.x_mean) A.x_mean[in.node_off + pn[tid]] = keep_forecast ? xm[tid] : (T)s;
   }
+  const double wsc = sqrt(c / st.s);
+  T wf[16];
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) wf[kk] = (T)(wsc * Zc[kk >> 2][kk & 3]);
   __syncthreads();
   const T srho = (T)sqrt(in.rho);
   const int c16 = lane & 15, k4 = lane >> 4;
@@ -806,10 +980,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     typename Mfma<T>::V o = Mfma<T>::zero();
     const int ia = 16 * I + c16;
     const T mu = ia < nown ? xm[ia] : (T)0;
+#pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       const int k = 4 * kk + k4;
       const T av = (ia < nown && k < m) ? xs[ia * kXsStride + k] - mu : (T)0;
-      o = Mfma<T>::mac(av, wmat[k * kYsStride + 16 * J + c16], o);
+      o = Mfma<T>::mac(av, wf[kk], o);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
