@@ -52,6 +52,7 @@ extern "C" hipError_t letkf_launch_eigh(const double *A, int m, int batch, doubl
 extern "C" size_t letkf_args_size(int fp64);
 extern "C" int letkf_analysis_threads(void);
 extern "C" size_t letkf_analysis_scratch_doubles(void);
+extern "C" size_t letkf_analysis_fwd_scratch_doubles(void);
 extern "C" size_t letkf_analysis_xch_bytes(void);
 extern "C" const void *letkf_adjoint_kernel(int fp64);
 extern "C" size_t letkf_adjoint_scratch_doubles(void);
@@ -120,7 +121,7 @@ template <typename T> struct AnaArgsHost {
   const uint32_t *frame;
   double jtol;
   int32_t max_sweeps;
-  int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u;
+  int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
 };
 
 // Mirror of PistonArgs<T>.
@@ -189,7 +190,8 @@ struct letkf_handle {
   double jtol = 0.0;
   int max_sweeps = 30;
   size_t lds = 0;
-  int32_t off[8] = {0};
+  int32_t off[9] = {0};      // LDS layout of the adjoint's forward stages
+  int32_t fwd_off[9] = {0};  // LDS layout of the analysis
   // device
   InstDesc *d_desc = nullptr;
   DomItem *d_items = nullptr;
@@ -498,6 +500,18 @@ void free_handle(letkf_handle *h) {
   delete h;
 }
 
+template <typename T> void set_offsets(AnaArgsHost<T> &A, const int32_t *off) {
+  A.off_xs = off[0];
+  A.off_xm = off[1];
+  A.off_sg = off[2];
+  A.off_dd = off[3];
+  A.off_yb = off[4];
+  A.off_pn = off[5];
+  A.off_s = off[6];
+  A.off_u = off[7];
+  A.off_ys = off[8];
+}
+
 template <typename T>
 AnaArgsHost<T> make_args(letkf_handle *h, bool fused, const void *V, const void *y, int xa_in,
                          int xa_out) {
@@ -525,14 +539,7 @@ AnaArgsHost<T> make_args(letkf_handle *h, bool fused, const void *V, const void 
   A.frame = h->d_frame;
   A.jtol = h->jtol;
   A.max_sweeps = h->max_sweeps;
-  A.off_xs = h->off[0];
-  A.off_xm = h->off[1];
-  A.off_sg = h->off[2];
-  A.off_dd = h->off[3];
-  A.off_yb = h->off[4];
-  A.off_pn = h->off[5];
-  A.off_s = h->off[6];
-  A.off_u = h->off[7];
+  set_offsets(A, h->fwd_off);
   return A;
 }
 
@@ -848,13 +855,36 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   h->off[2] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * 8);
   h->off[3] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * 8);
   h->off[4] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * T);
-  h->off[5] = (int32_t)o; o = align16(o + 64 * 4);
+  h->off[5] = (int32_t)o; o = align16(o + 128 * 4);
   h->off[6] = (int32_t)o; o = align16(o + letkf_analysis_scratch_doubles() * 8);
   h->off[7] = (int32_t)o;
+  h->off[8] = (int32_t)o;
   size_t u = std::max({p4 * kYsStride * T, (size_t)64 * kXsStride * T, letkf_analysis_xch_bytes(),
                        (size_t)64 * kYsStride * T, (size_t)64 * 65 * 8});
-  // the analysis: A~, then the two FP64 64 x 64 matrices of its inverse square root
-  h->lds = align16(o + std::max(u, (size_t)2 * 64 * 65 * 8));
+  {
+    // The analysis: small arrays, then the patch rows, of which only the owned
+    // ones (rows 0 .. n_own - 1) outlive stage 2; the others run on into the U
+    // area, which holds A~ and then the two FP64 64 x 64 matrices of its inverse
+    // square root from stage 3 on; the slopes operand ys of stages 2-3 sits at
+    // the end of U, clear of those rows.  FP32 at 80x80, m = 64: under 80 KiB,
+    // two workgroups per CU.
+    size_t f = 0;
+    h->fwd_off[1] = (int32_t)f; f = align16(f + 64 * T);
+    h->fwd_off[2] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * 8);
+    h->fwd_off[3] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * 8);
+    h->fwd_off[4] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * T);
+    h->fwd_off[5] = (int32_t)f; f = align16(f + 128 * 4);
+    h->fwd_off[6] = (int32_t)f; f = align16(f + letkf_analysis_fwd_scratch_doubles() * 8);
+    h->fwd_off[0] = (int32_t)f;
+    const size_t ub = align16(f + (size_t)h->max_own * kXsStride * T);
+    const size_t rows_end = f + (size_t)h->max_patch * kXsStride * T;  // end of the patch rows
+    const size_t ys_bytes = p4 * kYsStride * T;
+    const size_t spill = rows_end > ub ? align16(rows_end - ub) : 0;
+    const size_t uf = std::max((size_t)2 * 64 * 65 * 8, spill + ys_bytes);
+    h->fwd_off[7] = (int32_t)ub;
+    h->fwd_off[8] = (int32_t)(ub + uf - ys_bytes);
+    h->lds = align16(ub + uf);
+  }
   {  // the adjoint kernel: a larger U area (FP64 64 x 64), Q, a second matrix, scratch
     size_t oa = align16(o + std::max(u, (size_t)64 * 65 * 8));
     h->adj_off[0] = (int32_t)oa; oa = align16(oa + (size_t)64 * 65 * 8);
@@ -1395,6 +1425,7 @@ static AdjArgsHost<T> make_adj_args(letkf_handle *h, const void *xa_prev, const 
   // than the forward's transform needs
   D.F.jtol = h->fp64 ? h->jtol : std::min(h->jtol, 1e-6);
   D.F.frame = nullptr;
+  set_offsets(D.F, h->off);
   D.xbar = (const T *)xbar;
   D.xpbar = (T *)h->d_xpbar;
   D.xbbar = h->d_xbbar;

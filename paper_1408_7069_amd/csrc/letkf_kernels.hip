@@ -163,20 +163,21 @@ __device__ inline double rsq_nr(double x, int steps) {
 }
 
 // ------------------------------------------------------------ LDS scratch
-// Small FP64 scratch (offsets in doubles).
-constexpr int S_INVD = 0;      // 1 / L_kk
-constexpr int S_COL = 64;      // 2 x 64: Cholesky column broadcast
-constexpr int S_VEC = 192;     // 64: residual / z of the solves
-constexpr int S_WV = 256;      // 64: w
-constexpr int S_LAM = 320;     // 64: lambda^{-3/4}
-constexpr int S_NRM = 384;     // 4 waves x 16: column norms by register slot
-constexpr int S_XAM = 448;     // 64: analysis mean of the owned rows
-constexpr int S_MAX = 640;     // 2 x 4 waves: last round above tol, by block-move parity
-constexpr int S_XN = 648;      // 4 waves x 16: norms in flight between waves
-constexpr int S_B = 712;       // 64: b = Y^T sqrt(g) d
-constexpr int S_LAMV = 776;    // 64: lambda
-constexpr int S_RES = 840;     // 4 waves: partial sums of squares (norm, residual)
-constexpr int S_TOTAL = 848;
+// Small FP64 scratch (offsets in doubles).  The forward analysis uses the
+// first kFwdScratch; the Jacobi paths (adjoint, batched eigensolver) all.
+constexpr int S_VEC = 0;       // 64: b = Yt^T sqrt(g) d (residual / z of the solves)
+constexpr int S_WV = 64;       // 64: w
+constexpr int S_XAM = 128;     // 64: analysis mean of the owned rows
+constexpr int S_COL = 192;     // 2 x 64: Z b of the mean weights
+constexpr int S_RES = 320;     // 4 waves: partial sums of squares (norm, residual)
+constexpr int kFwdScratch = 328;
+constexpr int S_INVD = 328;    // 64: 1 / L_kk
+constexpr int S_LAM = 392;     // 64: lambda^{-3/4}
+constexpr int S_NRM = 456;     // 4 waves x 16: column norms by register slot
+constexpr int S_MAX = 520;     // 2 x 4 waves: last round above tol, by block-move parity
+constexpr int S_XN = 528;      // 4 waves x 16: norms in flight between waves
+constexpr int S_LAMV = 592;    // 64: lambda
+constexpr int S_TOTAL = 656;
 constexpr int kXchBytes = kWaves * 8 * 64 * 8;   // one block of every wave in flight
 
 // The 64 columns form 8 blocks of 8; wave q holds block q in X[0..7] and
@@ -539,6 +540,7 @@ __device__ inline void syrk_share(const T *M, int ld, int ksteps, typename Mfma<
     tile_of(q + 4 * u < 10 ? q + 4 * u : 0, I[u], J[u]);
   }
   const int nt = q < 2 ? 3 : 2;
+#pragma unroll 3
   for (int kk = 0; kk < ksteps; ++kk) {
     const T *row = M + (4 * kk + k4) * ld;
 #pragma unroll
@@ -681,7 +683,7 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
   bool conv = false, finite = true;
   for (;;) {
     __syncthreads();  // every read of Yb and Zb of the last step is done
-    store_colblock(Yb, Yc, q, lane);
+    if (!conv) store_colblock(Yb, Yc, q, lane);
     store_colblock(Zb, Zc, q, lane);
     __syncthreads();
     if (conv || !finite || it >= max_it) break;
@@ -704,9 +706,11 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
     store_colblock(Zb, Tc, q, lane);
     __syncthreads();
     const double d2 = sum4(sm + S_RES);
+    finite = isfinite(d2);
+    conv = finite && 0.75 * d2 <= tol;
     ColBlock Zn;
-    mm_colblock(Yb, Tc, Yc, lane);  // Y T
-    mm_colblock(Zb, Zc, Zn, lane);  // T Z
+    if (!conv) mm_colblock(Yb, Tc, Yc, lane);  // Y T (the last step needs only Z)
+    mm_colblock(Zb, Zc, Zn, lane);             // T Z
 #pragma unroll
     for (int I = 0; I < 4; ++I) {
       Yc[I] *= sa;
@@ -714,8 +718,6 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
     }
     l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
     ++it;
-    finite = isfinite(d2);
-    conv = finite && 0.75 * d2 <= tol;
   }
   return IsqrtStatus{conv ? it : -it, finite, s};
 }
@@ -740,7 +742,7 @@ template <typename T> struct AnaArgs {
   const uint32_t *frame;  // frame counter of the bank draws (device)
   double jtol;
   int32_t max_sweeps;
-  int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u;
+  int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
 };
 
 __device__ inline int xcd_item(int b, int grid) {
@@ -782,32 +784,43 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
   unsigned char *U = smem + A.off_u;
 
   // ---- 1. node patch of X_b (rows dealt to the four waves) ----
-  if (q == 0) pn[lane] = lane < np ? A.patch_node[it.patch_off + lane] : 0;
-  BankDraw bd{};
+  // patch node of row `lane` and its grid coordinates (pn[64 + r]: i | j << 16)
   const bool use_bank = FUSED && A.noise_bank;
+  if (q == 0) {
+    const int g = lane < np ? A.patch_node[it.patch_off + lane] : 0;
+    pn[lane] = g;
+    if (use_bank) pn[64 + lane] = A.node_ij[2 * (in.node_off + g)] | (A.node_ij[2 * (in.node_off + g) + 1] << 16);
+  }
+  BankDraw bd{};
   if (use_bank && lane < m) bd = bank_draw(in, frame, lane);
   __syncthreads();
   const T a = (T)in.a;
-  for (int r = q; r < np; r += kWaves) {
-    const int g = pn[r];
-    T v = (T)0;
-    if (lane < m) {
-      const int64_t e = in.x_off + (int64_t)g * m + lane;
-      const T x = A.x_in[e];
-      if (FUSED) {
-        T noise;
-        if (use_bank) {
-          const int gi = A.node_ij[2 * (in.node_off + g)], gj = A.node_ij[2 * (in.node_off + g) + 1];
-          noise = (T)bank_value(A.bank, bd, gi, gj);
-        } else {
-          noise = A.v_in[e];
+  // four rows a pass, their loads issued together
+  for (int r0 = q; r0 < np; r0 += 4 * kWaves) {
+    T xv[4], nv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + u * kWaves;
+      xv[u] = (T)0;
+      nv[u] = (T)0;
+      if (r < np && lane < m) {
+        const int64_t e = in.x_off + (int64_t)pn[r] * m + lane;
+        xv[u] = A.x_in[e];
+        if (FUSED) {
+          if (use_bank) {
+            const int ij = pn[64 + r];
+            nv[u] = (T)bank_value(A.bank, bd, ij & 0xFFFF, ij >> 16);
+          } else {
+            nv[u] = A.v_in[e];
+          }
         }
-        v = fma_t(a, x, noise);
-      } else {
-        v = x;
       }
     }
-    xs[r * kXsStride + lane] = v;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + u * kWaves;
+      if (r < np) xs[r * kXsStride + lane] = FUSED ? fma_t(a, xv[u], nv[u]) : xv[u];
+    }
   }
   __syncthreads();
   if (tid < np) {
@@ -838,7 +851,7 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
     yb[nobs + tid] = yby;
   }
   bad = __syncthreads_or(bad);
-  T *ys = (T *)U;  // [p4][kYsStride], K-major MFMA operand
+  T *ys = (T *)(smem + A.off_ys);  // [p4][kYsStride], K-major MFMA operand
   for (int o = q; o < nobs; o += kWaves) {
     const uint32_t cw = A.obs_corner[it.obs_off + o];
     const int ca = cw & 255, cb = (cw >> 8) & 255, cc = (cw >> 16) & 255, cd = cw >> 24;
@@ -851,10 +864,15 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
   }
   for (int o = p + q; o < p4; o += kWaves) ys[o * kYsStride + lane] = (T)0;
   __syncthreads();
-  if (q == 0) {  // b = Y^T sqrt(g) d, member = lane
-    double bj = 0.0;
-    for (int s = 0; s < p; ++s) bj = fma((double)ys[s * kYsStride + lane], dd[s], bj);
-    sm[S_VEC + lane] = bj;
+  if (q == 0) {  // b = Y^T sqrt(g) d, member = lane (p4 - p rows of ys are zero)
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    for (int s = 0; s < p4; s += 4) {
+      b0 = fma((double)ys[s * kYsStride + lane], s < p ? dd[s] : 0.0, b0);
+      b1 = fma((double)ys[(s + 1) * kYsStride + lane], s + 1 < p ? dd[s + 1] : 0.0, b1);
+      b2 = fma((double)ys[(s + 2) * kYsStride + lane], s + 2 < p ? dd[s + 2] : 0.0, b2);
+      b3 = fma((double)ys[(s + 3) * kYsStride + lane], s + 3 < p ? dd[s + 3] : 0.0, b3);
+    }
+    sm[S_VEC + lane] = (b0 + b1) + (b2 + b3);
   }
 
   // ---- 3. Gram on the matrix cores ----
@@ -1726,6 +1744,7 @@ extern "C" const void *letkf_analysis_kernel(int fp64, int fused) {
 extern "C" int letkf_analysis_threads(void) { return kThreads; }
 
 extern "C" size_t letkf_analysis_scratch_doubles(void) { return S_TOTAL; }
+extern "C" size_t letkf_analysis_fwd_scratch_doubles(void) { return kFwdScratch; }
 
 extern "C" size_t letkf_analysis_xch_bytes(void) {
   return (size_t)kXchBytes;
