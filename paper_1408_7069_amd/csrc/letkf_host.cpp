@@ -866,8 +866,8 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     // ones (rows 0 .. n_own - 1) outlive stage 2; the others run on into the U
     // area, which holds A~ and then the two FP64 64 x 64 matrices of its inverse
     // square root from stage 3 on; the slopes operand ys of stages 2-3 sits at
-    // the end of U, clear of those rows.  FP32 at 80x80, m = 64: under 80 KiB,
-    // two workgroups per CU.
+    // the end of U, clear of those rows.  FP32 at 80x80, m = 64: 78 KB, under
+    // 80 KiB: two workgroups per CU.
     size_t f = 0;
     h->fwd_off[1] = (int32_t)f; f = align16(f + 64 * T);
     h->fwd_off[2] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * 8);
@@ -880,7 +880,9 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     const size_t rows_end = f + (size_t)h->max_patch * kXsStride * T;  // end of the patch rows
     const size_t ys_bytes = p4 * kYsStride * T;
     const size_t spill = rows_end > ub ? align16(rows_end - ub) : 0;
-    const size_t uf = std::max((size_t)2 * 64 * 65 * 8, spill + ys_bytes);
+    // FP64: the iterates overwrite A~; FP32: A~ (FP64) and two FP32 iterates (row stride 68)
+    const size_t iter_bytes = T == 8 ? (size_t)2 * 64 * 65 * 8 : (size_t)64 * 65 * 8 + 2 * 64 * 68 * 4;
+    const size_t uf = std::max(iter_bytes, spill + ys_bytes);
     h->fwd_off[7] = (int32_t)ub;
     h->fwd_off[8] = (int32_t)(ub + uf - ys_bytes);
     h->lds = align16(ub + uf);

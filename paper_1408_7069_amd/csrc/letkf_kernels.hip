@@ -722,6 +722,131 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
   return IsqrtStatus{conv ? it : -it, finite, s};
 }
 
+// The same iteration in FP32 on the FP32 matrix cores (twice the FP64 rate).
+// Column blocks as FP32 16x16x4 accumulator tiles (tile I, element r: row
+// 16 I + 4 (lane / 16) + r, column 16 q + lane % 16); FP32 matrices in LDS
+// with row stride kNs32Stride (left-operand reads fall in distinct banks).
+constexpr int kNs32Stride = 68;
+typedef f32x4 ColBlock32[4];
+
+// Right-operand form of one accumulator tile: the tile's element (4 g + r, c)
+// sits in lane (g, c), register r; the FP32 MFMA's step kk reads element
+// (4 kk + g, c) in lane (g, c).  A 4 x 4 transpose of (lane group, register):
+// v_permlane32_swap exchanges bit 1 of the two, v_permlane16_swap bit 0.
+__device__ inline f32x4 tile_to_rhs(f32x4 v) {
+  auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[0]), __float_as_uint(v[2]), false, false);
+  auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[1]), __float_as_uint(v[3]), false, false);
+  auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
+  auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
+  return f32x4{__uint_as_float(c[0]), __uint_as_float(c[1]), __uint_as_float(d[0]), __uint_as_float(d[1])};
+}
+
+__device__ inline void mm_colblock32(const float *M, const ColBlock32 &B, ColBlock32 &C, int lane) {
+  const int c16 = lane & 15, k4 = lane >> 4;
+  f32x4 Bt[4];
+#pragma unroll
+  for (int I = 0; I < 4; ++I) {
+    Bt[I] = tile_to_rhs(B[I]);
+    C[I] = Mfma<float>::zero();
+  }
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const float b = Bt[kk >> 2][kk & 3];
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+      C[I] = Mfma<float>::mac(M[(16 * I + c16) * kNs32Stride + 4 * kk + k4], b, C[I]);
+  }
+}
+
+__device__ inline void store_colblock32(float *M, const ColBlock32 &B, int q, int lane) {
+#pragma unroll
+  for (int I = 0; I < 4; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      M[(16 * I + 4 * (lane >> 4) + r) * kNs32Stride + 16 * q + (lane & 15)] = B[I][r];
+}
+
+// ns_isqrt in FP32: A (FP64 in LDS, stride kLaStride) is read, not written;
+// Yb, Zb are FP32 64 x 64 areas.  The residual is summed in FP64.
+__device__ inline IsqrtStatus ns_isqrt32(const double *A, float *Yb, float *Zb, double *sm, double lmin,
+                                         double tol, int max_it, ColBlock32 &Zc, int q, int lane) {
+  const int col = 16 * q + (lane & 15), g4 = 4 * (lane >> 4);
+  ColBlock32 Yc, Tc;
+  double ss = 0.0;
+#pragma unroll
+  for (int I = 0; I < 4; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double v = A[(16 * I + g4 + r) * kLaStride + col];
+      Yc[I][r] = (float)v;
+      ss = fma(v, v, ss);
+    }
+  ss = wave_sum(ss);
+  if (lane == 0) sm[S_RES + q] = ss;
+  store_colblock32(Yb, Yc, q, lane);  // A in FP32, the left operand of the first product
+  __syncthreads();
+  const double s = sqrt(sum4(sm + S_RES));
+  double l = lmin / s;
+  double al = 3.0 / (1.0 + sqrt(l) + l);
+  float sa = (float)sqrt(al);
+  const float as = (float)(al / s);
+#pragma unroll
+  for (int I = 0; I < 4; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const bool dg = 16 * I + g4 + r == col;
+      Tc[I][r] = 0.5f * ((dg ? 3.0f : 0.0f) - as * Yc[I][r]);
+      Zc[I][r] = sa * Tc[I][r];
+    }
+  mm_colblock32(Yb, Tc, Yc, lane);
+  const float ys = (float)(sqrt(al) / s);
+#pragma unroll
+  for (int I = 0; I < 4; ++I) Yc[I] *= ys;
+  l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
+  int it = 1;
+  bool conv = false, finite = true;
+  for (;;) {
+    __syncthreads();  // every read of Yb and Zb of the last step is done
+    if (!conv) store_colblock32(Yb, Yc, q, lane);
+    store_colblock32(Zb, Zc, q, lane);
+    __syncthreads();
+    if (conv || !finite || it >= max_it) break;
+    al = 3.0 / (1.0 + sqrt(l) + l);
+    sa = (float)sqrt(al);
+    const float alf = (float)al;
+    mm_colblock32(Zb, Yc, Tc, lane);  // P = Z Y
+    double e2 = 0.0;
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float d = 16 * I + g4 + r == col ? 1.0f : 0.0f;
+        const float e = fmaf(alf, Tc[I][r], -d);  // a P - I
+        e2 = fma((double)e, (double)e, e2);
+        Tc[I][r] = d - 0.5f * e;                  // (3 I - a P) / 2
+      }
+    e2 = wave_sum(e2);
+    if (lane == 0) sm[S_RES + q] = e2;
+    __syncthreads();  // every read of Zb (as Z) is done
+    store_colblock32(Zb, Tc, q, lane);
+    __syncthreads();
+    const double d2 = sum4(sm + S_RES);
+    finite = isfinite(d2);
+    conv = finite && 0.75 * d2 <= tol;
+    ColBlock32 Zn;
+    if (!conv) mm_colblock32(Yb, Tc, Yc, lane);  // Y T (the last step needs only Z)
+    mm_colblock32(Zb, Zc, Zn, lane);             // T Z
+#pragma unroll
+    for (int I = 0; I < 4; ++I) {
+      Yc[I] *= sa;
+      Zc[I] = Zn[I] * sa;
+    }
+    l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
+    ++it;
+  }
+  return IsqrtStatus{conv ? it : -it, finite, s};
+}
+
 template <typename T> struct AnaArgs {
   const InstDesc *inst;
   const DomItem *items;
@@ -957,21 +1082,64 @@ __global__ __launch_bounds__(kThreads) void k_analysis(const AnaArgs<T> A) {
   const bool bad = stage_gram<T, FUSED>(A, it, in, frame, smem);
 
   // ---- 4. Z = (A~ / s)^{-1/2} on the matrix cores (eigenvalues >= c) ----
+  // ---- 5. w = A~^{-1} b = Z (Z b) / s (wave 0, lane = row) ----
   const double c = (double)(m - 1) / in.rho;
-  ColBlock Zc;
-  const IsqrtStatus st = ns_isqrt(Yb, Zb, sm, c, A.jtol * 0.01, A.max_sweeps, Zc, q, lane);
-  const bool conv = st.iters > 0;
-
-  // ---- 5. w = A~^{-1} b = Z (Z b) / s, wave 0, lane = row ----
-  if (q == 0) {
-    double u = 0.0;
-    for (int j = 0; j < 64; ++j) u = fma(Zb[lane * kLaStride + j], sm[S_VEC + j], u);
-    sm[S_COL + lane] = u;
-    wave_sync();
-    double w = 0.0;
-    for (int j = 0; j < 64; ++j) w = fma(Zb[lane * kLaStride + j], sm[S_COL + j], w);
-    sm[S_WV + lane] = w / st.s;
+  IsqrtStatus st;
+  T wf[16];  // this wave's column block of Z, right-operand layout of the update
+  if constexpr (sizeof(T) == 4) {
+    // FP32 iterates; A~ stays in FP64 for one refinement of w, which carries
+    // the mean (w = w0 + Z (Z (b - A~ w0)) / s)
+    float *Y32 = (float *)(Yb + 64 * kLaStride);
+    float *Z32 = Y32 + 64 * kNs32Stride;
+    ColBlock32 Zc;
+    st = ns_isqrt32(Yb, Y32, Z32, sm, c, A.jtol * 0.01, A.max_sweeps, Zc, q, lane);
+    if (q == 0) {
+      const float *zr = Z32 + lane * kNs32Stride;
+      double u = 0.0;
+      for (int j = 0; j < 64; ++j) u = fma((double)zr[j], sm[S_VEC + j], u);
+      sm[S_COL + lane] = u;
+      wave_sync();
+      double w0 = 0.0;
+      for (int j = 0; j < 64; ++j) w0 = fma((double)zr[j], sm[S_COL + j], w0);
+      w0 /= st.s;
+      sm[S_WV + lane] = w0;
+      wave_sync();
+      double r = sm[S_VEC + lane];
+      for (int j = 0; j < 64; ++j) r = fma(-Yb[lane * kLaStride + j], sm[S_WV + j], r);
+      sm[S_COL + 64 + lane] = r;
+      wave_sync();
+      double u2 = 0.0;
+      for (int j = 0; j < 64; ++j) u2 = fma((double)zr[j], sm[S_COL + 64 + j], u2);
+      sm[S_COL + lane] = u2;
+      wave_sync();
+      double dw = 0.0;
+      for (int j = 0; j < 64; ++j) dw = fma((double)zr[j], sm[S_COL + j], dw);
+      sm[S_WV + lane] = w0 + dw / st.s;
+    }
+    const float wsc = (float)sqrt(c / st.s);
+#pragma unroll
+    for (int I = 0; I < 4; ++I) {
+      const f32x4 bt = tile_to_rhs(Zc[I]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) wf[4 * I + r] = wsc * bt[r];
+    }
+  } else {
+    ColBlock Zc;
+    st = ns_isqrt(Yb, Zb, sm, c, A.jtol * 0.01, A.max_sweeps, Zc, q, lane);
+    if (q == 0) {
+      double u = 0.0;
+      for (int j = 0; j < 64; ++j) u = fma(Zb[lane * kLaStride + j], sm[S_VEC + j], u);
+      sm[S_COL + lane] = u;
+      wave_sync();
+      double w = 0.0;
+      for (int j = 0; j < 64; ++j) w = fma(Zb[lane * kLaStride + j], sm[S_COL + j], w);
+      sm[S_WV + lane] = w / st.s;
+    }
+    const double wsc = sqrt(c / st.s);
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) wf[kk] = (T)(wsc * Zc[kk >> 2][kk & 3]);
   }
+  const bool conv = st.iters > 0;
   __syncthreads();
 
   // ---- 6./7. owned rows: X_a = (x_b + X' w) 1^T + sqrt(rho) X' W with
@@ -986,10 +1154,6 @@ __global__ __launch_bounds__(kThreads) void k_analysis(const AnaArgs<T> A) {
     sm[S_XAM + tid] = s;
     if (A.x_mean) A.x_mean[in.node_off + pn[tid]] = keep_forecast ? xm[tid] : (T)s;
   }
-  const double wsc = sqrt(c / st.s);
-  T wf[16];
-#pragma unroll
-  for (int kk = 0; kk < 16; ++kk) wf[kk] = (T)(wsc * Zc[kk >> 2][kk & 3]);
   __syncthreads();
   const T srho = (T)sqrt(in.rho);
   const int c16 = lane & 15, k4 = lane >> 4;
