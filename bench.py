@@ -65,6 +65,32 @@ def algorithmic_flops(m: int, p_list, n_list) -> dict:
             "update": float(np.sum(2 * n * m * m + 2 * n * m)), "stencil": float(np.sum(6 * p * m))}
 
 
+def transform_variants(B, spec, y, K, W):
+    """The same frames with the other transforms of the local analyses: the
+    FP64 Jacobi eigendecomposition and the Newton-Schulz iteration with FP32
+    iterates (frame time by graph replay, analysis kernel by HIP events)."""
+    import dataclasses
+    import torch
+    out = {}
+    for name, tr in (("evd_jacobi_fp64", B.TRANSFORM_EVD), ("ns_fp32_iterates", B.TRANSFORM_NS32)):
+        g = B.Letkf([dataclasses.replace(spec, transform=tr)])
+        g.set_schedule(True, True)
+        ms = time_steps(g, y, K, W)
+        g.set_ensemble(torch.zeros(g.sizes["ensemble_elems"], dtype=torch.float32, device="cuda"))
+        g.set_frame(0)
+        g.set_schedule(False, True)
+        time_steps(g, y, 0, W)
+        g.set_timing(True)
+        time_steps(g, y, K, 0, offset=W)
+        kt = float(np.mean(g.analysis_times()))
+        g.set_timing(False)
+        steps = (g.status()[1] >> 8) & 255
+        out[name] = {"ms_per_step": round(ms, 5), "frames_per_s": round(1000.0 / ms, 2),
+                     "kernel_ms": round(kt, 4), "steps_mean": round(float(steps.mean()), 3)}
+        g.close()
+    return out
+
+
 def make_inputs(f, wl_mod, w, frames: int, rng):
     """Slopes of an AR(1) true phase for `frames` frames, resident on the GPU."""
     import torch
@@ -296,10 +322,20 @@ def main():
     fl = algorithmic_flops(w.m, p_list, n_list)
     total = sum(fl.values())
     achieved = total / (kernel_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+    # what the matrix cores executed for the inverse square root: per domain
+    # one product at the first step, three at each later one but the last (two)
+    steps = (f.status()[1] >> 8) & 255
+    products = np.maximum(3 * steps.astype(np.int64) - 3, 1)
+    ns_flops = float(products.sum()) * 2.0 * 64 ** 3
+    ns_tflops = ns_flops / (kernel_ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
-            "kernel": "k_analysis<float,true>", "kernel_ms": round(kernel_ms, 4),
-            "flops_per_launch": total, "flops_breakdown": fl}
+            "kernel": "k_analysis<float,true,NS64>", "kernel_ms": round(kernel_ms, 4),
+            "flops_per_launch": total, "flops_breakdown": fl,
+            "newton_schulz": {"steps_mean": round(float(steps.mean()), 3),
+                              "fp64_mfma_flops_per_launch": ns_flops,
+                              "achieved_tflops": round(ns_tflops, 3),
+                              "frac_of_fp64_mfma_peak": round(ns_tflops / FP64_PEAK_TFLOPS, 4)}}
 
     # batched throughput: several copies of the workload in one launch
     copies = None
@@ -311,6 +347,8 @@ def main():
                   "local_analyses_per_s": round(args.copies * n_dom * 1000.0 / msc, 1),
                   "frac_of_fp64_peak": round(args.copies * total / (msc * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
         fc.close()
+
+    transforms = transform_variants(B, spec, y, K, W)
 
     others = other_workloads(B, wl, 100, 20) if args.other_workloads else None
 
@@ -332,6 +370,7 @@ def main():
         "step_ms_p50": round(float(np.percentile(per, 50)), 4),
         "step_ms_p99": round(float(np.percentile(per, 99)), 4),
         "batched_copies": copies,
+        "transforms": transforms,
         "filter_check": filt,
         "other_workloads": others,
         "gradient": grad,

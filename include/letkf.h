@@ -11,8 +11,10 @@
  *               Y_l  = observation-region rows of D (X_b - x_b 1^T), scaled by
  *                      sqrt(g), g = f^2 / (s r) (taper f on Sigma_w^{-1/2}, Sec. 4.1)
  *               A~   = (m-1)/rho I + Y_l^T Y_l      (m x m, Sec. 3.1.1 EVD matrix)
- *               A~   = Q Lambda Q^T                 (FP64 Jacobi eigensolve)
  *               w    = A~^{-1} Y_l^T sqrt(g) d_l,   W = sqrt((m-1)/rho) A~^{-1/2}
+ *                      (Sec. 3.1.1 via A~ = Q Lambda Q^T); A~^{-1/2} from an
+ *                      FP64 Newton-Schulz iteration by default, or from the
+ *                      FP64 Jacobi eigendecomposition (see `transform`)
  *               X_a,l = (x_b,l + X_l' w) 1^T + sqrt(rho) X_l' W   (owned rows)
  *   gather    the owned rows of all domains form X_a (Sec. 4.2, concatenation)
  * with D the Fried-geometry Shack-Hartmann slope operator (App. B).
@@ -51,15 +53,33 @@ extern "C" {
 #define LETKF_E_NOMEM (-2)      /* device or host allocation failed           */
 #define LETKF_E_DEVICE (-3)     /* HIP runtime error                          */
 #define LETKF_E_NONFINITE (-4)  /* NaN/Inf met in the slopes or the update     */
-#define LETKF_E_NOCONV (-5)     /* eigensolve hit max_sweeps in >= 1 domain   */
+#define LETKF_E_NOCONV (-5)     /* transform hit max_sweeps in >= 1 domain   */
 #define LETKF_E_STATE (-6)      /* call out of order (e.g. analyse before forecast) */
 
-#define LETKF_FP32 0            /* FP32 state and MFMA contractions, FP64 eigensolve */
-#define LETKF_FP64 1            /* FP64 everywhere                                    */
+#define LETKF_FP32 0            /* FP32 state and MFMA contractions, FP64 transform */
+#define LETKF_FP64 1            /* FP64 everywhere                                   */
 
-/* Per-domain status bits (letkf_status). */
+/* Transform of the local analyses (letkf_config.transform): how W and w are
+ * obtained from A~ (Sec. 3.1.1).
+ *   NS64  A~^{-1/2} by the scaled coupled Newton-Schulz iteration in FP64 on
+ *         the FP64 matrix cores (Higham 1997), w = A~^{-1} b from the same
+ *         iterate; stops when the predicted residual ||a Z Y - I||_F^2 after
+ *         a step is <= jacobi_tol / 100.  Default.
+ *   NS32  the same iteration with FP32 iterates on the FP32 matrix cores
+ *         (W within ~2e-5 relative), w refined once in FP64 against A~.
+ *         FP32 handles only; an FP64 handle runs NS64.
+ *   EVD   A~ = Q Lambda Q^T by the FP64 one-sided Jacobi on the Cholesky
+ *         factor (stop: jacobi_tol on the relative inner products), then
+ *         W = sqrt(c) Q Lambda^{-1/2} Q^T and w from the Cholesky factor. */
+#define LETKF_TRANSFORM_NS64 0
+#define LETKF_TRANSFORM_NS32 1
+#define LETKF_TRANSFORM_EVD 2
+
+/* Per-domain status bits (letkf_status); bits 8-15 hold the steps the
+ * transform took (Newton-Schulz steps, or Jacobi sweeps begun). */
 #define LETKF_FLAG_NONFINITE 1
 #define LETKF_FLAG_NOCONV 2
+#define LETKF_FLAG_STEPS_SHIFT 8
 
 typedef struct letkf_handle letkf_handle;
 
@@ -89,17 +109,22 @@ typedef struct letkf_config {
   int32_t bank_side;           /* power of two, >= N + 1                           */
   uint64_t seed;               /* Philox4x32-10 key for the bank draws             */
   int32_t precision;           /* LETKF_FP32 or LETKF_FP64 (same for all instances) */
-  double jacobi_tol;           /* stop after a sweep whose largest relative off-
-                                  diagonal measure is <= tol; 0 = 1e-4 (FP32:
-                                  W then within ~5e-6 relative, below FP32
-                                  state rounding), 1e-10 (FP64)                    */
-  int32_t max_sweeps;          /* 0 = 30                                           */
+  double jacobi_tol;           /* accuracy of the transform: EVD stops when 63
+                                  rounds pass with no relative inner product
+                                  above tol; NS64/NS32 stop when the predicted
+                                  residual is <= tol / 100.  0 = 1e-4 (FP32: W
+                                  within ~5e-6 relative with EVD, ~1e-9 with
+                                  NS64), 1e-10 (FP64).  The adjoint's Jacobi
+                                  uses min(tol, 1e-6) in FP32.                     */
+  int32_t max_sweeps;          /* 0 = 30: Jacobi sweeps, or Newton-Schulz steps    */
   int32_t piston_removal;      /* 1: after the gather, remove one piston per domain
                                   fitted by least squares to the slopes of the
                                   subapertures that straddle domains (Sec. 4.4:
                                   local estimates are blind to their own piston);
                                   every member of the domain is shifted. Needs at
                                   most 4096 domains in the instance.              */
+  int32_t transform;           /* LETKF_TRANSFORM_* (same for all instances);
+                                  0 = NS64                                         */
 } letkf_config;
 
 /* Sizes of one instance (or totals when instance = -1). */
@@ -177,7 +202,8 @@ int letkf_set_frame(letkf_handle *h, uint32_t frame);
 
 /* Per-domain status bits of the last analysis, in work-list order mapped back
  * to (instance, domain): flags[sum of domains].  Synchronous.  Returns
- * LETKF_E_NOCONV / LETKF_E_NONFINITE when any bit is set, else LETKF_OK. */
+ * LETKF_E_NONFINITE / LETKF_E_NOCONV when a domain has that bit set, else
+ * LETKF_OK. */
 int letkf_status(letkf_handle *h, int32_t *flags);
 
 /* Change rho, r_scale and taper_c of one instance (tuning runs). */

@@ -27,6 +27,7 @@ lib = C.CDLL(LIB_PATH)
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6
 FP32, FP64 = 0, 1
 FLAG_NONFINITE, FLAG_NOCONV = 1, 2
+TRANSFORM_NS64, TRANSFORM_NS32, TRANSFORM_EVD = 0, 1, 2
 
 
 class Config(C.Structure):
@@ -51,6 +52,7 @@ class Config(C.Structure):
         ("jacobi_tol", C.c_double),
         ("max_sweeps", C.c_int32),
         ("piston_removal", C.c_int32),
+        ("transform", C.c_int32),
     ]
 
 
@@ -144,6 +146,7 @@ class InstanceSpec:
     jacobi_tol: float = 0.0
     max_sweeps: int = 0
     piston: bool = False                  # differential-piston removal after the gather
+    transform: int = TRANSFORM_NS64       # how W, w come from A~ (NS64, NS32 or the Jacobi EVD)
 
 
 def _config(spec: InstanceSpec, keep: list) -> Config:
@@ -177,6 +180,7 @@ def _config(spec: InstanceSpec, keep: list) -> Config:
     c.jacobi_tol = spec.jacobi_tol
     c.max_sweeps = spec.max_sweeps
     c.piston_removal = 1 if spec.piston else 0
+    c.transform = spec.transform
     return c
 
 

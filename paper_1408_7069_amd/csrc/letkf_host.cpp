@@ -30,11 +30,9 @@
 
 using namespace letkf;
 
-extern "C" hipError_t letkf_launch_analysis_f32(const void *args, int fused, int grid, size_t lds,
-                                                hipStream_t s);
-extern "C" hipError_t letkf_launch_analysis_f64(const void *args, int fused, int grid, size_t lds,
-                                                hipStream_t s);
-extern "C" const void *letkf_analysis_kernel(int fp64, int fused);
+extern "C" hipError_t letkf_launch_analysis(const void *args, int fp64, int fused, int eig, int grid,
+                                            size_t lds, hipStream_t s);
+extern "C" const void *letkf_analysis_kernel(int fp64, int fused, int eig);
 extern "C" hipError_t letkf_launch_forecast(int fp64, const InstDesc *insts, int n_inst,
                                             const int32_t *node_ij, const void *xa, const void *v,
                                             const float *bank, const uint32_t *frame, void *xb,
@@ -189,6 +187,7 @@ struct letkf_handle {
   bool any_bank = false, all_bank = true;
   double jtol = 0.0;
   int max_sweeps = 30;
+  int transform = LETKF_TRANSFORM_NS64;  // forward transform (FP64 handles: never NS32)
   size_t lds = 0;
   int32_t off[9] = {0};      // LDS layout of the adjoint's forward stages
   int32_t fwd_off[9] = {0};  // LDS layout of the analysis
@@ -613,10 +612,10 @@ int launch_analysis(letkf_handle *h, bool fused, const void *V, const void *y, i
                     hipStream_t s) {
   if (h->fp64) {
     auto A = make_args<double>(h, fused, V, y, xa_in, xa_out);
-    HIPCHK(letkf_launch_analysis_f64(&A, fused, grid_for(h), h->lds, s));
+    HIPCHK(letkf_launch_analysis(&A, 1, fused, h->transform, grid_for(h), h->lds, s));
   } else {
     auto A = make_args<float>(h, fused, V, y, xa_in, xa_out);
-    HIPCHK(letkf_launch_analysis_f32(&A, fused, grid_for(h), h->lds, s));
+    HIPCHK(letkf_launch_analysis(&A, 0, fused, h->transform, grid_for(h), h->lds, s));
   }
   return LETKF_OK;
 }
@@ -642,7 +641,7 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
   hipKernelNodeParams kp{};
   kp.blockDim = dim3(letkf_analysis_threads());
   kp.gridDim = dim3(grid_for(h));
-  kp.func = (void *)letkf_analysis_kernel(h->fp64, 1);
+  kp.func = (void *)letkf_analysis_kernel(h->fp64, 1, h->transform);
   kp.sharedMemBytes = (unsigned)h->lds;
   // piston nodes: the right-hand side reads y; solve and apply do not
   std::vector<unsigned char> prhs, pfix;
@@ -751,7 +750,12 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     if (validate(cfgs[i], i, err) != LETKF_OK) return fail(LETKF_E_INVAL, err);
     if (cfgs[i].precision != cfgs[0].precision)
       return fail(LETKF_E_INVAL, "all instances of a handle must share the precision");
+    if (cfgs[i].transform != cfgs[0].transform)
+      return fail(LETKF_E_INVAL, "all instances of a handle must share the transform");
   }
+  if (cfgs[0].transform != LETKF_TRANSFORM_NS64 && cfgs[0].transform != LETKF_TRANSFORM_NS32 &&
+      cfgs[0].transform != LETKF_TRANSFORM_EVD)
+    return fail(LETKF_E_INVAL, "unknown transform");
   letkf_handle *h = new letkf_handle();
   h->device = device;
   h->fp64 = cfgs[0].precision == LETKF_FP64;
@@ -759,6 +763,8 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   h->n_inst = n_instances;
   h->jtol = cfgs[0].jacobi_tol > 0 ? cfgs[0].jacobi_tol : (h->fp64 ? 1e-10 : 1e-4);
   h->max_sweeps = cfgs[0].max_sweeps > 0 ? cfgs[0].max_sweeps : 30;
+  h->transform = cfgs[0].transform;
+  if (h->fp64 && h->transform == LETKF_TRANSFORM_NS32) h->transform = LETKF_TRANSFORM_NS64;
   h->geom.resize(n_instances);
   std::vector<int32_t> patch, obs_sub, node_ij, subap_nodes;
   std::vector<uint32_t> obs_corner;
@@ -866,7 +872,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     // ones (rows 0 .. n_own - 1) outlive stage 2; the others run on into the U
     // area, which holds A~ and then the two FP64 64 x 64 matrices of its inverse
     // square root from stage 3 on; the slopes operand ys of stages 2-3 sits at
-    // the end of U, clear of those rows.  FP32 at 80x80, m = 64: 78 KB, under
+    // the end of U, clear of those rows.  FP32 at 80x80, m = 64: 79.7 KB, under
     // 80 KiB: two workgroups per CU.
     size_t f = 0;
     h->fwd_off[1] = (int32_t)f; f = align16(f + 64 * T);
@@ -874,14 +880,21 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     h->fwd_off[3] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * 8);
     h->fwd_off[4] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * T);
     h->fwd_off[5] = (int32_t)f; f = align16(f + 128 * 4);
-    h->fwd_off[6] = (int32_t)f; f = align16(f + letkf_analysis_fwd_scratch_doubles() * 8);
+    // (the Jacobi transform uses the whole scratch, the Newton-Schulz ones its head)
+    const size_t scratch = h->transform == LETKF_TRANSFORM_EVD ? letkf_analysis_scratch_doubles()
+                                                               : letkf_analysis_fwd_scratch_doubles();
+    h->fwd_off[6] = (int32_t)f; f = align16(f + scratch * 8);
     h->fwd_off[0] = (int32_t)f;
     const size_t ub = align16(f + (size_t)h->max_own * kXsStride * T);
     const size_t rows_end = f + (size_t)h->max_patch * kXsStride * T;  // end of the patch rows
     const size_t ys_bytes = p4 * kYsStride * T;
     const size_t spill = rows_end > ub ? align16(rows_end - ub) : 0;
-    // FP64: the iterates overwrite A~; FP32: A~ (FP64) and two FP32 iterates (row stride 68)
-    const size_t iter_bytes = T == 8 ? (size_t)2 * 64 * 65 * 8 : (size_t)64 * 65 * 8 + 2 * 64 * 68 * 4;
+    // Newton-Schulz in FP64: A~, then the two FP64 iterates; with FP32
+    // iterates: three of them and the FP32 Gram (row stride 68); Jacobi: A~
+    // and its factor (the block exchange and W reuse the area)
+    const size_t iter_bytes = h->transform == LETKF_TRANSFORM_NS32   ? (size_t)4 * 64 * 68 * 4
+                              : h->transform == LETKF_TRANSFORM_EVD ? std::max(u, (size_t)64 * 65 * 8)
+                                                                    : (size_t)2 * 64 * 65 * 8;
     const size_t uf = std::max(iter_bytes, spill + ys_bytes);
     h->fwd_off[7] = (int32_t)ub;
     h->fwd_off[8] = (int32_t)(ub + uf - ys_bytes);
@@ -964,7 +977,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     return fail(LETKF_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
   }
   for (int fused = 0; fused < 2; ++fused)
-    hipFuncSetAttribute(letkf_analysis_kernel(h->fp64, fused),
+    hipFuncSetAttribute(letkf_analysis_kernel(h->fp64, fused, h->transform),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
   {
     int max_lds = 0;
@@ -1172,12 +1185,12 @@ int letkf_step_plain(letkf_handle *h, const void *V_dev, const void *y_dev, void
       auto A = make_args<double>(h, true, V_dev, y_dev, h->cur, 1 - h->cur);
       A.item_base = i;
       A.xcd_order = 0;
-      HIPCHK(letkf_launch_analysis_f64(&A, 1, 1, h->lds, s));
+      HIPCHK(letkf_launch_analysis(&A, 1, 1, h->transform, 1, h->lds, s));
     } else {
       auto A = make_args<float>(h, true, V_dev, y_dev, h->cur, 1 - h->cur);
       A.item_base = i;
       A.xcd_order = 0;
-      HIPCHK(letkf_launch_analysis_f32(&A, 1, 1, h->lds, s));
+      HIPCHK(letkf_launch_analysis(&A, 0, 1, h->transform, 1, h->lds, s));
     }
   }
   if ((rc = launch_frame_tail(h, y_dev, h->d_xa[1 - h->cur], h->d_frame, s))) return rc;

@@ -590,6 +590,19 @@ __device__ inline void syrk_store_f64(const typename Mfma<T>::V acc[3], double *
   }
 }
 
+// sum_j a[j] v[j] over 64 terms in FP64 (four independent chains)
+template <typename TA> __device__ inline double dot64(const TA *a, const double *v) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+  for (int j = 0; j < 64; j += 4) {
+    s0 = fma((double)a[j], v[j], s0);
+    s1 = fma((double)a[j + 1], v[j + 1], s1);
+    s2 = fma((double)a[j + 2], v[j + 2], s2);
+    s3 = fma((double)a[j + 3], v[j + 3], s3);
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
 // ------------------------------------------- inverse square root (MFMA)
 // Column block of an FP64 64 x 64 matrix held by one wave: columns
 // 16 q .. 16 q + 15 as four 16x16 accumulator tiles of the FP64 16x16x4 MFMA
@@ -727,12 +740,14 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
 // 16 I + 4 (lane / 16) + r, column 16 q + lane % 16); FP32 matrices in LDS
 // with row stride kNs32Stride (left-operand reads fall in distinct banks).
 constexpr int kNs32Stride = 68;
+constexpr int kNsGOff = 3 * 64 * kNs32Stride;  // G after the three FP32 iterates (floats)
 typedef f32x4 ColBlock32[4];
 
-// Right-operand form of one accumulator tile: the tile's element (4 g + r, c)
-// sits in lane (g, c), register r; the FP32 MFMA's step kk reads element
-// (4 kk + g, c) in lane (g, c).  A 4 x 4 transpose of (lane group, register):
-// v_permlane32_swap exchanges bit 1 of the two, v_permlane16_swap bit 0.
+// 4 x 4 transpose of (lane group, register): out[g][i] = in[i][g] for the
+// four 16-lane groups g; v_permlane32_swap exchanges bit 1 of the two indices,
+// v_permlane16_swap bit 0.  Applied to one accumulator tile (element (4 g + r,
+// c) in lane (g, c), register r) it gives the right-operand form of the FP32
+// MFMA, whose step kk reads element (4 kk + g, c) in lane (g, c).
 __device__ inline f32x4 tile_to_rhs(f32x4 v) {
   auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[0]), __float_as_uint(v[2]), false, false);
   auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[1]), __float_as_uint(v[3]), false, false);
@@ -741,21 +756,37 @@ __device__ inline f32x4 tile_to_rhs(f32x4 v) {
   return f32x4{__uint_as_float(c[0]), __uint_as_float(c[1]), __uint_as_float(d[0]), __uint_as_float(d[1])};
 }
 
+// C = M B for the wave's column block, with the contraction index permuted:
+// step kk of lane group g takes k = 16 g + kk (the sum is over all 64 k in
+// any order), so each lane's left operand of a tile is 16 consecutive floats
+// of one row (four 16-byte LDS reads, all issued before the products), and
+// its right operand is row 16 g + kk of the column block: element kk % 4 of
+// tile g in lane group kk / 4, a (lane group, tile) transpose per register.
 __device__ inline void mm_colblock32(const float *M, const ColBlock32 &B, ColBlock32 &C, int lane) {
-  const int c16 = lane & 15, k4 = lane >> 4;
-  f32x4 Bt[4];
+  const int c16 = lane & 15, g = lane >> 4;
+  f32x4 Av[4][4];
 #pragma unroll
-  for (int I = 0; I < 4; ++I) {
-    Bt[I] = tile_to_rhs(B[I]);
-    C[I] = Mfma<float>::zero();
+  for (int I = 0; I < 4; ++I)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      Av[I][t] = *(const f32x4 *)(M + (16 * I + c16) * kNs32Stride + 16 * g + 4 * t);
+  f32x4 Bt[4];  // Bt[a][r]: step 4 a + r
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const f32x4 v = tile_to_rhs(f32x4{B[0][r], B[1][r], B[2][r], B[3][r]});
+#pragma unroll
+    for (int a = 0; a < 4; ++a) Bt[a][r] = v[a];
   }
 #pragma unroll
-  for (int kk = 0; kk < 16; ++kk) {
-    const float b = Bt[kk >> 2][kk & 3];
+  for (int I = 0; I < 4; ++I) C[I] = Mfma<float>::zero();
 #pragma unroll
-    for (int I = 0; I < 4; ++I)
-      C[I] = Mfma<float>::mac(M[(16 * I + c16) * kNs32Stride + 4 * kk + k4], b, C[I]);
-  }
+  for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+    for (int I = 0; I < 4; ++I) C[I] = Mfma<float>::mac(Av[I][kk >> 2][kk & 3], Bt[kk >> 2][kk & 3], C[I]);
+  // issue order: the 16 LDS reads, the transposes, then the 64 products
+  __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
+  __builtin_amdgcn_sched_group_barrier(0x002, 64, 0);
+  __builtin_amdgcn_sched_group_barrier(0x008, 64, 0);
 }
 
 __device__ inline void store_colblock32(float *M, const ColBlock32 &B, int q, int lane) {
@@ -766,10 +797,14 @@ __device__ inline void store_colblock32(float *M, const ColBlock32 &B, int q, in
       M[(16 * I + 4 * (lane >> 4) + r) * kNs32Stride + 16 * q + (lane & 15)] = B[I][r];
 }
 
-// ns_isqrt in FP32: A (FP64 in LDS, stride kLaStride) is read, not written;
-// Yb, Zb are FP32 64 x 64 areas.  The residual is summed in FP64.
-__device__ inline IsqrtStatus ns_isqrt32(const double *A, float *Yb, float *Zb, double *sm, double lmin,
-                                         double tol, int max_it, ColBlock32 &Zc, int q, int lane) {
+// ns_isqrt in FP32 for A = c I + G, with G (FP32, in LDS) exact: the Gram of
+// the FP32 products.  Three FP32 areas hold Y, Z and T; T gets its own so that
+// it is written as soon as it is formed, Z is overwritten once the products
+// that read it are done, and Y (read only by the second pair of products)
+// after the next barrier: two barriers a step.  The residual is summed in
+// FP64.
+__device__ inline IsqrtStatus ns_isqrt32(const float *G, float *Yb, float *Zb, float *Tb, double *sm,
+                                         double c, double tol, int max_it, ColBlock32 &Zc, int q, int lane) {
   const int col = 16 * q + (lane & 15), g4 = 4 * (lane >> 4);
   ColBlock32 Yc, Tc;
   double ss = 0.0;
@@ -777,40 +812,40 @@ __device__ inline IsqrtStatus ns_isqrt32(const double *A, float *Yb, float *Zb, 
   for (int I = 0; I < 4; ++I)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const double v = A[(16 * I + g4 + r) * kLaStride + col];
-      Yc[I][r] = (float)v;
-      ss = fma(v, v, ss);
+      const float v = G[(16 * I + g4 + r) * kNs32Stride + col];
+      const double a = (double)v + (16 * I + g4 + r == col ? c : 0.0);
+      Yc[I][r] = v;
+      ss = fma(a, a, ss);
     }
   ss = wave_sum(ss);
   if (lane == 0) sm[S_RES + q] = ss;
-  store_colblock32(Yb, Yc, q, lane);  // A in FP32, the left operand of the first product
   __syncthreads();
   const double s = sqrt(sum4(sm + S_RES));
-  double l = lmin / s;
+  double l = c / s;
+  // k = 0 (Z_0 = I): T_0 = (3 I - a A / s) / 2, Z_1 = sqrt(a) T_0,
+  // Y_1 = sqrt(a) / s (G T_0 + c T_0)
   double al = 3.0 / (1.0 + sqrt(l) + l);
   float sa = (float)sqrt(al);
-  const float as = (float)(al / s);
+  const float as = (float)(al / s), cf = (float)c;
 #pragma unroll
   for (int I = 0; I < 4; ++I)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const bool dg = 16 * I + g4 + r == col;
-      Tc[I][r] = 0.5f * ((dg ? 3.0f : 0.0f) - as * Yc[I][r]);
+      Tc[I][r] = 0.5f * ((dg ? 3.0f : 0.0f) - as * (Yc[I][r] + (dg ? cf : 0.0f)));
       Zc[I][r] = sa * Tc[I][r];
     }
-  mm_colblock32(Yb, Tc, Yc, lane);
+  mm_colblock32(G, Tc, Yc, lane);
   const float ys = (float)(sqrt(al) / s);
 #pragma unroll
-  for (int I = 0; I < 4; ++I) Yc[I] *= ys;
+  for (int I = 0; I < 4; ++I) Yc[I] = (Yc[I] + Tc[I] * cf) * ys;
   l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
+  store_colblock32(Yb, Yc, q, lane);
+  store_colblock32(Zb, Zc, q, lane);
+  __syncthreads();
   int it = 1;
   bool conv = false, finite = true;
-  for (;;) {
-    __syncthreads();  // every read of Yb and Zb of the last step is done
-    if (!conv) store_colblock32(Yb, Yc, q, lane);
-    store_colblock32(Zb, Zc, q, lane);
-    __syncthreads();
-    if (conv || !finite || it >= max_it) break;
+  while (it < max_it) {
     al = 3.0 / (1.0 + sqrt(l) + l);
     sa = (float)sqrt(al);
     const float alf = (float)al;
@@ -827,24 +862,47 @@ __device__ inline IsqrtStatus ns_isqrt32(const double *A, float *Yb, float *Zb, 
       }
     e2 = wave_sum(e2);
     if (lane == 0) sm[S_RES + q] = e2;
-    __syncthreads();  // every read of Zb (as Z) is done
-    store_colblock32(Zb, Tc, q, lane);
-    __syncthreads();
+    store_colblock32(Tb, Tc, q, lane);
+    __syncthreads();  // T complete; every read of Zb is done
     const double d2 = sum4(sm + S_RES);
     finite = isfinite(d2);
     conv = finite && 0.75 * d2 <= tol;
     ColBlock32 Zn;
     if (!conv) mm_colblock32(Yb, Tc, Yc, lane);  // Y T (the last step needs only Z)
-    mm_colblock32(Zb, Zc, Zn, lane);             // T Z
+    mm_colblock32(Tb, Zc, Zn, lane);             // T Z
 #pragma unroll
-    for (int I = 0; I < 4; ++I) {
-      Yc[I] *= sa;
-      Zc[I] = Zn[I] * sa;
-    }
+    for (int I = 0; I < 4; ++I) Zc[I] = Zn[I] * sa;
+    store_colblock32(Zb, Zc, q, lane);
+    __syncthreads();  // Z complete; every read of Yb and Tb is done
     l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
     ++it;
+    if (conv || !finite) break;
+#pragma unroll
+    for (int I = 0; I < 4; ++I) Yc[I] *= sa;
+    store_colblock32(Yb, Yc, q, lane);  // read after the next barrier
   }
   return IsqrtStatus{conv ? it : -it, finite, s};
+}
+
+// Row i of M x (M: 64 x 64 FP32 in LDS, row stride kNs32Stride; x: FP64 in
+// LDS) for i = 16 q + lane / 4: four lanes a row, 16 terms each, summed over
+// the quad (the result is in all four lanes).
+__device__ inline double matvec_quad(const float *M, const double *x, int q, int lane) {
+  const int i = 16 * q + (lane >> 2), t = lane & 3;
+  const float *mr = M + i * kNs32Stride + 16 * t;
+  const double *xr = x + 16 * t;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+  for (int j = 0; j < 16; j += 4) {
+    s0 = fma((double)mr[j], xr[j], s0);
+    s1 = fma((double)mr[j + 1], xr[j + 1], s1);
+    s2 = fma((double)mr[j + 2], xr[j + 2], s2);
+    s3 = fma((double)mr[j + 3], xr[j + 3], s3);
+  }
+  double v = (s0 + s1) + (s2 + s3);
+  v += dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]
+  return v;
 }
 
 template <typename T> struct AnaArgs {
@@ -885,12 +943,13 @@ __device__ inline int xcd_item(int b, int grid) {
 // kYsStride) at the start of the U area.
 struct CoreStatus {
   bool bad, conv, lam_ok;
+  int sweeps;  // Jacobi sweeps begun
 };
 
 // Stages 1-3: on return A~ = c I + Yt^T Yt (FP64, both triangles) at the start
 // of the U area, b = Yt^T sqrt(g) d in sm[S_VEC]; returns whether an
 // observation was not finite.
-template <typename T, bool FUSED>
+template <typename T, bool FUSED, bool G32 = false>
 __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &it, const InstDesc &in,
                                            uint32_t frame, unsigned char *smem) {
   const int tid = threadIdx.x;
@@ -1004,9 +1063,14 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
   typename Mfma<T>::V acc[3];
   syrk_share<T>(ys, kYsStride, p4 / 4, acc, q, lane);
   __syncthreads();
-  const double c = (double)(m - 1) / in.rho;
-  double *La = (double *)U;  // A~ = c I + Y^T Y in FP64, then its Cholesky factor
-  syrk_store_f64<T>(acc, La, c, q, lane);
+  if constexpr (G32) {
+    // G = Yt^T Yt as the FP32 products left it (exact), row stride kNs32Stride
+    syrk_store<T>(acc, (T *)U + kNsGOff, kNs32Stride, (T)1, q, lane);
+  } else {
+    const double c = (double)(m - 1) / in.rho;
+    double *La = (double *)U;  // A~ = c I + Y^T Y in FP64, then its Cholesky factor
+    syrk_store_f64<T>(acc, La, c, q, lane);
+  }
   __syncthreads();
   return bad != 0;
 }
@@ -1057,11 +1121,16 @@ __device__ __forceinline__ CoreStatus analysis_core(const AnaArgs<T> &A, const D
   T *wmat = ut;  // W row-major [64][kYsStride]
   syrk_store<T>(acc, wmat, kYsStride, (T)sqrt(c), q, lane);
   __syncthreads();
-  return CoreStatus{bad, conv, lam_ok};
+  return CoreStatus{bad, conv, lam_ok, sweeps > 0 ? sweeps : -sweeps};
 }
 
-template <typename T, bool FUSED>
-__global__ __launch_bounds__(kThreads) void k_analysis(const AnaArgs<T> A) {
+// Transform of the analysis (stages 4-6): the inverse square root by the
+// Newton-Schulz iteration in FP64 (default) or with FP32 iterates, or the
+// symmetric eigendecomposition by the one-sided Jacobi.
+constexpr int kEigNs64 = 0, kEigNs32 = 1, kEigJacobi = 2;
+
+template <typename T, bool FUSED, int EIG>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_analysis(const AnaArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int q = tid >> 6, lane = tid & 63;
@@ -1076,77 +1145,84 @@ __global__ __launch_bounds__(kThreads) void k_analysis(const AnaArgs<T> A) {
   T *xm = (T *)(smem + A.off_xm);
   int *pn = (int *)(smem + A.off_pn);
   double *sm = (double *)(smem + A.off_s);
-  double *Yb = (double *)(smem + A.off_u);  // A~, then the iteration's two matrices
-  double *Zb = Yb + 64 * kLaStride;
   const uint32_t frame = (FUSED && A.noise_bank) ? *A.frame : 0u;
-  const bool bad = stage_gram<T, FUSED>(A, it, in, frame, smem);
-
-  // ---- 4. Z = (A~ / s)^{-1/2} on the matrix cores (eigenvalues >= c) ----
-  // ---- 5. w = A~^{-1} b = Z (Z b) / s (wave 0, lane = row) ----
   const double c = (double)(m - 1) / in.rho;
-  IsqrtStatus st;
-  T wf[16];  // this wave's column block of Z, right-operand layout of the update
-  if constexpr (sizeof(T) == 4) {
-    // FP32 iterates; A~ stays in FP64 for one refinement of w, which carries
-    // the mean (w = w0 + Z (Z (b - A~ w0)) / s)
-    float *Y32 = (float *)(Yb + 64 * kLaStride);
-    float *Z32 = Y32 + 64 * kNs32Stride;
-    ColBlock32 Zc;
-    st = ns_isqrt32(Yb, Y32, Z32, sm, c, A.jtol * 0.01, A.max_sweeps, Zc, q, lane);
-    if (q == 0) {
-      const float *zr = Z32 + lane * kNs32Stride;
-      double u = 0.0;
-      for (int j = 0; j < 64; ++j) u = fma((double)zr[j], sm[S_VEC + j], u);
-      sm[S_COL + lane] = u;
-      wave_sync();
-      double w0 = 0.0;
-      for (int j = 0; j < 64; ++j) w0 = fma((double)zr[j], sm[S_COL + j], w0);
-      w0 /= st.s;
-      sm[S_WV + lane] = w0;
-      wave_sync();
-      double r = sm[S_VEC + lane];
-      for (int j = 0; j < 64; ++j) r = fma(-Yb[lane * kLaStride + j], sm[S_WV + j], r);
-      sm[S_COL + 64 + lane] = r;
-      wave_sync();
-      double u2 = 0.0;
-      for (int j = 0; j < 64; ++j) u2 = fma((double)zr[j], sm[S_COL + 64 + j], u2);
-      sm[S_COL + lane] = u2;
-      wave_sync();
-      double dw = 0.0;
-      for (int j = 0; j < 64; ++j) dw = fma((double)zr[j], sm[S_COL + j], dw);
-      sm[S_WV + lane] = w0 + dw / st.s;
-    }
-    const float wsc = (float)sqrt(c / st.s);
-#pragma unroll
-    for (int I = 0; I < 4; ++I) {
-      const f32x4 bt = tile_to_rhs(Zc[I]);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) wf[4 * I + r] = wsc * bt[r];
-    }
-  } else {
-    ColBlock Zc;
-    st = ns_isqrt(Yb, Zb, sm, c, A.jtol * 0.01, A.max_sweeps, Zc, q, lane);
-    if (q == 0) {
-      double u = 0.0;
-      for (int j = 0; j < 64; ++j) u = fma(Zb[lane * kLaStride + j], sm[S_VEC + j], u);
-      sm[S_COL + lane] = u;
-      wave_sync();
-      double w = 0.0;
-      for (int j = 0; j < 64; ++j) w = fma(Zb[lane * kLaStride + j], sm[S_COL + j], w);
-      sm[S_WV + lane] = w / st.s;
-    }
-    const double wsc = sqrt(c / st.s);
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) wf[kk] = (T)(wsc * Zc[kk >> 2][kk & 3]);
-  }
-  const bool conv = st.iters > 0;
-  __syncthreads();
+  bool bad, conv;
+  int flag;
+  T wf[16];  // this wave's column block of W, right-operand layout of the update
 
-  // ---- 6./7. owned rows: X_a = (x_b + X' w) 1^T + sqrt(rho) X' W with
-  // W = sqrt(c) A~^{-1/2} = sqrt(c / s) Z: this wave's members are Z's column
-  // block, already in the right-operand layout of the update's MFMA ----
+  if constexpr (EIG == kEigJacobi) {
+    // ---- 1.-6. staging, Gram, Cholesky and w, Jacobi, W in LDS ----
+    double X[8], Y[8];
+    const CoreStatus cs = analysis_core<T, FUSED>(A, it, in, frame, smem, X, Y);
+    bad = cs.bad || !cs.lam_ok;
+    conv = cs.conv;
+    flag = (bad ? 1 : 0) | (conv ? 0 : 2) | (min(cs.sweeps, 255) << 8);
+    const T *wmat = (const T *)(smem + A.off_u);
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) wf[kk] = wmat[(4 * kk + (lane >> 4)) * kYsStride + 16 * q + (lane & 15)];
+  } else {
+    bad = stage_gram<T, FUSED, EIG == kEigNs32>(A, it, in, frame, smem);
+    // ---- 4. Z = (A~ / s)^{-1/2} on the matrix cores (eigenvalues >= c) ----
+    // ---- 5. w = A~^{-1} b = Z (Z b) / s ----
+    IsqrtStatus st;
+    if constexpr (EIG == kEigNs32) {
+      // FP32 iterates; the exact FP32 Gram G gives A~ = c I + G for one FP64
+      // refinement of w, which carries the mean: w = w0 + Z (Z (b - A~ w0)) / s
+      float *Y32 = (float *)(smem + A.off_u);
+      float *Z32 = Y32 + 64 * kNs32Stride, *T32 = Z32 + 64 * kNs32Stride;
+      const float *G32 = Y32 + kNsGOff;
+      ColBlock32 Zc;
+      st = ns_isqrt32(G32, Y32, Z32, T32, sm, c, A.jtol * 0.01, A.max_sweeps, Zc, q, lane);
+      const int i = 16 * q + (lane >> 2);
+      const bool lead = (lane & 3) == 0;
+      const double u = matvec_quad(Z32, sm + S_VEC, q, lane);
+      if (lead) sm[S_COL + i] = u;
+      __syncthreads();
+      const double w0 = matvec_quad(Z32, sm + S_COL, q, lane) / st.s;
+      if (lead) sm[S_WV + i] = w0;
+      __syncthreads();
+      const double r = sm[S_VEC + i] - c * w0 - matvec_quad(G32, sm + S_WV, q, lane);
+      if (lead) sm[S_COL + 64 + i] = r;
+      __syncthreads();
+      const double u2 = matvec_quad(Z32, sm + S_COL + 64, q, lane);
+      if (lead) sm[S_COL + i] = u2;
+      __syncthreads();
+      const double dw = matvec_quad(Z32, sm + S_COL, q, lane) / st.s;
+      if (lead) sm[S_WV + i] = w0 + dw;
+      const float wsc = (float)sqrt(c / st.s);
+#pragma unroll
+      for (int I = 0; I < 4; ++I) {
+        const f32x4 bt = tile_to_rhs(Zc[I]);
+#pragma unroll
+        for (int r2 = 0; r2 < 4; ++r2) wf[4 * I + r2] = (T)(wsc * bt[r2]);
+      }
+    } else {
+      double *Yb = (double *)(smem + A.off_u);  // A~, then the iteration's two matrices
+      double *Zb = Yb + 64 * kLaStride;
+      ColBlock Zc;
+      st = ns_isqrt(Yb, Zb, sm, c, A.jtol * 0.01, A.max_sweeps, Zc, q, lane);
+      if (q == 0) {
+        sm[S_COL + lane] = dot64(Zb + lane * kLaStride, sm + S_VEC);
+        wave_sync();
+        sm[S_WV + lane] = dot64(Zb + lane * kLaStride, sm + S_COL) / st.s;
+      }
+      // W = sqrt(c) A~^{-1/2} = sqrt(c / s) Z: this wave's members are Z's
+      // column block, already in the right-operand layout of the update
+      const double wsc = sqrt(c / st.s);
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) wf[kk] = (T)(wsc * Zc[kk >> 2][kk & 3]);
+    }
+    conv = st.iters > 0;
+    flag = (bad || !st.finite ? 1 : 0) | (conv || !st.finite ? 0 : 2) |
+           (min(st.iters > 0 ? st.iters : -st.iters, 255) << 8);
+    bad = bad || !st.finite;
+    __syncthreads();
+  }
+
+  // ---- 7. owned rows: X_a = (x_b + X' w) 1^T + sqrt(rho) X' W ----
   const bool keep_forecast = bad || !conv;
-  if (tid == 0) A.flags[item] = (bad || !st.finite ? 1 : 0) | (conv || !st.finite ? 0 : 2);
+  if (tid == 0) A.flags[item] = flag;
   if (tid < nown) {
     const double mu = (double)xm[tid];
     double s = mu;
@@ -1880,29 +1956,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 // Launch wrappers called by the host side.
 using namespace letkf;
 
-extern "C" hipError_t letkf_launch_analysis_f32(const void *args, int fused, int grid,
-                                                size_t lds, hipStream_t s) {
-  const AnaArgs<float> &A = *(const AnaArgs<float> *)args;
-  if (fused)
-    hipLaunchKernelGGL((k_analysis<float, true>), dim3(grid), dim3(kThreads), lds, s, A);
-  else
-    hipLaunchKernelGGL((k_analysis<float, false>), dim3(grid), dim3(kThreads), lds, s, A);
-  return hipGetLastError();
+template <typename T> static const void *analysis_kernel_of(int fused, int eig) {
+  if (eig == kEigJacobi)
+    return fused ? (const void *)k_analysis<T, true, kEigJacobi> : (const void *)k_analysis<T, false, kEigJacobi>;
+  if (eig == kEigNs32 && sizeof(T) == 4)
+    return fused ? (const void *)k_analysis<T, true, kEigNs32> : (const void *)k_analysis<T, false, kEigNs32>;
+  return fused ? (const void *)k_analysis<T, true, kEigNs64> : (const void *)k_analysis<T, false, kEigNs64>;
 }
 
-extern "C" hipError_t letkf_launch_analysis_f64(const void *args, int fused, int grid,
-                                                size_t lds, hipStream_t s) {
-  const AnaArgs<double> &A = *(const AnaArgs<double> *)args;
-  if (fused)
-    hipLaunchKernelGGL((k_analysis<double, true>), dim3(grid), dim3(kThreads), lds, s, A);
-  else
-    hipLaunchKernelGGL((k_analysis<double, false>), dim3(grid), dim3(kThreads), lds, s, A);
-  return hipGetLastError();
+extern "C" const void *letkf_analysis_kernel(int fp64, int fused, int eig) {
+  return fp64 ? analysis_kernel_of<double>(fused, eig) : analysis_kernel_of<float>(fused, eig);
 }
 
-extern "C" const void *letkf_analysis_kernel(int fp64, int fused) {
-  if (fp64) return fused ? (const void *)k_analysis<double, true> : (const void *)k_analysis<double, false>;
-  return fused ? (const void *)k_analysis<float, true> : (const void *)k_analysis<float, false>;
+extern "C" hipError_t letkf_launch_analysis(const void *args, int fp64, int fused, int eig, int grid,
+                                            size_t lds, hipStream_t s) {
+  void *kargs[] = {(void *)args};
+  return hipLaunchKernel(letkf_analysis_kernel(fp64, fused, eig), dim3(grid), dim3(kThreads), kargs, lds, s);
 }
 
 extern "C" int letkf_analysis_threads(void) { return kThreads; }

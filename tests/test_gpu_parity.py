@@ -36,11 +36,21 @@ def _frame_vs_oracle(case, f, Xa_prev, V, y):
     return got, ref
 
 
-@pytest.mark.parametrize("fp64,tol", [(True, 1e-10), (False, 1e-4)])
-def test_smallest_workload_frames(fp64, tol):
+TRANSFORMS = ["ns64", "ns32", "evd"]
+
+
+def _tr(name):
+    bb = B()
+    return {"ns64": bb.TRANSFORM_NS64, "ns32": bb.TRANSFORM_NS32, "evd": bb.TRANSFORM_EVD}[name]
+
+
+@pytest.mark.parametrize("fp64,tol,transform", [(True, 1e-10, "ns64"), (True, 1e-10, "evd"),
+                                                (False, 1e-4, "ns64"), (False, 1e-4, "ns32"),
+                                                (False, 1e-4, "evd")])
+def test_smallest_workload_frames(fp64, tol, transform):
     # 8x8 square pupil, 2x2 domains, halo 1, m = 20 (16 domains)
     case = Case(8, None, 2, 1, 20, seed=1, fp64=fp64, pitch=0.4)
-    f = B().Letkf([case.spec(B())])
+    f = B().Letkf([case.spec(B(), transform=_tr(transform))])
     Xa = np.zeros((case.G.n_nodes, case.m))
     for k in range(6):
         V, y = case.noise(), case.slopes(case.truth())
@@ -49,7 +59,8 @@ def test_smallest_workload_frames(fp64, tol):
         assert rel_err(got, ref) <= tol, k
         Xa = ref
     rc, flags = f.status()
-    assert rc == 0 and not flags.any()
+    assert rc == 0 and not (flags & 3).any()
+    assert ((flags >> 8) > 0).all()  # the transform's step count
 
 
 @pytest.mark.parametrize("fp64,tol", [(True, 1e-10), (False, 1e-4)])
@@ -124,12 +135,13 @@ def test_fused_step_with_bank_noise():
         Xa = ref
 
 
-def test_full_size_80x80_m64_in_the_timed_configuration():
+@pytest.mark.parametrize("transform", TRANSFORMS)
+def test_full_size_80x80_m64_in_the_timed_configuration(transform):
     # the benchmark shape (4632 subapertures, 4836 nodes, 332 domains), graph
     # replay with the XCD-ordered work list, compared domain by domain
     case = Case(80, 0.28, 4, 1, 64, seed=7)
     bb = B()
-    f = bb.Letkf([case.spec(bb)])
+    f = bb.Letkf([case.spec(bb, transform=_tr(transform))])
     f.set_schedule(True, True)
     assert f.sizes["n_domains"] == 332 and f.sizes["n_nodes"] == 4836
     Xa = np.zeros((case.G.n_nodes, case.m))
@@ -146,11 +158,12 @@ def test_full_size_80x80_m64_in_the_timed_configuration():
         Xa = ref
 
 
-def test_many_instances_in_one_launch():
+@pytest.mark.parametrize("transform", TRANSFORMS)
+def test_many_instances_in_one_launch(transform):
     bb = B()
     cases = [Case(16, 0.0, 4, 1, 32, seed=10), Case(23, 0.14, 4, 1, 48, seed=11),
              Case(12, 0.28, 4, 1, 64, seed=12), Case(9, None, 3, 1, 20, seed=13)]
-    f = bb.Letkf([c.spec(bb) for c in cases])
+    f = bb.Letkf([c.spec(bb, transform=_tr(transform)) for c in cases])
     V = [c.noise() for c in cases]
     ys = [c.slopes(c.truth()) for c in cases]
     f.step(_t(np.concatenate([y.ravel() for y in ys])), V=_t(np.concatenate([v.ravel() for v in V])))
@@ -233,12 +246,13 @@ def test_flags_nonfinite_and_noconv():
     assert np.array_equal(g.get_ensemble().cpu().numpy().reshape(-1, case.m), Xb)
 
 
+@pytest.mark.parametrize("transform", TRANSFORMS)
 @pytest.mark.parametrize("N,eps,b,h,m", [(1, None, 1, 0, 2), (5, None, 1, 0, 3), (13, 0.3, 3, 2, 17),
                                          (17, 0.0, 5, 1, 64), (10, None, 2, 0, 64), (7, None, 7, 0, 9)])
-def test_edge_shapes(N, eps, b, h, m):
+def test_edge_shapes(N, eps, b, h, m, transform):
     case = Case(N, eps, b, h, m, seed=N * 7 + m)
     bb = B()
-    f = bb.Letkf([case.spec(bb)])
+    f = bb.Letkf([case.spec(bb, transform=_tr(transform))])
     X0 = (case.rng.standard_normal((case.G.n_nodes, case.m))).astype(np.float32)
     f.set_ensemble(_t(X0))
     V, y = case.noise(), case.slopes(case.truth())
@@ -282,3 +296,10 @@ def test_runs_are_deterministic():
         torch.cuda.synchronize()
         res.append(f.get_ensemble().cpu().numpy())
     assert np.array_equal(res[0], res[1])
+
+
+def test_unknown_transform_is_rejected():
+    case = Case(8, None, 2, 1, 20, seed=1)
+    bb = B()
+    with pytest.raises(Exception):
+        bb.Letkf([case.spec(bb, transform=7)])
