@@ -9,16 +9,21 @@
 //      Sec. 4.1), and the scaled innovation;
 //   3. Gram Y^T Y on the matrix cores (FP32 MFMA 16x16x4; FP64 MFMA in FP64
 //      mode), A~ = (m-1)/rho I + Y^T Y promoted to FP64;
-//   4. FP64 Cholesky A~ = L L^T and the mean weights w = A~^{-1} b by two
-//      triangular solves;
-//   5. FP64 one-sided Jacobi on the columns of L until they are orthogonal:
-//      L J = U with U^T U = Lambda, so A~ = (U Lambda^{-1/2}) Lambda
-//      (U Lambda^{-1/2})^T;
-//   6. W = sqrt(c) U Lambda^{-3/2} U^T on the matrix cores;
+//   4.-6. the transform, one of
+//      NS64 (default): A~^{-1/2} by the scaled coupled Newton-Schulz
+//        iteration on the FP64 matrix cores (64 x 64 products; each wave holds
+//        one 16-column block of the iterates in accumulator tiles), then
+//        w = A~^{-1} b = Z (Z b) / s and W = sqrt(c / s) Z;
+//      NS32: the same iteration with FP32 iterates on the FP32 matrix cores,
+//        w refined once in FP64;
+//      EVD: FP64 Cholesky A~ = L L^T, w by two triangular solves, the FP64
+//        one-sided Jacobi on the columns of L until they are orthogonal
+//        (L J = U, U^T U = Lambda, A~ = (U Lambda^{-1/2}) Lambda
+//        (U Lambda^{-1/2})^T), W = sqrt(c) U Lambda^{-3/2} U^T;
 //   7. owned rows: X_a = (x_b + X' w) 1^T + sqrt(rho) X' W (matrix cores),
 //      written straight into the global analysis ensemble (the gather).
 //
-// Layout of the 64 x 64 FP64 factor during stages 4-6: lane = row; the 64
+// Layout of the 64 x 64 FP64 factor during the Jacobi: lane = row; the 64
 // columns form 8 blocks of 8, wave q holding block q and block 7 - q in
 // registers.  A Jacobi sweep pairs the columns inside each held block (7
 // rounds of a round robin on 8), then runs 7 block-rounds of 8 rounds that
@@ -27,7 +32,7 @@
 // fixed, slots 1..7 rotating): every pair of columns meets once per sweep and
 // only the block moves need a workgroup barrier.
 //
-// k_adjoint recomputes stages 1-6 with the same code and then runs the reverse
+// k_adjoint recomputes stages 1-6 (EVD transform) and then runs the reverse
 // of stage 7 and of the transform (see the comment above it); k_adjoint_nodes
 // sums the per-domain slope adjoints per slope, applies D^T and hands the
 // adjoint of the previous analysis ensemble back.
