@@ -16,4 +16,6 @@ Modules
   accounting  the paper's operation counts (App. B, Tables 1, 3, 4)
   piston      least-squares differential-piston removal after the gather
   adjoint     hand-written reverse-mode gradient of the residual-variance loss
+  delayed     the paper's state [phi_k; phi_{k-1}] with the measurement delay,
+              the DM term of the observation and the command u_k
 """
