@@ -91,6 +91,42 @@ def transform_variants(B, spec, y, K, W):
     return out
 
 
+def closed_loop_line(B, spec, wl_mod, w, y, truth, ij, K, W, frames=200):
+    """The closed AO loop (Sec. 2.2 state: slopes of phi_{k-1} under the
+    command u_{k-2}, command u_k from the analysis) on the same workload: frame
+    time by graph replay on the staged slopes, then a loop of `frames` frames
+    on the GPU with the sensor reading D (phi_{k-1} - u_{k-2}) + noise, and the
+    variance of the residual phase phi_k - u_{k-1} over its second half."""
+    import dataclasses
+    import torch
+    g = B.Letkf([dataclasses.replace(spec, model=B.MODEL_CLOSED_LOOP)])
+    g.set_schedule(True, True)
+    ms = time_steps(g, y, K, W)
+    g.set_ensemble(torch.zeros(g.sizes["ensemble_elems"], dtype=torch.float32, device="cuda"))
+    g.set_frame(0)
+    n = g.sizes["n_nodes"]
+    zero = torch.zeros(n, dtype=torch.float32, device="cuda")
+    g.set_command(zero, zero)
+    T = min(frames, truth.shape[0] - 1)
+    ph = torch.from_numpy(np.ascontiguousarray(truth[:T + 1, ij[:, 0], ij[:, 1]], dtype=np.float32)).cuda()
+    nrng = np.random.default_rng(w.seed + 2)
+    noise = torch.from_numpy(wl_mod.gaussian_noise((T, g.sizes["n_slopes"]), w.sigma, nrng)
+                             .astype(np.float32)).cuda()
+    u1, u2 = zero.clone(), zero.clone()
+    res, tur = [], []
+    for k in range(1, T + 1):
+        yk = g.slopes(ph[k - 1] - u2) + noise[k - 1]
+        g.step(yk)
+        if k > T // 2:
+            r = ph[k] - u1
+            res.append(float(torch.var(r, unbiased=False)))
+            tur.append(float(torch.var(ph[k], unbiased=False)))
+        u2, u1 = u1, g.get_command()
+    g.close()
+    return {"ms_per_step": round(ms, 5), "frames_per_s": round(1000.0 / ms, 2), "loop_frames": T,
+            "residual_variance": round(float(np.mean(res)), 5), "phase_variance": round(float(np.mean(tur)), 3)}
+
+
 def make_inputs(f, wl_mod, w, frames: int, rng):
     """Slopes of an AR(1) true phase for `frames` frames, resident on the GPU."""
     import torch
@@ -349,6 +385,7 @@ def main():
         fc.close()
 
     transforms = transform_variants(B, spec, y, K, W)
+    loop = closed_loop_line(B, spec, wl, w, y, truth, ij, K, W)
 
     others = other_workloads(B, wl, 100, 20) if args.other_workloads else None
 
@@ -371,6 +408,7 @@ def main():
         "step_ms_p99": round(float(np.percentile(per, 99)), 4),
         "batched_copies": copies,
         "transforms": transforms,
+        "closed_loop": loop,
         "filter_check": filt,
         "other_workloads": others,
         "gradient": grad,

@@ -75,6 +75,22 @@ extern "C" {
 #define LETKF_TRANSFORM_NS32 1
 #define LETKF_TRANSFORM_EVD 2
 
+/* State model of an instance (letkf_config.model).
+ *   PHASE        delay-free: x_k = phi_k, y_k = D phi_k + w_k.
+ *   CLOSED_LOOP  the AO loop of Sec. 2.2: x_k = [phi_k; phi_{k-1}; u_{k-1};
+ *                u_{k-2}], y_k = D phi_{k-1} - D N u_{k-2} + w_k, command
+ *                u_k = P phi^_{k+1/k}, with a zonal DM whose actuators are the
+ *                valid phase nodes (N = P = I).  The library keeps u_{k-1},
+ *                u_{k-2} (zero at create).  Each frame analyses phi_{k-1} on
+ *                y_k with y_bar = D x_b - D u_{k-2}; phi_k follows the model
+ *                (its gain is a times that of phi_{k-1}, the model noise being
+ *                independent of the slopes), so the ensemble carried to the
+ *                next frame is a X_a + V, which the next frame's forecast
+ *                forms; the command is u_k = a^2 x_a.  The piston fit (Sec.
+ *                4.4) works on x_a - u_{k-2}.  No adjoint. */
+#define LETKF_MODEL_PHASE 0
+#define LETKF_MODEL_CLOSED_LOOP 1
+
 /* Per-domain status bits (letkf_status); bits 8-15 hold the steps the
  * transform took (Newton-Schulz steps, or Jacobi sweeps begun). */
 #define LETKF_FLAG_NONFINITE 1
@@ -125,6 +141,7 @@ typedef struct letkf_config {
                                   most 4096 domains in the instance.              */
   int32_t transform;           /* LETKF_TRANSFORM_* (same for all instances);
                                   0 = NS64                                         */
+  int32_t model;               /* LETKF_MODEL_PHASE (0) or LETKF_MODEL_CLOSED_LOOP  */
 } letkf_config;
 
 /* Sizes of one instance (or totals when instance = -1). */
@@ -195,6 +212,14 @@ int letkf_get_ensemble(letkf_handle *h, void *dst, int on_device);
 int letkf_set_ensemble(letkf_handle *h, const void *src, int on_device);
 int letkf_get_forecast(letkf_handle *h, void *dst, int on_device);
 int letkf_get_mean(letkf_handle *h, void *dst, int on_device);
+
+/* Closed loop (LETKF_MODEL_CLOSED_LOOP, Sec. 2.2 control part): the latest
+ * command u_k per node of every instance ([sum of n_nodes], element type of
+ * the handle; zero for delay-free instances), written by each analysis after
+ * the pistons; and the command history (u_{k-1}, u_{k-2}) for exact restarts.
+ * Synchronous.  LETKF_E_STATE when no instance runs the closed loop. */
+int letkf_get_command(letkf_handle *h, void *dst, int on_device);
+int letkf_set_command(letkf_handle *h, const void *u_prev1, const void *u_prev2, int on_device);
 
 /* Frame counter (drives the bank draws): get / set, for exact restarts. */
 int letkf_get_frame(letkf_handle *h, uint32_t *frame);

@@ -28,6 +28,7 @@ OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_NOCONV, E_STATE = 0, -1, -2, -3, 
 FP32, FP64 = 0, 1
 FLAG_NONFINITE, FLAG_NOCONV = 1, 2
 TRANSFORM_NS64, TRANSFORM_NS32, TRANSFORM_EVD = 0, 1, 2
+MODEL_PHASE, MODEL_CLOSED_LOOP = 0, 1
 
 
 class Config(C.Structure):
@@ -53,6 +54,7 @@ class Config(C.Structure):
         ("max_sweeps", C.c_int32),
         ("piston_removal", C.c_int32),
         ("transform", C.c_int32),
+        ("model", C.c_int32),
     ]
 
 
@@ -90,6 +92,8 @@ _SIGS = {
     "letkf_set_ensemble": (C.c_int, [_P, _P, C.c_int]),
     "letkf_get_forecast": (C.c_int, [_P, _P, C.c_int]),
     "letkf_get_mean": (C.c_int, [_P, _P, C.c_int]),
+    "letkf_get_command": (C.c_int, [_P, _P, C.c_int]),
+    "letkf_set_command": (C.c_int, [_P, _P, _P, C.c_int]),
     "letkf_get_frame": (C.c_int, [_P, C.POINTER(C.c_uint32)]),
     "letkf_set_frame": (C.c_int, [_P, C.c_uint32]),
     "letkf_status": (C.c_int, [_P, _I32P]),
@@ -147,6 +151,7 @@ class InstanceSpec:
     max_sweeps: int = 0
     piston: bool = False                  # differential-piston removal after the gather
     transform: int = TRANSFORM_NS64       # how W, w come from A~ (NS64, NS32 or the Jacobi EVD)
+    model: int = MODEL_PHASE              # delay-free phase state, or the closed AO loop (Sec. 2.2)
 
 
 def _config(spec: InstanceSpec, keep: list) -> Config:
@@ -181,6 +186,7 @@ def _config(spec: InstanceSpec, keep: list) -> Config:
     c.max_sweeps = spec.max_sweeps
     c.piston_removal = 1 if spec.piston else 0
     c.transform = spec.transform
+    c.model = spec.model
     return c
 
 
@@ -309,6 +315,17 @@ class Letkf:
         out = torch.empty(self.sizes["n_nodes"], dtype=self.dtype, device=f"cuda:{self.device}")
         _check(lib.letkf_get_mean(self._h, _ptr(out), 1), "letkf_get_mean")
         return out
+
+    def get_command(self):
+        """The latest closed-loop command u_k per node (all instances)."""
+        import torch
+        out = torch.empty(self.sizes["n_nodes"], dtype=self.dtype, device=f"cuda:{self.device}")
+        _check(lib.letkf_get_command(self._h, _ptr(out), 1), "letkf_get_command")
+        return out
+
+    def set_command(self, u_prev1, u_prev2):
+        """Set the command history (u_{k-1}, u_{k-2}), device tensors [n_nodes]."""
+        _check(lib.letkf_set_command(self._h, _ptr(u_prev1), _ptr(u_prev2), 1), "letkf_set_command")
 
     def get_frame(self) -> int:
         f = C.c_uint32()

@@ -33,6 +33,9 @@ using namespace letkf;
 extern "C" hipError_t letkf_launch_analysis(const void *args, int fp64, int fused, int eig, int grid,
                                             size_t lds, hipStream_t s);
 extern "C" const void *letkf_analysis_kernel(int fp64, int fused, int eig);
+extern "C" const void *letkf_command_kernel(int fp64);
+extern "C" hipError_t letkf_launch_command(int fp64, const InstDesc *insts, int n_inst, int max_nodes,
+                                           const void *x, void *u1, void *u2, hipStream_t s);
 extern "C" hipError_t letkf_launch_forecast(int fp64, const InstDesc *insts, int n_inst,
                                             const int32_t *node_ij, const void *xa, const void *v,
                                             const float *bank, const uint32_t *frame, void *xb,
@@ -117,6 +120,7 @@ template <typename T> struct AnaArgsHost {
   T *x_mean;
   int32_t *flags;
   const uint32_t *frame;
+  const T *u_prev2;
   double jtol;
   int32_t max_sweeps;
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
@@ -223,6 +227,8 @@ struct letkf_handle {
   double *d_xbbar = nullptr, *d_dbar = nullptr, *d_theta = nullptr;
   // differential pistons: per-instance M^+ and the work buffers
   bool any_piston = false;
+  bool any_loop = false;           // an instance runs the closed-loop model
+  void *d_u1 = nullptr, *d_u2 = nullptr;  // commands u_{k-1}, u_{k-2} per node
   int32_t *d_owner_item = nullptr;
   int64_t *d_minv_off = nullptr;
   double *d_minv = nullptr, *d_prhs = nullptr, *d_pi = nullptr;
@@ -460,6 +466,7 @@ int validate(const letkf_config &c, int idx, std::string &err) {
   else if (!(c.taper_c >= 0)) err = o.str() + "taper_c must be >= 0";
   else if (!c.subap_mask && !(c.obscuration >= 0 && c.obscuration < 1)) err = o.str() + "obscuration must be in [0, 1)";
   else if (c.precision != LETKF_FP32 && c.precision != LETKF_FP64) err = o.str() + "unknown precision";
+  else if (c.model != LETKF_MODEL_PHASE && c.model != LETKF_MODEL_CLOSED_LOOP) err = o.str() + "unknown model";
   else if (c.noise_bank && (c.bank_screens < 1 || c.bank_side < c.n_sub + 1 ||
                             (c.bank_side & (c.bank_side - 1)) != 0))
     err = o.str() + "noise bank needs >= 1 screen and a power-of-two side >= N + 1";
@@ -489,7 +496,7 @@ void free_handle(letkf_handle *h) {
                   h->d_xb, h->d_tmp, h->d_frame, h->d_flags, h->d_node_adj, h->d_slot_off,
                   h->d_slots, h->d_dom_base, h->d_ones, h->d_stats, h->d_xpbar, h->d_ybar,
                   h->d_xbbar, h->d_dbar, h->d_theta, h->d_owner_item, h->d_minv_off, h->d_minv,
-                  h->d_prhs, h->d_pi, h->d_xmean};
+                  h->d_prhs, h->d_pi, h->d_xmean, h->d_u1, h->d_u2};
   for (void *p : ptrs)
     if (p) hipFree(p);
   for (auto &e : h->tev) {
@@ -534,6 +541,7 @@ AnaArgsHost<T> make_args(letkf_handle *h, bool fused, const void *V, const void 
   A.y = (const T *)y;
   A.x_out = (T *)h->d_xa[xa_out];
   A.x_mean = h->any_piston ? (T *)h->d_xmean : nullptr;
+  A.u_prev2 = h->any_loop ? (const T *)h->d_u2 : nullptr;
   A.flags = h->d_flags;
   A.frame = h->d_frame;
   A.jtol = h->jtol;
@@ -591,15 +599,19 @@ int launch_piston_seq(letkf_handle *h, std::initializer_list<int> which, const v
 // The end of a frame after the analysis: the piston fit (right-hand sides,
 // then pistons applied per domain) when enabled, and the frame counter of the
 // bank draws when `frame` is given (folded into the last piston kernel).
+// After the analysis: the pistons (when on) and the frame counter, then the
+// closed loop's command from the final ensemble x.
 int launch_frame_tail(letkf_handle *h, const void *y, void *x, uint32_t *frame, hipStream_t s) {
   if (!h->any_piston) {
     if (frame) HIPCHK(letkf_launch_frame_advance(frame, s));
-    return LETKF_OK;
+  } else {
+    int rc = launch_piston_seq(h, {0}, y, x, s);
+    if (rc) return rc;
+    std::vector<unsigned char> blob = piston_blob(h, y, x);
+    HIPCHK(letkf_launch_piston_finish(h->fp64, blob.data(), (int)h->items.size(), frame, s));
   }
-  int rc = launch_piston_seq(h, {0}, y, x, s);
-  if (rc) return rc;
-  std::vector<unsigned char> blob = piston_blob(h, y, x);
-  HIPCHK(letkf_launch_piston_finish(h->fp64, blob.data(), (int)h->items.size(), frame, s));
+  if (h->any_loop)
+    HIPCHK(letkf_launch_command(h->fp64, h->d_desc, h->n_inst, h->max_nodes, x, h->d_u1, h->d_u2, s));
   return LETKF_OK;
 }
 
@@ -686,6 +698,7 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
       q1.extra = nullptr;
       q1.sharedMemBytes = 0;
       HIPCHK(hipGraphAddKernelNode(&h->gpnode[p][1], h->graph[p], &h->gpnode[p][0], 1, &q1));
+      last = h->gpnode[p][1];
     } else {
       // the frame counter of the bank draws
       hipKernelNodeParams kp2{};
@@ -698,6 +711,21 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
       kp2.sharedMemBytes = 0;
       hipGraphNode_t adv;
       HIPCHK(hipGraphAddKernelNode(&adv, h->graph[p], &last, 1, &kp2));
+      last = adv;
+    }
+    if (h->any_loop) {
+      // the closed loop's command from this parity's analysis ensemble
+      void *xo = h->d_xa[1 - p];
+      void *c3[] = {&h->d_desc, &xo, &h->d_u1, &h->d_u2};
+      hipKernelNodeParams kc{};
+      kc.blockDim = dim3(letkf_analysis_threads());
+      kc.gridDim = dim3((unsigned)((h->max_nodes + 3) / 4), (unsigned)h->n_inst);
+      kc.func = (void *)letkf_command_kernel(h->fp64);
+      kc.kernelParams = c3;
+      kc.extra = nullptr;
+      kc.sharedMemBytes = 0;
+      hipGraphNode_t cmd;
+      HIPCHK(hipGraphAddKernelNode(&cmd, h->graph[p], &last, 1, &kc));
     }
     HIPCHK(hipGraphInstantiate(&h->gexec[p], h->graph[p], nullptr, nullptr, 0));
   } else {
@@ -797,6 +825,8 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     d.instance = (uint32_t)i;
     d.piston = c.piston_removal ? 1 : 0;
     h->any_piston = h->any_piston || d.piston;
+    d.model = c.model;
+    h->any_loop = h->any_loop || d.model == LETKF_MODEL_CLOSED_LOOP;
     d.a = c.ar_coeff;
     d.rho = c.rho;
     d.r_scale = c.r_scale;
@@ -861,7 +891,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   h->off[2] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * 8);
   h->off[3] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * 8);
   h->off[4] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * T);
-  h->off[5] = (int32_t)o; o = align16(o + 128 * 4);
+  h->off[5] = (int32_t)o; o = align16(o + 128 * 4 + 64 * 8);  // patch nodes, their (i, j), u_{k-2}
   h->off[6] = (int32_t)o; o = align16(o + letkf_analysis_scratch_doubles() * 8);
   h->off[7] = (int32_t)o;
   h->off[8] = (int32_t)o;
@@ -879,7 +909,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     h->fwd_off[2] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * 8);
     h->fwd_off[3] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * 8);
     h->fwd_off[4] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * T);
-    h->fwd_off[5] = (int32_t)f; f = align16(f + 128 * 4);
+    h->fwd_off[5] = (int32_t)f; f = align16(f + 128 * 4 + 64 * 8);
     // (the Jacobi transform uses the whole scratch, the Newton-Schulz ones its head)
     const size_t scratch = h->transform == LETKF_TRANSFORM_EVD ? letkf_analysis_scratch_doubles()
                                                                : letkf_analysis_fwd_scratch_doubles();
@@ -1022,6 +1052,15 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   }
   hipMemset(h->d_frame, 0, 16);
   hipMemset(h->d_flags, 0, std::max<size_t>(h->items.size(), 1) * 4);
+  if (h->any_loop) {
+    const size_t ub = std::max<size_t>((size_t)h->total_nodes * T, 16);
+    if (hipMalloc(&h->d_u1, ub) != hipSuccess || hipMalloc(&h->d_u2, ub) != hipSuccess) {
+      free_handle(h);
+      return fail(LETKF_E_NOMEM, "hipMalloc of the command history failed");
+    }
+    hipMemset(h->d_u1, 0, ub);
+    hipMemset(h->d_u2, 0, ub);
+  }
   e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_handle(h);
@@ -1232,6 +1271,20 @@ int letkf_get_mean(letkf_handle *h, void *dst, int on_device) {
   HIPCHK(letkf_launch_mean(h->fp64, h->d_desc, h->n_inst, h->d_xa[h->cur], h->d_tmp, h->max_nodes,
                            nullptr));
   return copy_state(h, dst, h->d_tmp, (size_t)h->total_nodes * h->esize, on_device, false);
+}
+
+int letkf_get_command(letkf_handle *h, void *dst, int on_device) {
+  if (!h || !dst) return fail(LETKF_E_INVAL, "NULL argument");
+  if (!h->any_loop) return fail(LETKF_E_STATE, "no instance runs the closed-loop model");
+  return copy_state(h, dst, h->d_u1, (size_t)h->total_nodes * h->esize, on_device, false);
+}
+
+int letkf_set_command(letkf_handle *h, const void *u1, const void *u2, int on_device) {
+  if (!h || !u1 || !u2) return fail(LETKF_E_INVAL, "NULL argument");
+  if (!h->any_loop) return fail(LETKF_E_STATE, "no instance runs the closed-loop model");
+  const size_t b = (size_t)h->total_nodes * h->esize;
+  int rc = copy_state(h, h->d_u1, u1, b, on_device, true);
+  return rc ? rc : copy_state(h, h->d_u2, u2, b, on_device, true);
 }
 
 int letkf_get_frame(letkf_handle *h, uint32_t *frame) {
@@ -1459,6 +1512,7 @@ int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, u
                   const void *y_dev, void *xbar_dev, double *theta_bar_dev, void *stream) {
   if (!h || !xa_prev_dev || !y_dev || !xbar_dev || !theta_bar_dev)
     return fail(LETKF_E_INVAL, "NULL argument");
+  if (h->any_loop) return fail(LETKF_E_INVAL, "no adjoint for the closed-loop model");
   int rc = check_noise(h, V_dev);
   if (rc) return rc;
   hipSetDevice(h->device);

@@ -928,6 +928,7 @@ template <typename T> struct AnaArgs {
   T *x_mean;           // analysis mean of every node (NULL: not written)
   int32_t *flags;
   const uint32_t *frame;  // frame counter of the bank draws (device)
+  const T *u_prev2;       // closed loop: the command u_{k-2} per node (NULL: none)
   double jtol;
   int32_t max_sweeps;
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
@@ -975,10 +976,14 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
   // ---- 1. node patch of X_b (rows dealt to the four waves) ----
   // patch node of row `lane` and its grid coordinates (pn[64 + r]: i | j << 16)
   const bool use_bank = FUSED && A.noise_bank;
+  // closed loop: the command u_{k-2} at the patch nodes (uc, after pn)
+  T *uc = (T *)(pn + 128);
+  const bool use_u = in.model == 1 && A.u_prev2;
   if (q == 0) {
     const int g = lane < np ? A.patch_node[it.patch_off + lane] : 0;
     pn[lane] = g;
     if (use_bank) pn[64 + lane] = A.node_ij[2 * (in.node_off + g)] | (A.node_ij[2 * (in.node_off + g) + 1] << 16);
+    uc[lane] = use_u && lane < np ? A.u_prev2[in.node_off + g] : (T)0;
   }
   BankDraw bd{};
   if (use_bank && lane < m) bd = bank_draw(in, frame, lane);
@@ -1032,10 +1037,16 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
     const double sgx = f / sqrt(in.r_scale * rx), sgy = f / sqrt(in.r_scale * ry);
     const double yx = (double)A.y[in.y_off + k], yy = (double)A.y[in.y_off + in.n_subaps + k];
     bad = !(isfinite(yx) && isfinite(yy));
+    // predicted slopes D x_b, less D N u_{k-2} in the closed loop (N = I)
+    double ypx = (double)ybx, ypy = (double)yby;
+    if (use_u) {
+      ypx -= 0.5 * (((double)uc[cb] - (double)uc[ca]) + ((double)uc[cd] - (double)uc[cc]));
+      ypy -= 0.5 * (((double)uc[cc] - (double)uc[ca]) + ((double)uc[cd] - (double)uc[cb]));
+    }
     sg[tid] = sgx;
     sg[nobs + tid] = sgy;
-    dd[tid] = sgx * (yx - (double)ybx);
-    dd[nobs + tid] = sgy * (yy - (double)yby);
+    dd[tid] = sgx * (yx - ypx);
+    dd[nobs + tid] = sgy * (yy - ypy);
     yb[tid] = ybx;
     yb[nobs + tid] = yby;
   }
@@ -1233,7 +1244,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     double s = mu;
     for (int k = 0; k < m; ++k) s = fma((double)xs[tid * kXsStride + k] - mu, sm[S_WV + k], s);
     sm[S_XAM + tid] = s;
-    if (A.x_mean) A.x_mean[in.node_off + pn[tid]] = keep_forecast ? xm[tid] : (T)s;
+    // the piston fit reads this mean; in the closed loop it is the residual
+    // x_a - N u_{k-2} that the slopes y_k see
+    const T uo = (in.model == 1 && A.u_prev2) ? ((const T *)(pn + 128))[tid] : (T)0;
+    if (A.x_mean) A.x_mean[in.node_off + pn[tid]] = (keep_forecast ? xm[tid] : (T)s) - uo;
   }
   __syncthreads();
   const T srho = (T)sqrt(in.rho);
@@ -1826,6 +1840,26 @@ template <typename T> __global__ void k_piston_finish(const PistonArgs<T> P, uin
   }
 }
 
+// The command of the closed loop (Sec. 2.2 control part): u_k = P phi^_{k+1/k}
+// with a zonal DM (N = P = I) and the two-step prediction of the analysed
+// phase phi_{k-1}: u_k = a^2 x_a.  The history moves on: u_{k-2} <- u_{k-1},
+// u_{k-1} <- u_k.  One wavefront per node (lane = member), grid (nodes / 4,
+// instances); instances of the delay-free model are left alone.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_command(const InstDesc *insts, const T *x, T *u1, T *u2) {
+  const InstDesc in = insts[blockIdx.y];
+  const int g = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (in.model != 1 || g >= in.n_nodes) return;
+  const int m = in.m;
+  const double v = lane < m ? (double)x[in.x_off + (int64_t)g * m + lane] : 0.0;
+  const double mean = wave_sum(v) / m;
+  if (lane == 0) {
+    const int64_t e = in.node_off + g;
+    u2[e] = u1[e];
+    u1[e] = (T)(in.a * in.a * mean);
+  }
+}
+
 // Adjoint: rhs[item] = sum over the owned nodes and members of Z_bar.
 template <typename T> __global__ void k_piston_adj_sum(const PistonArgs<T> P) {
   const int item = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6);
@@ -1977,6 +2011,22 @@ extern "C" hipError_t letkf_launch_analysis(const void *args, int fp64, int fuse
                                             size_t lds, hipStream_t s) {
   void *kargs[] = {(void *)args};
   return hipLaunchKernel(letkf_analysis_kernel(fp64, fused, eig), dim3(grid), dim3(kThreads), kargs, lds, s);
+}
+
+extern "C" const void *letkf_command_kernel(int fp64) {
+  return fp64 ? (const void *)k_command<double> : (const void *)k_command<float>;
+}
+
+extern "C" hipError_t letkf_launch_command(int fp64, const InstDesc *insts, int n_inst, int max_nodes,
+                                           const void *x, void *u1, void *u2, hipStream_t s) {
+  const dim3 grid((max_nodes + kWaves - 1) / kWaves, n_inst);
+  if (fp64)
+    hipLaunchKernelGGL(k_command<double>, grid, dim3(kThreads), 0, s, insts, (const double *)x,
+                       (double *)u1, (double *)u2);
+  else
+    hipLaunchKernelGGL(k_command<float>, grid, dim3(kThreads), 0, s, insts, (const float *)x,
+                       (float *)u1, (float *)u2);
+  return hipGetLastError();
 }
 
 extern "C" int letkf_analysis_threads(void) { return kThreads; }

@@ -22,6 +22,8 @@ struct InstDesc {
   uint32_t seed_lo, seed_hi;
   uint32_t instance;
   int32_t piston;      // 1: differential-piston removal after the gather
+  int32_t model;       // 0: delay-free phase state; 1: closed loop (delayed slopes, DM terms)
+  int32_t pad1;
   double a, rho, r_scale, taper_c;
 };
 
