@@ -127,6 +127,38 @@ def closed_loop_line(B, spec, wl_mod, w, y, truth, ij, K, W, frames=200):
             "residual_variance": round(float(np.mean(res)), 5), "phase_variance": round(float(np.mean(tur)), 3)}
 
 
+def kf_reference_line(B, wl_mod):
+    """Sec. 5 criterion on the seeded 12x12 reference loop: the coherent energy
+    of the local ETKF closed loop on the GPU (4x4 domains, halo 1, m = 64,
+    pistons, FP32 state) and its loss against the stationary KF's, which
+    tests/golden/kf_reference_12x12.json stores (written from the oracle)."""
+    import torch
+    c = wl_mod.reference_loop()
+    N, a = c["n_sub"], c["a"]
+    bank = wl_mod.noise_bank(16, 32, c["pitch"], c["r0"], c["L0"], a, np.random.default_rng(7))
+    spec = B.InstanceSpec(n_sub=N, m=64, domain_size=4, halo=1, obscuration=0.0,
+                          mask=np.ones((N, N), np.uint8), rho=1.05, r_sigma2=c["sigma"] ** 2, ar_coeff=a,
+                          noise_bank=bank, seed=99, precision=B.FP32, piston=True, model=B.MODEL_CLOSED_LOOP)
+    f = B.Letkf([spec])
+    ij = f.geometry(0)["node_ij"]
+    ph = torch.from_numpy(np.ascontiguousarray(c["truth"][:, ij[:, 0], ij[:, 1]], dtype=np.float32)).cuda()
+    noise = torch.from_numpy(c["noise"].astype(np.float32)).cuda()
+    u1 = torch.zeros(ph.shape[1], dtype=torch.float32, device="cuda")
+    u2 = u1.clone()
+    var = []
+    for k in range(1, ph.shape[0]):
+        f.step(f.slopes(ph[k - 1] - u2) + noise[k - 1])
+        if k > c["burn_in"]:
+            var.append(float(torch.var(ph[k] - u1, unbiased=False)))
+        u2, u1 = u1, f.get_command()
+    f.close()
+    e = float(np.exp(-np.mean(var)))
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "kf_reference_12x12.json")))
+    return {"system": ref["system"], "frames": ph.shape[0] - 1, "burn_in": c["burn_in"],
+            "e_coh_letkf": round(e, 5), "e_coh_kf": round(ref["e_coh_kf"], 5),
+            "loss_percent": round((ref["e_coh_kf"] - e) / ref["e_coh_kf"] * 100.0, 3)}
+
+
 def make_inputs(f, wl_mod, w, frames: int, rng):
     """Slopes of an AR(1) true phase for `frames` frames, resident on the GPU."""
     import torch
@@ -386,6 +418,7 @@ def main():
 
     transforms = transform_variants(B, spec, y, K, W)
     loop = closed_loop_line(B, spec, wl, w, y, truth, ij, K, W)
+    kfref = kf_reference_line(B, wl)
 
     others = other_workloads(B, wl, 100, 20) if args.other_workloads else None
 
@@ -409,6 +442,7 @@ def main():
         "batched_copies": copies,
         "transforms": transforms,
         "closed_loop": loop,
+        "kf_reference": kfref,
         "filter_check": filt,
         "other_workloads": others,
         "gradient": grad,

@@ -11,11 +11,13 @@ through the seeded synthetic inputs.
 Modules
   geometry    pupil mask, actuator grid, Fried slope operator, domains, taper
   letkf       forecast, per-domain analysis (three independent forms), gather
-  kalman      brute-force Kalman update (the exact limit the ETKF must reach)
+  kalman      brute-force Kalman update (the exact limit the ETKF must reach),
+              the DARE gain and the stationary KF closed loop (the reference)
   philox      Philox4x32-10 counter-based generator and the noise-bank lookup
   accounting  the paper's operation counts (App. B, Tables 1, 3, 4)
   piston      least-squares differential-piston removal after the gather
   adjoint     hand-written reverse-mode gradient of the residual-variance loss
   delayed     the paper's state [phi_k; phi_{k-1}] with the measurement delay,
               the DM term of the observation and the command u_k
+  metrics     coherent energy and the loss against the KF (Sec. 5)
 """

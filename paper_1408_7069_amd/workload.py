@@ -45,6 +45,19 @@ def vk_screens(G: int, dx: float, r0: float, L0: float, n: int,
     return out
 
 
+def vk_covariance(G: int, dx: float, r0: float, L0: float) -> np.ndarray:
+    """Exact covariance of the screens vk_screens draws, as a (G, G) table of
+    periodic lags: each screen is the real (or imaginary) part of the FFT of
+    complex white noise shaped by amp, so cov(s_p, s_q) = sum_f amp_f^2
+    cos(2 pi f . (p - q)), the real FFT of amp^2."""
+    f = np.fft.fftfreq(G, dx)
+    fx, fy = np.meshgrid(f, f)
+    psd = vk_psd(fx * fx + fy * fy, r0, L0)
+    psd[0, 0] = 0.0
+    amp2 = psd / (G * dx) ** 2
+    return np.fft.fft2(amp2).real
+
+
 def noise_bank(n_screens: int, side: int, pitch: float, r0: float, L0: float,
                a: float, rng: np.random.Generator) -> np.ndarray:
     """Model-noise bank (n_screens, side, side) float32: von Karman screens
@@ -91,6 +104,20 @@ def frozen_flow_truth(n_sub: int, T: int, pitch: float, r0: float, L0: float,
             ramp = np.exp(-2j * np.pi * (f[None, :] * sx + f[:, None] * sy))
             out[k] += np.sqrt(w) * np.fft.ifft2(F * ramp).real[:n1, :n1]
     return out
+
+
+def reference_loop(seed: int = 2024, frames: int = 400):
+    """The seeded loop on which the KF reference is compared (square 12 x 12
+    SH, all (N+1)^2 nodes valid, a = 0.999, slope noise variance 0.04 rad^2 --
+    the value of the paper's comparisons -- r0 0.15 m, pitch 0.4 m, L0 25 m):
+    the truth grids (frames + 1, 13, 13), the slope noise (frames, p) and the
+    parameters.  Used by the fixture script and the benchmark alike."""
+    N, a, sigma, pitch, r0, L0 = 12, 0.999, 0.2, 0.4, 0.15, 25.0
+    rng = np.random.default_rng(seed)
+    truth = ar1_truth(N, frames + 1, pitch, r0, L0, a, rng)
+    noise = gaussian_noise((frames, 2 * N * N), sigma, rng)
+    return {"n_sub": N, "a": a, "sigma": sigma, "pitch": pitch, "r0": r0, "L0": L0, "burn_in": 100,
+            "truth": truth, "noise": noise}
 
 
 def gaussian_noise(shape, sigma, rng: np.random.Generator) -> np.ndarray:
