@@ -142,6 +142,13 @@ typedef struct letkf_config {
   int32_t transform;           /* LETKF_TRANSFORM_* (same for all instances);
                                   0 = NS64                                         */
   int32_t model;               /* LETKF_MODEL_PHASE (0) or LETKF_MODEL_CLOSED_LOOP  */
+  double ar2_coeff;            /* a2 of an AR(2) turbulence model (Sec. 6 names it
+                                  as the extension of the AR(1) model):
+                                  X_b = a X_a(k) + a2 X_a(k-1) + V, each member
+                                  forecast from its own last two analyses (the
+                                  lagged phase is not re-analysed); |a2| < 1;
+                                  0 = AR(1).  Delay-free model only; no adjoint.
+                                  letkf_set_ensemble sets both frames.            */
 } letkf_config;
 
 /* Sizes of one instance (or totals when instance = -1). */

@@ -55,6 +55,7 @@ class Config(C.Structure):
         ("piston_removal", C.c_int32),
         ("transform", C.c_int32),
         ("model", C.c_int32),
+        ("ar2_coeff", C.c_double),
     ]
 
 
@@ -152,6 +153,7 @@ class InstanceSpec:
     piston: bool = False                  # differential-piston removal after the gather
     transform: int = TRANSFORM_NS64       # how W, w come from A~ (NS64, NS32 or the Jacobi EVD)
     model: int = MODEL_PHASE              # delay-free phase state, or the closed AO loop (Sec. 2.2)
+    ar2_coeff: float = 0.0                # a2 of an AR(2) turbulence model (0: AR(1))
 
 
 def _config(spec: InstanceSpec, keep: list) -> Config:
@@ -187,6 +189,7 @@ def _config(spec: InstanceSpec, keep: list) -> Config:
     c.piston_removal = 1 if spec.piston else 0
     c.transform = spec.transform
     c.model = spec.model
+    c.ar2_coeff = spec.ar2_coeff
     return c
 
 

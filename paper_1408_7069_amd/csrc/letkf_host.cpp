@@ -36,9 +36,12 @@ extern "C" const void *letkf_analysis_kernel(int fp64, int fused, int eig);
 extern "C" const void *letkf_command_kernel(int fp64);
 extern "C" hipError_t letkf_launch_command(int fp64, const InstDesc *insts, int n_inst, int max_nodes,
                                            const void *x, void *u1, void *u2, hipStream_t s);
+extern "C" const void *letkf_copy_kernel(int fp64);
+extern "C" hipError_t letkf_launch_copy(int fp64, const void *src, void *dst, int64_t n, hipStream_t s);
 extern "C" hipError_t letkf_launch_forecast(int fp64, const InstDesc *insts, int n_inst,
                                             const int32_t *node_ij, const void *xa, const void *v,
                                             const float *bank, const uint32_t *frame, void *xb,
+                                            const void *xprev,
                                             int64_t max_elems, hipStream_t s);
 extern "C" hipError_t letkf_launch_frame_advance(uint32_t *frame, hipStream_t s);
 extern "C" const void *letkf_frame_advance_kernel(void);
@@ -121,6 +124,7 @@ template <typename T> struct AnaArgsHost {
   int32_t *flags;
   const uint32_t *frame;
   const T *u_prev2;
+  const T *x_prev;
   double jtol;
   int32_t max_sweeps;
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
@@ -228,6 +232,8 @@ struct letkf_handle {
   // differential pistons: per-instance M^+ and the work buffers
   bool any_piston = false;
   bool any_loop = false;           // an instance runs the closed-loop model
+  bool any_ar2 = false;            // an instance has an AR(2) model
+  void *d_xprev = nullptr;         // AR(2): the analysis ensemble of the frame before the current one
   void *d_u1 = nullptr, *d_u2 = nullptr;  // commands u_{k-1}, u_{k-2} per node
   int32_t *d_owner_item = nullptr;
   int64_t *d_minv_off = nullptr;
@@ -467,6 +473,9 @@ int validate(const letkf_config &c, int idx, std::string &err) {
   else if (!c.subap_mask && !(c.obscuration >= 0 && c.obscuration < 1)) err = o.str() + "obscuration must be in [0, 1)";
   else if (c.precision != LETKF_FP32 && c.precision != LETKF_FP64) err = o.str() + "unknown precision";
   else if (c.model != LETKF_MODEL_PHASE && c.model != LETKF_MODEL_CLOSED_LOOP) err = o.str() + "unknown model";
+  else if (!(std::fabs(c.ar2_coeff) < 1.0)) err = o.str() + "ar2_coeff must be in (-1, 1)";
+  else if (c.ar2_coeff != 0.0 && c.model != LETKF_MODEL_PHASE)
+    err = o.str() + "the AR(2) model runs with the delay-free phase state only";
   else if (c.noise_bank && (c.bank_screens < 1 || c.bank_side < c.n_sub + 1 ||
                             (c.bank_side & (c.bank_side - 1)) != 0))
     err = o.str() + "noise bank needs >= 1 screen and a power-of-two side >= N + 1";
@@ -496,7 +505,7 @@ void free_handle(letkf_handle *h) {
                   h->d_xb, h->d_tmp, h->d_frame, h->d_flags, h->d_node_adj, h->d_slot_off,
                   h->d_slots, h->d_dom_base, h->d_ones, h->d_stats, h->d_xpbar, h->d_ybar,
                   h->d_xbbar, h->d_dbar, h->d_theta, h->d_owner_item, h->d_minv_off, h->d_minv,
-                  h->d_prhs, h->d_pi, h->d_xmean, h->d_u1, h->d_u2};
+                  h->d_prhs, h->d_pi, h->d_xmean, h->d_u1, h->d_u2, h->d_xprev};
   for (void *p : ptrs)
     if (p) hipFree(p);
   for (auto &e : h->tev) {
@@ -542,6 +551,7 @@ AnaArgsHost<T> make_args(letkf_handle *h, bool fused, const void *V, const void 
   A.x_out = (T *)h->d_xa[xa_out];
   A.x_mean = h->any_piston ? (T *)h->d_xmean : nullptr;
   A.u_prev2 = h->any_loop ? (const T *)h->d_u2 : nullptr;
+  A.x_prev = h->any_ar2 ? (const T *)h->d_xprev : nullptr;
   A.flags = h->d_flags;
   A.frame = h->d_frame;
   A.jtol = h->jtol;
@@ -726,6 +736,22 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
       kc.sharedMemBytes = 0;
       hipGraphNode_t cmd;
       HIPCHK(hipGraphAddKernelNode(&cmd, h->graph[p], &last, 1, &kc));
+      last = cmd;
+    }
+    if (h->any_ar2) {
+      // AR(2): this frame's input ensemble becomes the next frame's history
+      void *src = h->d_xa[p];
+      int64_t ne = h->total_x;
+      void *c4[] = {&src, &h->d_xprev, &ne};
+      hipKernelNodeParams kq{};
+      kq.blockDim = dim3(256);
+      kq.gridDim = dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (ne + 255) / 256)));
+      kq.func = (void *)letkf_copy_kernel(h->fp64);
+      kq.kernelParams = c4;
+      kq.extra = nullptr;
+      kq.sharedMemBytes = 0;
+      hipGraphNode_t cp;
+      HIPCHK(hipGraphAddKernelNode(&cp, h->graph[p], &last, 1, &kq));
     }
     HIPCHK(hipGraphInstantiate(&h->gexec[p], h->graph[p], nullptr, nullptr, 0));
   } else {
@@ -828,6 +854,8 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     d.model = c.model;
     h->any_loop = h->any_loop || d.model == LETKF_MODEL_CLOSED_LOOP;
     d.a = c.ar_coeff;
+    d.a2 = c.ar2_coeff;
+    h->any_ar2 = h->any_ar2 || d.a2 != 0.0;
     d.rho = c.rho;
     d.r_scale = c.r_scale;
     d.taper_c = c.taper_c;
@@ -1052,6 +1080,13 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   }
   hipMemset(h->d_frame, 0, 16);
   hipMemset(h->d_flags, 0, std::max<size_t>(h->items.size(), 1) * 4);
+  if (h->any_ar2) {
+    if (hipMalloc(&h->d_xprev, std::max<size_t>(xbytes, 16)) != hipSuccess) {
+      free_handle(h);
+      return fail(LETKF_E_NOMEM, "hipMalloc of the AR(2) history failed");
+    }
+    hipMemset(h->d_xprev, 0, std::max<size_t>(xbytes, 16));
+  }
   if (h->any_loop) {
     const size_t ub = std::max<size_t>((size_t)h->total_nodes * T, 16);
     if (hipMalloc(&h->d_u1, ub) != hipSuccess || hipMalloc(&h->d_u2, ub) != hipSuccess) {
@@ -1164,8 +1199,10 @@ int letkf_forecast(letkf_handle *h, const void *V_dev, void *stream) {
   hipSetDevice(h->device);
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(letkf_launch_forecast(h->fp64, h->d_desc, h->n_inst, h->d_node_ij, h->d_xa[h->cur], V_dev,
-                               h->d_bank, h->d_frame, h->d_xb, h->max_elems, s));
+                               h->d_bank, h->d_frame, h->d_xb, h->d_xprev, h->max_elems, s));
   HIPCHK(letkf_launch_frame_advance(h->d_frame, s));
+  // AR(2): X_a(k-1) becomes the history before the analysis overwrites it
+  if (h->any_ar2) HIPCHK(letkf_launch_copy(h->fp64, h->d_xa[h->cur], h->d_xprev, h->total_x, s));
   h->have_xb = true;
   return LETKF_OK;
 }
@@ -1206,6 +1243,7 @@ int letkf_step(letkf_handle *h, const void *V_dev, const void *y_dev, void *stre
     if (rc) return rc;
     if (ev) HIPCHK(hipEventRecord(ev->second, s));
     if ((rc = launch_frame_tail(h, y_dev, h->d_xa[1 - h->cur], h->d_frame, s))) return rc;
+    if (h->any_ar2) HIPCHK(letkf_launch_copy(h->fp64, h->d_xa[h->cur], h->d_xprev, h->total_x, s));
   }
   h->cur = 1 - h->cur;
   h->have_xb = false;
@@ -1233,6 +1271,7 @@ int letkf_step_plain(letkf_handle *h, const void *V_dev, const void *y_dev, void
     }
   }
   if ((rc = launch_frame_tail(h, y_dev, h->d_xa[1 - h->cur], h->d_frame, s))) return rc;
+  if (h->any_ar2) HIPCHK(letkf_launch_copy(h->fp64, h->d_xa[h->cur], h->d_xprev, h->total_x, s));
   h->cur = 1 - h->cur;
   h->have_xb = false;
   return LETKF_OK;
@@ -1256,7 +1295,10 @@ int letkf_get_ensemble(letkf_handle *h, void *dst, int on_device) {
 int letkf_set_ensemble(letkf_handle *h, const void *src, int on_device) {
   if (!h || !src) return fail(LETKF_E_INVAL, "NULL argument");
   h->have_xb = false;
-  return copy_state(h, h->d_xa[h->cur], src, (size_t)h->total_x * h->esize, on_device, true);
+  const size_t b = (size_t)h->total_x * h->esize;
+  int rc = copy_state(h, h->d_xa[h->cur], src, b, on_device, true);
+  if (rc || !h->any_ar2) return rc;
+  return copy_state(h, h->d_xprev, src, b, on_device, true);  // the AR(2) history starts steady
 }
 
 int letkf_get_forecast(letkf_handle *h, void *dst, int on_device) {
@@ -1513,6 +1555,7 @@ int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, u
   if (!h || !xa_prev_dev || !y_dev || !xbar_dev || !theta_bar_dev)
     return fail(LETKF_E_INVAL, "NULL argument");
   if (h->any_loop) return fail(LETKF_E_INVAL, "no adjoint for the closed-loop model");
+  if (h->any_ar2) return fail(LETKF_E_INVAL, "no adjoint for the AR(2) model");
   int rc = check_noise(h, V_dev);
   if (rc) return rc;
   hipSetDevice(h->device);

@@ -929,6 +929,7 @@ template <typename T> struct AnaArgs {
   int32_t *flags;
   const uint32_t *frame;  // frame counter of the bank draws (device)
   const T *u_prev2;       // closed loop: the command u_{k-2} per node (NULL: none)
+  const T *x_prev;        // AR(2): the analysis ensemble of the frame before x_in (NULL: none)
   double jtol;
   int32_t max_sweeps;
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
@@ -989,6 +990,8 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
   if (use_bank && lane < m) bd = bank_draw(in, frame, lane);
   __syncthreads();
   const T a = (T)in.a;
+  const bool use_prev = FUSED && A.x_prev && in.a2 != 0.0;
+  const T a2 = (T)in.a2;
   // four rows a pass, their loads issued together
   for (int r0 = q; r0 < np; r0 += 4 * kWaves) {
     T xv[4], nv[4];
@@ -1000,12 +1003,13 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
       if (r < np && lane < m) {
         const int64_t e = in.x_off + (int64_t)pn[r] * m + lane;
         xv[u] = A.x_in[e];
+        if (use_prev) nv[u] = a2 * A.x_prev[e];  // the AR(2) term joins the noise
         if (FUSED) {
           if (use_bank) {
             const int ij = pn[64 + r];
-            nv[u] = (T)bank_value(A.bank, bd, ij & 0xFFFF, ij >> 16);
+            nv[u] += (T)bank_value(A.bank, bd, ij & 0xFFFF, ij >> 16);
           } else {
-            nv[u] = A.v_in[e];
+            nv[u] += A.v_in[e];
           }
         }
       }
@@ -1904,10 +1908,12 @@ template <typename T> __global__ void k_piston_adj_apply(const PistonArgs<T> P) 
 // Forecast X_b = a X_a + V over every instance (blockIdx.y = instance).
 template <typename T>
 __global__ void k_forecast(const InstDesc *insts, const int32_t *node_ij, const T *xa, const T *v,
-                           const float *bank, const uint32_t *frame, T *xb) {
+                           const float *bank, const uint32_t *frame, T *xb, const T *xprev) {
   const InstDesc in = insts[blockIdx.y];
   const int64_t n = (int64_t)in.n_nodes * in.m;
   const T a = (T)in.a;
+  const T a2 = (T)in.a2;
+  const bool use_prev = xprev && in.a2 != 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     T noise;
@@ -1920,8 +1926,16 @@ __global__ void k_forecast(const InstDesc *insts, const int32_t *node_ij, const 
       noise = (T)bank_value(bank, bd, node_ij[2 * (in.node_off + node)],
                             node_ij[2 * (in.node_off + node) + 1]);
     }
+    if (use_prev) noise = fma_t(a2, xprev[in.x_off + e], noise);
     xb[in.x_off + e] = fma_t(a, xa[in.x_off + e], noise);
   }
+}
+
+// dst <- src over n elements (the AR(2) history, kept as a kernel so that it
+// can sit in the frame graph).
+template <typename T> __global__ void k_copy(const T *src, T *dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
 }
 
 __global__ void k_frame_advance(uint32_t *frame) {
@@ -2038,19 +2052,36 @@ extern "C" size_t letkf_analysis_xch_bytes(void) {
   return (size_t)kXchBytes;
 }
 
+extern "C" const void *letkf_copy_kernel(int fp64) {
+  return fp64 ? (const void *)k_copy<double> : (const void *)k_copy<float>;
+}
+
+extern "C" hipError_t letkf_launch_copy(int fp64, const void *src, void *dst, int64_t n, hipStream_t s) {
+  int gx = (int)((n + 255) / 256);
+  if (gx > 4096) gx = 4096;
+  if (gx < 1) gx = 1;
+  if (fp64)
+    hipLaunchKernelGGL(k_copy<double>, dim3(gx), dim3(256), 0, s, (const double *)src, (double *)dst, n);
+  else
+    hipLaunchKernelGGL(k_copy<float>, dim3(gx), dim3(256), 0, s, (const float *)src, (float *)dst, n);
+  return hipGetLastError();
+}
+
 extern "C" hipError_t letkf_launch_forecast(int fp64, const InstDesc *insts, int n_inst,
                                             const int32_t *node_ij, const void *xa, const void *v,
                                             const float *bank, const uint32_t *frame, void *xb,
-                                            int64_t max_elems, hipStream_t s) {
+                                            const void *xprev, int64_t max_elems, hipStream_t s) {
   int gx = (int)((max_elems + 255) / 256);
   if (gx > 4096) gx = 4096;
   if (gx < 1) gx = 1;
   if (fp64)
     hipLaunchKernelGGL(k_forecast<double>, dim3(gx, n_inst), dim3(256), 0, s, insts, node_ij,
-                       (const double *)xa, (const double *)v, bank, frame, (double *)xb);
+                       (const double *)xa, (const double *)v, bank, frame, (double *)xb,
+                       (const double *)xprev);
   else
     hipLaunchKernelGGL(k_forecast<float>, dim3(gx, n_inst), dim3(256), 0, s, insts, node_ij,
-                       (const float *)xa, (const float *)v, bank, frame, (float *)xb);
+                       (const float *)xa, (const float *)v, bank, frame, (float *)xb,
+                       (const float *)xprev);
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ struct InstDesc {
   int32_t model;       // 0: delay-free phase state; 1: closed loop (delayed slopes, DM terms)
   int32_t pad1;
   double a, rho, r_scale, taper_c;
+  double a2;           // AR(2): X_b = a X_a(k) + a2 X_a(k-1) + V (0: AR(1))
 };
 
 // One (instance, domain) work item.  Patch entries 0..n_own-1 are the owned

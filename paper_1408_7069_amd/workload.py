@@ -86,6 +86,30 @@ def ar1_truth(n_sub: int, T: int, pitch: float, r0: float, L0: float, a: float,
     return out
 
 
+def ar2_truth(n_sub: int, T: int, pitch: float, r0: float, L0: float, a1: float, a2: float,
+              rng: np.random.Generator) -> np.ndarray:
+    """(T, N+1, N+1) stationary AR(2) truth x_k = a1 x_{k-1} + a2 x_{k-2} + s w_k
+    with fresh von Karman w_k, s the innovation scale that keeps the von
+    Karman variance, started from two draws with the lag-1 correlation
+    a1 / (1 - a2)."""
+    n1 = n_sub + 1
+    G = 2 * n1
+    s = np.sqrt((1.0 + a2) * ((1.0 - a2) ** 2 - a1 * a1) / (1.0 - a2))
+    r1 = a1 / (1.0 - a2)
+    w = vk_screens(G, pitch, r0, L0, 2, rng)
+    xm = w[0, :n1, :n1]
+    x = r1 * xm + np.sqrt(1.0 - r1 * r1) * w[1, :n1, :n1]
+    out = np.empty((T, n1, n1))
+    k = 0
+    while k < T:
+        w = vk_screens(G, pitch, r0, L0, min(2, T - k), rng)
+        for e in w:
+            x, xm = a1 * x + a2 * xm + s * e[:n1, :n1], x
+            out[k] = x
+            k += 1
+    return out
+
+
 def frozen_flow_truth(n_sub: int, T: int, pitch: float, r0: float, L0: float,
                       layers, rate_hz: float, rng: np.random.Generator,
                       big: int = 512) -> np.ndarray:

@@ -16,6 +16,7 @@ class Case:
         self.G = geo.geometry_for(N, eps)
         self.doms = geo.domains(self.G, b, h)
         self.prm = ol.Params(a=a, rho=rho, r_scale=r_scale, b=b, h=h, taper_c=taper_c, piston=piston)
+        self.noise_scale = np.sqrt(1 - a * a)   # AR(1) model noise, fixed at construction
         self.sigma, self.r0, self.pitch, self.fp64 = sigma, r0, pitch, fp64
         self.ij = self.G.node_coords()
         self.r = np.full(self.G.n_slopes, sigma * sigma) * self.rng.uniform(0.8, 1.25, self.G.n_slopes)
@@ -41,7 +42,7 @@ class Case:
         G = 2 * (self.N + 1)
         s = wl.vk_screens(G, self.pitch, self.r0, 25.0, self.m, self.rng)
         V = np.stack([x[self.ij[:, 0], self.ij[:, 1]] for x in s], axis=1)
-        return (scale * np.sqrt(1 - self.prm.a ** 2) * V).astype(self.dt)
+        return (scale * self.noise_scale * V).astype(self.dt)
 
     def truth(self):
         s = wl.vk_screens(2 * (self.N + 1), self.pitch, self.r0, 25.0, 1, self.rng)[0]
