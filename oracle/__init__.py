@@ -20,4 +20,7 @@ Modules
   delayed     the paper's state [phi_k; phi_{k-1}] with the measurement delay,
               the DM term of the observation and the command u_k
   metrics     coherent energy and the loss against the KF (Sec. 5)
+  ar2         the AR(2) turbulence model from each member's last two analyses
+  refit       online least-squares refit of the AR(1) coefficient and the
+              model-noise scale that follows it (Sec. 4.2)
 """
