@@ -149,6 +149,22 @@ typedef struct letkf_config {
                                   lagged phase is not re-analysed); |a2| < 1;
                                   0 = AR(1).  Delay-free model only; no adjoint.
                                   letkf_set_ensemble sets both frames.            */
+  double refit_forgetting;     /* online refit of the AR(1) model (Sec. 4.2: the
+                                  model may be re-identified during the
+                                  prediction step); 0 = off, else the forgetting
+                                  factor f in (0, 1].  After every frame k the
+                                  piston-removed analysis means x_k, x_{k-1}
+                                  (means over members, then the mean over the
+                                  nodes taken out) update
+                                    s01 = f s01 + x_k . x_{k-1}
+                                    s11 = f s11 + x_{k-1} . x_{k-1}
+                                  and, once s11 > 0, the model of the next
+                                  frames: a = clip(s01 / s11, 0, 0.9999) and the
+                                  model noise V (drawn for a_0 = ar_coeff, given
+                                  or from the bank) scaled by
+                                  sqrt((1 - a^2) / (1 - a_0^2)).  Needs
+                                  0 <= ar_coeff < 1 and the AR(1) model; no
+                                  adjoint.  See letkf_get_model.                  */
 } letkf_config;
 
 /* Sizes of one instance (or totals when instance = -1). */
@@ -229,6 +245,16 @@ int letkf_get_command(letkf_handle *h, void *dst, int on_device);
 int letkf_set_command(letkf_handle *h, const void *u_prev1, const void *u_prev2, int on_device);
 
 /* Frame counter (drives the bank draws): get / set, for exact restarts. */
+/* The model each instance's next forecast uses: a[i] (ar_coeff, or the
+ * refitted coefficient) and noise_scale[i] (the factor on V; 1 without the
+ * refit).  Host arrays of n_instances entries; either may be NULL.  Waits
+ * for the device. */
+int letkf_get_model(letkf_handle *h, double *a, double *noise_scale);
+
+/* Restart the online refit: sums cleared, a = ar_coeff, noise scale 1.
+ * LETKF_E_STATE when no instance refits. */
+int letkf_reset_refit(letkf_handle *h);
+
 int letkf_get_frame(letkf_handle *h, uint32_t *frame);
 int letkf_set_frame(letkf_handle *h, uint32_t frame);
 
@@ -254,7 +280,9 @@ int letkf_get_schedule(letkf_handle *h, int32_t *use_graph, int32_t *xcd_order);
 
 /* Time the step under each schedule on `stream` (frames frames each, using
  * the given V/y buffers) and keep the fastest; results are cached in
- * cache_path (text, one line per shape) when cache_path != NULL. */
+ * cache_path (text, one line per shape) when cache_path != NULL.  The filter
+ * state (ensemble, frame counter, AR(2) and command histories, refitted
+ * model) is restored afterwards. */
 int letkf_autotune(letkf_handle *h, const void *V_dev, const void *y_dev, int32_t frames,
                    const char *cache_path, void *stream);
 
@@ -313,7 +341,9 @@ int letkf_residual_variance_adjoint(letkf_handle *h, const void *xa_dev, const v
  * passes through the eigenvectors themselves, so in FP32 mode its recompute
  * runs the Jacobi to min(jacobi_tol, 1e-6) (the forward's transform W only
  * needs the looser default).  Returns LETKF_E_INVAL when the device cannot
- * give the adjoint kernel its LDS. */
+ * give the adjoint kernel its LDS, and for handles with a closed-loop
+ * instance, an AR(2) model or the online refit (the frame it reverses is the
+ * delay-free AR(1) one). */
 int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, uint32_t frame,
                   const void *y_dev, void *xbar_dev, double *theta_bar_dev, void *stream);
 

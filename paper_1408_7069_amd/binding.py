@@ -56,6 +56,7 @@ class Config(C.Structure):
         ("transform", C.c_int32),
         ("model", C.c_int32),
         ("ar2_coeff", C.c_double),
+        ("refit_forgetting", C.c_double),
     ]
 
 
@@ -95,6 +96,8 @@ _SIGS = {
     "letkf_get_mean": (C.c_int, [_P, _P, C.c_int]),
     "letkf_get_command": (C.c_int, [_P, _P, C.c_int]),
     "letkf_set_command": (C.c_int, [_P, _P, _P, C.c_int]),
+    "letkf_get_model": (C.c_int, [_P, _P, _P]),
+    "letkf_reset_refit": (C.c_int, [_P]),
     "letkf_get_frame": (C.c_int, [_P, C.POINTER(C.c_uint32)]),
     "letkf_set_frame": (C.c_int, [_P, C.c_uint32]),
     "letkf_status": (C.c_int, [_P, _I32P]),
@@ -154,6 +157,7 @@ class InstanceSpec:
     transform: int = TRANSFORM_NS64       # how W, w come from A~ (NS64, NS32 or the Jacobi EVD)
     model: int = MODEL_PHASE              # delay-free phase state, or the closed AO loop (Sec. 2.2)
     ar2_coeff: float = 0.0                # a2 of an AR(2) turbulence model (0: AR(1))
+    refit_forgetting: float = 0.0         # online AR(1) refit with this forgetting factor (0: off)
 
 
 def _config(spec: InstanceSpec, keep: list) -> Config:
@@ -190,6 +194,7 @@ def _config(spec: InstanceSpec, keep: list) -> Config:
     c.transform = spec.transform
     c.model = spec.model
     c.ar2_coeff = spec.ar2_coeff
+    c.refit_forgetting = spec.refit_forgetting
     return c
 
 
@@ -329,6 +334,17 @@ class Letkf:
     def set_command(self, u_prev1, u_prev2):
         """Set the command history (u_{k-1}, u_{k-2}), device tensors [n_nodes]."""
         _check(lib.letkf_set_command(self._h, _ptr(u_prev1), _ptr(u_prev2), 1), "letkf_set_command")
+
+    def get_model(self):
+        """(a, noise scale) per instance that the next forecast uses."""
+        a = np.zeros(len(self.specs), dtype=np.float64)
+        v = np.zeros(len(self.specs), dtype=np.float64)
+        _check(lib.letkf_get_model(self._h, a.ctypes.data, v.ctypes.data), "letkf_get_model")
+        return a, v
+
+    def reset_refit(self):
+        """Restart the online refit (sums cleared, a = ar_coeff)."""
+        _check(lib.letkf_reset_refit(self._h), "letkf_reset_refit")
 
     def get_frame(self) -> int:
         f = C.c_uint32()

@@ -37,6 +37,11 @@ extern "C" const void *letkf_command_kernel(int fp64);
 extern "C" hipError_t letkf_launch_command(int fp64, const InstDesc *insts, int n_inst, int max_nodes,
                                            const void *x, void *u1, void *u2, hipStream_t s);
 extern "C" const void *letkf_copy_kernel(int fp64);
+extern "C" const void *letkf_refit_sums_kernel(int fp64);
+extern "C" const void *letkf_refit_finish_kernel(void);
+extern "C" int letkf_refit_stride(int max_nodes);
+extern "C" hipError_t letkf_launch_refit(int fp64, void *insts, void *rs, const void *x_now, const void *x_prev,
+                                         double *part, int max_nodes, int n_inst, hipStream_t s);
 extern "C" hipError_t letkf_launch_copy(int fp64, const void *src, void *dst, int64_t n, hipStream_t s);
 extern "C" hipError_t letkf_launch_forecast(int fp64, const InstDesc *insts, int n_inst,
                                             const int32_t *node_ij, const void *xa, const void *v,
@@ -233,7 +238,10 @@ struct letkf_handle {
   bool any_piston = false;
   bool any_loop = false;           // an instance runs the closed-loop model
   bool any_ar2 = false;            // an instance has an AR(2) model
-  void *d_xprev = nullptr;         // AR(2): the analysis ensemble of the frame before the current one
+  bool any_refit = false;          // an instance refits its AR(1) model online
+  void *d_xprev = nullptr;         // AR(2) / refit: the analysis ensemble of the frame before the current one
+  RefitState *d_refit = nullptr;   // refit sums and settings per instance
+  double *d_rpart = nullptr;       // refit partial sums [instance][stride][4]
   void *d_u1 = nullptr, *d_u2 = nullptr;  // commands u_{k-1}, u_{k-2} per node
   int32_t *d_owner_item = nullptr;
   int64_t *d_minv_off = nullptr;
@@ -476,6 +484,11 @@ int validate(const letkf_config &c, int idx, std::string &err) {
   else if (!(std::fabs(c.ar2_coeff) < 1.0)) err = o.str() + "ar2_coeff must be in (-1, 1)";
   else if (c.ar2_coeff != 0.0 && c.model != LETKF_MODEL_PHASE)
     err = o.str() + "the AR(2) model runs with the delay-free phase state only";
+  else if (!(c.refit_forgetting >= 0.0 && c.refit_forgetting <= 1.0))
+    err = o.str() + "refit_forgetting must be in [0, 1]";
+  else if (c.refit_forgetting > 0.0 && c.ar2_coeff != 0.0) err = o.str() + "the online refit fits the AR(1) model only";
+  else if (c.refit_forgetting > 0.0 && !(c.ar_coeff >= 0.0 && c.ar_coeff < 1.0))
+    err = o.str() + "the online refit needs ar_coeff in [0, 1)";
   else if (c.noise_bank && (c.bank_screens < 1 || c.bank_side < c.n_sub + 1 ||
                             (c.bank_side & (c.bank_side - 1)) != 0))
     err = o.str() + "noise bank needs >= 1 screen and a power-of-two side >= N + 1";
@@ -505,7 +518,8 @@ void free_handle(letkf_handle *h) {
                   h->d_xb, h->d_tmp, h->d_frame, h->d_flags, h->d_node_adj, h->d_slot_off,
                   h->d_slots, h->d_dom_base, h->d_ones, h->d_stats, h->d_xpbar, h->d_ybar,
                   h->d_xbbar, h->d_dbar, h->d_theta, h->d_owner_item, h->d_minv_off, h->d_minv,
-                  h->d_prhs, h->d_pi, h->d_xmean, h->d_u1, h->d_u2, h->d_xprev};
+                  h->d_prhs, h->d_pi, h->d_xmean, h->d_u1, h->d_u2, h->d_xprev,
+                  h->d_refit, h->d_rpart};
   for (void *p : ptrs)
     if (p) hipFree(p);
   for (auto &e : h->tev) {
@@ -608,10 +622,11 @@ int launch_piston_seq(letkf_handle *h, std::initializer_list<int> which, const v
 
 // The end of a frame after the analysis: the piston fit (right-hand sides,
 // then pistons applied per domain) when enabled, and the frame counter of the
-// bank draws when `frame` is given (folded into the last piston kernel).
-// After the analysis: the pistons (when on) and the frame counter, then the
-// closed loop's command from the final ensemble x.
-int launch_frame_tail(letkf_handle *h, const void *y, void *x, uint32_t *frame, hipStream_t s) {
+// bank draws when `frame` is given (folded into the last piston kernel); then
+// the closed loop's command from the final ensemble x, and the online refit
+// of the AR(1) model from x and the frame's input ensemble x_prev.
+int launch_frame_tail(letkf_handle *h, const void *y, void *x, const void *x_prev, uint32_t *frame,
+                      hipStream_t s) {
   if (!h->any_piston) {
     if (frame) HIPCHK(letkf_launch_frame_advance(frame, s));
   } else {
@@ -622,6 +637,8 @@ int launch_frame_tail(letkf_handle *h, const void *y, void *x, uint32_t *frame, 
   }
   if (h->any_loop)
     HIPCHK(letkf_launch_command(h->fp64, h->d_desc, h->n_inst, h->max_nodes, x, h->d_u1, h->d_u2, s));
+  if (h->any_refit)
+    HIPCHK(letkf_launch_refit(h->fp64, h->d_desc, h->d_refit, x, x_prev, h->d_rpart, h->max_nodes, h->n_inst, s));
   return LETKF_OK;
 }
 
@@ -738,6 +755,32 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
       HIPCHK(hipGraphAddKernelNode(&cmd, h->graph[p], &last, 1, &kc));
       last = cmd;
     }
+    if (h->any_refit) {
+      // the online refit: sums over the nodes, then the model of the next frame
+      void *xo = h->d_xa[1 - p], *xi = h->d_xa[p];
+      int stride = letkf_refit_stride(h->max_nodes);
+      void *c5[] = {&h->d_desc, &h->d_refit, &xo, &xi, &h->d_rpart, &stride};
+      hipKernelNodeParams kr{};
+      kr.blockDim = dim3(letkf_analysis_threads());
+      kr.gridDim = dim3((unsigned)stride, (unsigned)h->n_inst);
+      kr.func = (void *)letkf_refit_sums_kernel(h->fp64);
+      kr.kernelParams = c5;
+      kr.extra = nullptr;
+      kr.sharedMemBytes = 0;
+      hipGraphNode_t rs;
+      HIPCHK(hipGraphAddKernelNode(&rs, h->graph[p], &last, 1, &kr));
+      void *c6[] = {&h->d_desc, &h->d_refit, &h->d_rpart, &stride};
+      hipKernelNodeParams kf{};
+      kf.blockDim = dim3(letkf_analysis_threads());
+      kf.gridDim = dim3((unsigned)h->n_inst);
+      kf.func = (void *)letkf_refit_finish_kernel();
+      kf.kernelParams = c6;
+      kf.extra = nullptr;
+      kf.sharedMemBytes = 0;
+      hipGraphNode_t rf;
+      HIPCHK(hipGraphAddKernelNode(&rf, h->graph[p], &rs, 1, &kf));
+      last = rf;
+    }
     if (h->any_ar2) {
       // AR(2): this frame's input ensemble becomes the next frame's history
       void *src = h->d_xa[p];
@@ -825,6 +868,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   std::vector<double> obs_dist;
   std::vector<float> bank;
   std::vector<double> r;
+  std::vector<RefitState> refit;
   int64_t x_off = 0, y_off = 0, node_off = 0, bank_off = 0;
   int dom_total = 0;
   for (int i = 0; i < n_instances; ++i) {
@@ -856,6 +900,13 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     d.a = c.ar_coeff;
     d.a2 = c.ar2_coeff;
     h->any_ar2 = h->any_ar2 || d.a2 != 0.0;
+    d.vscale = 1.0;
+    RefitState rs{};
+    rs.f = c.refit_forgetting;
+    rs.a0 = c.ar_coeff;
+    rs.a_max = 0.9999;
+    refit.push_back(rs);
+    h->any_refit = h->any_refit || rs.f > 0.0;
     d.rho = c.rho;
     d.r_scale = c.r_scale;
     d.taper_c = c.taper_c;
@@ -1048,6 +1099,10 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   }
   (void)hipGetLastError();
   if ((rc = to_device(&h->d_desc, h->desc)) || (rc = to_device(&h->d_items, h->items)) ||
+      (h->any_refit && (rc = to_device(&h->d_refit, refit))) ||
+      (h->any_refit &&
+       (rc = to_device(&h->d_rpart, std::vector<double>((size_t)n_instances * letkf_refit_stride(h->max_nodes) * 4,
+                                                        0.0)))) ||
       (rc = to_device(&h->d_patch, patch)) || (rc = to_device(&h->d_obs_sub, obs_sub)) ||
       (rc = to_device(&h->d_obs_corner, obs_corner)) || (rc = to_device(&h->d_obs_dist, obs_dist)) ||
       (rc = to_device(&h->d_node_ij, node_ij)) || (rc = to_device(&h->d_subap_nodes, subap_nodes)) ||
@@ -1080,10 +1135,10 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   }
   hipMemset(h->d_frame, 0, 16);
   hipMemset(h->d_flags, 0, std::max<size_t>(h->items.size(), 1) * 4);
-  if (h->any_ar2) {
+  if (h->any_ar2 || h->any_refit) {
     if (hipMalloc(&h->d_xprev, std::max<size_t>(xbytes, 16)) != hipSuccess) {
       free_handle(h);
-      return fail(LETKF_E_NOMEM, "hipMalloc of the AR(2) history failed");
+      return fail(LETKF_E_NOMEM, "hipMalloc of the previous analysis ensemble failed");
     }
     hipMemset(h->d_xprev, 0, std::max<size_t>(xbytes, 16));
   }
@@ -1201,8 +1256,8 @@ int letkf_forecast(letkf_handle *h, const void *V_dev, void *stream) {
   HIPCHK(letkf_launch_forecast(h->fp64, h->d_desc, h->n_inst, h->d_node_ij, h->d_xa[h->cur], V_dev,
                                h->d_bank, h->d_frame, h->d_xb, h->d_xprev, h->max_elems, s));
   HIPCHK(letkf_launch_frame_advance(h->d_frame, s));
-  // AR(2): X_a(k-1) becomes the history before the analysis overwrites it
-  if (h->any_ar2) HIPCHK(letkf_launch_copy(h->fp64, h->d_xa[h->cur], h->d_xprev, h->total_x, s));
+  // AR(2), refit: X_a(k-1) becomes the history before the analysis overwrites it
+  if (h->any_ar2 || h->any_refit) HIPCHK(letkf_launch_copy(h->fp64, h->d_xa[h->cur], h->d_xprev, h->total_x, s));
   h->have_xb = true;
   return LETKF_OK;
 }
@@ -1213,7 +1268,7 @@ int letkf_analyse(letkf_handle *h, const void *y_dev, void *stream) {
   hipSetDevice(h->device);
   int rc = launch_analysis(h, false, nullptr, y_dev, h->cur, h->cur, (hipStream_t)stream);
   if (rc) return rc;
-  if ((rc = launch_frame_tail(h, y_dev, h->d_xa[h->cur], nullptr, (hipStream_t)stream))) return rc;
+  if ((rc = launch_frame_tail(h, y_dev, h->d_xa[h->cur], h->d_xprev, nullptr, (hipStream_t)stream))) return rc;
   h->have_xb = false;
   return LETKF_OK;
 }
@@ -1242,7 +1297,7 @@ int letkf_step(letkf_handle *h, const void *V_dev, const void *y_dev, void *stre
     rc = launch_analysis(h, true, V_dev, y_dev, h->cur, 1 - h->cur, s);
     if (rc) return rc;
     if (ev) HIPCHK(hipEventRecord(ev->second, s));
-    if ((rc = launch_frame_tail(h, y_dev, h->d_xa[1 - h->cur], h->d_frame, s))) return rc;
+    if ((rc = launch_frame_tail(h, y_dev, h->d_xa[1 - h->cur], h->d_xa[h->cur], h->d_frame, s))) return rc;
     if (h->any_ar2) HIPCHK(letkf_launch_copy(h->fp64, h->d_xa[h->cur], h->d_xprev, h->total_x, s));
   }
   h->cur = 1 - h->cur;
@@ -1270,7 +1325,7 @@ int letkf_step_plain(letkf_handle *h, const void *V_dev, const void *y_dev, void
       HIPCHK(letkf_launch_analysis(&A, 0, 1, h->transform, 1, h->lds, s));
     }
   }
-  if ((rc = launch_frame_tail(h, y_dev, h->d_xa[1 - h->cur], h->d_frame, s))) return rc;
+  if ((rc = launch_frame_tail(h, y_dev, h->d_xa[1 - h->cur], h->d_xa[h->cur], h->d_frame, s))) return rc;
   if (h->any_ar2) HIPCHK(letkf_launch_copy(h->fp64, h->d_xa[h->cur], h->d_xprev, h->total_x, s));
   h->cur = 1 - h->cur;
   h->have_xb = false;
@@ -1364,8 +1419,45 @@ int letkf_set_params(letkf_handle *h, int32_t instance, double rho, double r_sca
   d.taper_c = taper_c;
   hipSetDevice(h->device);
   HIPCHK(hipDeviceSynchronize());
-  HIPCHK(hipMemcpy(h->d_desc + instance, &d, sizeof(d), hipMemcpyHostToDevice));
+  // the device copy may hold a refitted model (a, noise scale): keep it
+  InstDesc dv;
+  HIPCHK(hipMemcpy(&dv, h->d_desc + instance, sizeof(dv), hipMemcpyDeviceToHost));
+  dv.rho = rho;
+  dv.r_scale = r_scale;
+  dv.taper_c = taper_c;
+  HIPCHK(hipMemcpy(h->d_desc + instance, &dv, sizeof(dv), hipMemcpyHostToDevice));
   return LETKF_OK;
+}
+
+int letkf_get_model(letkf_handle *h, double *a, double *noise_scale) {
+  if (!h || (!a && !noise_scale)) return fail(LETKF_E_INVAL, "NULL argument");
+  std::vector<InstDesc> dv(h->n_inst);
+  int rc = copy_state(h, dv.data(), h->d_desc, dv.size() * sizeof(InstDesc), 0, false);
+  if (rc) return rc;
+  for (int i = 0; i < h->n_inst; ++i) {
+    if (a) a[i] = dv[i].a;
+    if (noise_scale) noise_scale[i] = dv[i].vscale;
+  }
+  return LETKF_OK;
+}
+
+int letkf_reset_refit(letkf_handle *h) {
+  if (!h) return fail(LETKF_E_INVAL, "NULL handle");
+  if (!h->any_refit) return fail(LETKF_E_STATE, "no instance refits its model");
+  std::vector<RefitState> rs(h->n_inst);
+  int rc = copy_state(h, rs.data(), h->d_refit, rs.size() * sizeof(RefitState), 0, false);
+  if (rc) return rc;
+  std::vector<InstDesc> dv(h->n_inst);
+  if ((rc = copy_state(h, dv.data(), h->d_desc, dv.size() * sizeof(InstDesc), 0, false))) return rc;
+  for (int i = 0; i < h->n_inst; ++i) {
+    if (rs[i].f == 0.0) continue;
+    rs[i].s01 = rs[i].s11 = 0.0;
+    rs[i].frames = 0;
+    dv[i].a = rs[i].a0;
+    dv[i].vscale = 1.0;
+  }
+  if ((rc = copy_state(h, h->d_refit, rs.data(), rs.size() * sizeof(RefitState), 0, true))) return rc;
+  return copy_state(h, h->d_desc, dv.data(), dv.size() * sizeof(InstDesc), 0, true);
 }
 
 int letkf_slopes(letkf_handle *h, const void *phase_dev, void *slopes_dev, void *stream) {
@@ -1419,14 +1511,23 @@ int letkf_autotune(letkf_handle *h, const void *V_dev, const void *y_dev, int32_
   }
   hipStream_t s = (hipStream_t)stream;
   hipSetDevice(h->device);
-  // keep the state: tuning frames must not change it
-  const size_t xbytes = (size_t)h->total_x * h->esize;
-  void *backup = nullptr;
-  HIPCHK(hipMalloc(&backup, std::max<size_t>(xbytes, 16)));
-  uint32_t frame0 = 0;
+  // keep the state: tuning frames must not change it (ensemble, frame
+  // counter, AR(2) history, command history, refitted model and its sums)
+  const size_t xbytes = (size_t)h->total_x * h->esize, ubytes = (size_t)h->total_nodes * h->esize;
+  std::vector<std::pair<void *, size_t>> keep = {{h->d_xa[h->cur], xbytes}, {h->d_frame, 4},
+                                                 {h->d_desc, h->n_inst * sizeof(InstDesc)}};
+  if (h->d_xprev) keep.push_back({h->d_xprev, xbytes});
+  if (h->any_loop) {
+    keep.push_back({h->d_u1, ubytes});
+    keep.push_back({h->d_u2, ubytes});
+  }
+  if (h->any_refit) keep.push_back({h->d_refit, h->n_inst * sizeof(RefitState)});
+  std::vector<std::vector<unsigned char>> saved(keep.size());
   HIPCHK(hipDeviceSynchronize());
-  HIPCHK(hipMemcpy(backup, h->d_xa[h->cur], xbytes, hipMemcpyDeviceToDevice));
-  HIPCHK(hipMemcpy(&frame0, h->d_frame, 4, hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < keep.size(); ++i) {
+    saved[i].resize(keep[i].second);
+    HIPCHK(hipMemcpy(saved[i].data(), keep[i].first, keep[i].second, hipMemcpyDeviceToHost));
+  }
   const int cur0 = h->cur;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -1455,9 +1556,8 @@ int letkf_autotune(letkf_handle *h, const void *V_dev, const void *y_dev, int32_
   hipEventDestroy(e1);
   HIPCHK(hipDeviceSynchronize());
   h->cur = cur0;
-  HIPCHK(hipMemcpy(h->d_xa[h->cur], backup, xbytes, hipMemcpyDeviceToDevice));
-  HIPCHK(hipMemcpy(h->d_frame, &frame0, 4, hipMemcpyHostToDevice));
-  hipFree(backup);
+  for (size_t i = 0; i < keep.size(); ++i)
+    HIPCHK(hipMemcpy(keep[i].first, saved[i].data(), keep[i].second, hipMemcpyHostToDevice));
   letkf_set_schedule(h, bg, bx);
   if (cache_path) {
     std::ofstream o(cache_path, std::ios::app);
@@ -1556,6 +1656,7 @@ int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, u
     return fail(LETKF_E_INVAL, "NULL argument");
   if (h->any_loop) return fail(LETKF_E_INVAL, "no adjoint for the closed-loop model");
   if (h->any_ar2) return fail(LETKF_E_INVAL, "no adjoint for the AR(2) model");
+  if (h->any_refit) return fail(LETKF_E_INVAL, "no adjoint with the online refit");
   int rc = check_noise(h, V_dev);
   if (rc) return rc;
   hipSetDevice(h->device);

@@ -992,6 +992,7 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
   const T a = (T)in.a;
   const bool use_prev = FUSED && A.x_prev && in.a2 != 0.0;
   const T a2 = (T)in.a2;
+  const T vs = (T)in.vscale;
   // four rows a pass, their loads issued together
   for (int r0 = q; r0 < np; r0 += 4 * kWaves) {
     T xv[4], nv[4];
@@ -1007,9 +1008,9 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
         if (FUSED) {
           if (use_bank) {
             const int ij = pn[64 + r];
-            nv[u] += (T)bank_value(A.bank, bd, ij & 0xFFFF, ij >> 16);
+            nv[u] = fma_t(vs, (T)bank_value(A.bank, bd, ij & 0xFFFF, ij >> 16), nv[u]);
           } else {
-            nv[u] += A.v_in[e];
+            nv[u] = fma_t(vs, A.v_in[e], nv[u]);
           }
         }
       }
@@ -1926,6 +1927,7 @@ __global__ void k_forecast(const InstDesc *insts, const int32_t *node_ij, const 
       noise = (T)bank_value(bank, bd, node_ij[2 * (in.node_off + node)],
                             node_ij[2 * (in.node_off + node) + 1]);
     }
+    noise *= (T)in.vscale;
     if (use_prev) noise = fma_t(a2, xprev[in.x_off + e], noise);
     xb[in.x_off + e] = fma_t(a, xa[in.x_off + e], noise);
   }
@@ -1936,6 +1938,91 @@ __global__ void k_forecast(const InstDesc *insts, const int32_t *node_ij, const 
 template <typename T> __global__ void k_copy(const T *src, T *dst, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     dst[e] = src[e];
+}
+
+// Online refit of the AR(1) model (Sec. 4.2: the model may be re-identified
+// while the filter runs).  Per instance and frame, the lag-1 pair of analysis
+// means x_k = mean of X_a(k), x_{k-1} = mean of X_a(k-1) gives four sums over
+// the nodes: <x_k>, <x_{k-1}>, x_k . x_{k-1}, x_{k-1} . x_{k-1}.  One
+// wavefront per node (lane = member), grid (ceil(max nodes / 4), instances);
+// each workgroup writes its four partial sums to part[(inst * stride + block) * 4].
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_refit_sums(const InstDesc *insts, const RefitState *rs,
+                                                         const T *x_now, const T *x_prev, double *part,
+                                                         int stride) {
+  const int inst = blockIdx.y;
+  const InstDesc in = insts[inst];
+  if (rs[inst].f == 0.0 || (int)blockIdx.x * kWaves >= in.n_nodes) return;  // whole workgroup
+  __shared__ double red[kWaves][4];
+  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = (int)blockIdx.x * kWaves + q, m = in.m;
+  double xn = 0.0, xp = 0.0;
+  if (g < in.n_nodes && lane < m) {
+    const int64_t e = in.x_off + (int64_t)g * m + lane;
+    xn = (double)x_now[e];
+    xp = (double)x_prev[e];
+  }
+  xn = wave_sum(xn) / m;
+  xp = wave_sum(xp) / m;
+  if (lane == 0) {
+    const bool v = g < in.n_nodes;
+    red[q][0] = v ? xn : 0.0;
+    red[q][1] = v ? xp : 0.0;
+    red[q][2] = v ? xn * xp : 0.0;
+    red[q][3] = v ? xp * xp : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double t = 0.0;
+    for (int w = 0; w < kWaves; ++w) t += red[w][threadIdx.x];
+    part[((int64_t)inst * stride + blockIdx.x) * 4 + threadIdx.x] = t;
+  }
+}
+
+// The refit's update, one workgroup per instance: the partial sums reduced in
+// a fixed order, the piston-removed products
+//   c01 = x_k . x_{k-1} - n <x_k> <x_{k-1}>,   c11 = |x_{k-1}|^2 - n <x_{k-1}>^2,
+// folded in with forgetting f (s01 = f s01 + c01, s11 = f s11 + c11), and the
+// model of the next frames: a = clip(s01 / s11, 0, a_max) once s11 > 0, and
+// the factor on the model noise (drawn for a_0) that keeps the stationary
+// variance, sqrt((1 - a^2) / (1 - a_0^2)).
+__global__ __launch_bounds__(kThreads) void k_refit_finish(InstDesc *insts, RefitState *rs,
+                                                           const double *part, int stride) {
+  const int inst = blockIdx.x;
+  if (rs[inst].f == 0.0) return;
+  const int n = insts[inst].n_nodes, nb = (n + kWaves - 1) / kWaves;
+  __shared__ double red[kWaves][4];
+  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += kThreads) {
+    const double *p = part + ((int64_t)inst * stride + b) * 4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] += p[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double v = wave_sum(acc[c]);
+    if (lane == 0) red[q][c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double S[4];
+    for (int c = 0; c < 4; ++c) {
+      S[c] = 0.0;
+      for (int w = 0; w < kWaves; ++w) S[c] += red[w][c];
+    }
+    RefitState r = rs[inst];
+    const double c01 = S[2] - S[0] * S[1] / n, c11 = S[3] - S[1] * S[1] / n;
+    r.s01 = r.f * r.s01 + c01;
+    r.s11 = r.f * r.s11 + c11;
+    r.frames += 1;
+    rs[inst] = r;
+    if (r.s11 > 0.0) {
+      const double a = fmin(fmax(r.s01 / r.s11, 0.0), r.a_max);
+      insts[inst].a = a;
+      insts[inst].vscale = sqrt((1.0 - a * a) / (1.0 - r.a0 * r.a0));
+    }
+  }
 }
 
 __global__ void k_frame_advance(uint32_t *frame) {
@@ -2050,6 +2137,30 @@ extern "C" size_t letkf_analysis_fwd_scratch_doubles(void) { return kFwdScratch;
 
 extern "C" size_t letkf_analysis_xch_bytes(void) {
   return (size_t)kXchBytes;
+}
+
+extern "C" const void *letkf_refit_sums_kernel(int fp64) {
+  return fp64 ? (const void *)k_refit_sums<double> : (const void *)k_refit_sums<float>;
+}
+
+extern "C" const void *letkf_refit_finish_kernel(void) { return (const void *)k_refit_finish; }
+
+// Partial-sum rows per instance of the refit (grid x of k_refit_sums).
+extern "C" int letkf_refit_stride(int max_nodes) { return (max_nodes + kWaves - 1) / kWaves; }
+
+extern "C" hipError_t letkf_launch_refit(int fp64, void *insts, void *rs, const void *x_now, const void *x_prev,
+                                         double *part, int max_nodes, int n_inst, hipStream_t s) {
+  const int stride = letkf_refit_stride(max_nodes);
+  const dim3 g(stride, n_inst);
+  if (fp64)
+    hipLaunchKernelGGL(k_refit_sums<double>, g, dim3(kThreads), 0, s, (const InstDesc *)insts,
+                       (const RefitState *)rs, (const double *)x_now, (const double *)x_prev, part, stride);
+  else
+    hipLaunchKernelGGL(k_refit_sums<float>, g, dim3(kThreads), 0, s, (const InstDesc *)insts,
+                       (const RefitState *)rs, (const float *)x_now, (const float *)x_prev, part, stride);
+  hipLaunchKernelGGL(k_refit_finish, dim3(n_inst), dim3(kThreads), 0, s, (InstDesc *)insts, (RefitState *)rs,
+                     (const double *)part, stride);
+  return hipGetLastError();
 }
 
 extern "C" const void *letkf_copy_kernel(int fp64) {

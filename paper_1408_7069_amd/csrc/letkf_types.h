@@ -26,6 +26,17 @@ struct InstDesc {
   int32_t pad1;
   double a, rho, r_scale, taper_c;
   double a2;           // AR(2): X_b = a X_a(k) + a2 X_a(k-1) + V (0: AR(1))
+  double vscale;       // factor on the model noise V (1; the online refit sets it)
+};
+
+// Online AR(1) refit of one instance: the forgetting least-squares sums of the
+// lag-1 pairs of analysis means (piston removed) and the model it feeds.
+struct RefitState {
+  double s01, s11;     // sum f^j <x_k - <x_k>, x_{k-1} - <x_{k-1}>>, sum f^j |x_{k-1} - <x_{k-1}>|^2
+  double f;            // forgetting factor in (0, 1]; 0: the instance does not refit
+  double a0;           // the configured coefficient (the model noise was drawn for it)
+  double a_max;        // upper clip of the fitted coefficient
+  int64_t frames;      // frames folded in
 };
 
 // One (instance, domain) work item.  Patch entries 0..n_own-1 are the owned
