@@ -127,14 +127,14 @@ def closed_loop_line(B, spec, wl_mod, w, y, truth, ij, K, W, frames=200):
             "residual_variance": round(float(np.mean(res)), 5), "phase_variance": round(float(np.mean(tur)), 3)}
 
 
-def model_variants(B, spec, wl_mod, w, y, truth, ij, K, W, frames=300, a0=0.9, forgetting=0.98):
+def model_variants(B, spec, wl_mod, w, y, truth, ij, K, W, frames=300, a0s=(0.9, 0.9995), forgetting=0.98):
     """The turbulence-model variants on the same workload: frame times (graph
     replay) of the AR(2) forecast (a1 = 1.24, a2 = -0.26: lag correlations
-    near 0.99 and 0.97) and of the online AR(1) refit, and a loop
-    over the staged slopes (true a = w.a) from a mismatched a0 with model noise
-    drawn for a0: the residual variance of the analysis mean over the second
-    half with the model fixed at a0 and with the refit, and the refit's final
-    coefficient."""
+    near 0.99 and 0.97) and of the online AR(1) refit, and for each
+    mismatched a0 a loop over the staged slopes (true a = w.a) with model
+    noise drawn for a0: the residual variance of the analysis mean over the
+    second half with the model fixed at a0 and with the refit, and the
+    refit's final coefficient."""
     import dataclasses
     import torch
     out = {}
@@ -146,22 +146,26 @@ def model_variants(B, spec, wl_mod, w, y, truth, ij, K, W, frames=300, a0=0.9, f
     g.set_schedule(True, True)
     out["refit_ms_per_step"] = round(time_steps(g, y, K, W), 5)
     g.close()
-    bank = wl_mod.bank_for(dataclasses.replace(w, a=a0), np.random.default_rng(w.seed + 3), n_screens=16)
     T = min(frames, y.shape[0])
     ph = torch.from_numpy(np.ascontiguousarray(truth[:T, ij[:, 0], ij[:, 1]], dtype=np.float32)).cuda()
-    for name, fg in (("fixed", 0.0), ("refit", forgetting)):
-        g = B.Letkf([dataclasses.replace(spec, ar_coeff=a0, noise_bank=bank, refit_forgetting=fg)])
-        g.set_schedule(True, True)
-        var = []
-        for k in range(T):
-            g.step(y[k])
-            if k >= T // 2:
-                var.append(float(torch.var(g.get_mean() - ph[k], unbiased=False)))
-        out[name + "_residual_variance"] = round(float(np.mean(var)), 5)
-        if fg:
-            out["refit_final_a"] = round(float(g.get_model()[0][0]), 5)
-        g.close()
-    out.update({"true_a": w.a, "a0": a0, "forgetting": forgetting, "loop_frames": T})
+    loops = []
+    for a0 in a0s:
+        bank = wl_mod.bank_for(dataclasses.replace(w, a=a0), np.random.default_rng(w.seed + 3), n_screens=16)
+        row = {"a0": a0}
+        for name, fg in (("fixed", 0.0), ("refit", forgetting)):
+            g = B.Letkf([dataclasses.replace(spec, ar_coeff=a0, noise_bank=bank, refit_forgetting=fg)])
+            g.set_schedule(True, True)
+            var = []
+            for k in range(T):
+                g.step(y[k])
+                if k >= T // 2:
+                    var.append(float(torch.var(g.get_mean() - ph[k], unbiased=False)))
+            row[name + "_residual_variance"] = round(float(np.mean(var)), 5)
+            if fg:
+                row["refit_final_a"] = round(float(g.get_model()[0][0]), 5)
+            g.close()
+        loops.append(row)
+    out.update({"true_a": w.a, "forgetting": forgetting, "loop_frames": T, "loops": loops})
     return out
 
 
