@@ -23,4 +23,6 @@ Modules
   ar2         the AR(2) turbulence model from each member's last two analyses
   refit       online least-squares refit of the AR(1) coefficient and the
               model-noise scale that follows it (Sec. 4.2)
+  blend       blend-mode gather: patch analyses put on a common piston and
+              averaged with tent weights (a variant of the Sec. 4.2 gather)
 """
