@@ -90,6 +90,9 @@ extern "C" {
  *                4.4) works on x_a - u_{k-2}.  No adjoint. */
 #define LETKF_MODEL_PHASE 0
 #define LETKF_MODEL_CLOSED_LOOP 1
+/* letkf_config.gather_mode */
+#define LETKF_GATHER_CONCAT 0
+#define LETKF_GATHER_BLEND 1
 
 /* Per-domain status bits (letkf_status); bits 8-15 hold the steps the
  * transform took (Newton-Schulz steps, or Jacobi sweeps begun). */
@@ -165,6 +168,21 @@ typedef struct letkf_config {
                                   sqrt((1 - a^2) / (1 - a_0^2)).  Needs
                                   0 <= ar_coeff < 1 and the AR(1) model; no
                                   adjoint.  See letkf_get_model.                  */
+  int32_t gather_mode;         /* how X_a is formed from the local analyses:
+                                  LETKF_GATHER_CONCAT (0): the owned rows of each
+                                  domain, concatenated (Sec. 4.2).
+                                  LETKF_GATHER_BLEND (1), a variant: every domain
+                                  updates all nodes of its patch (owned nodes and
+                                  the corners of its observation subapertures);
+                                  the patches are put on a common piston (least
+                                  squares over the nodes two patches share, the
+                                  minimum-norm solution), then each node takes
+                                  the weighted mean of its patch rows with
+                                  weights t(d_i) t(d_j), t(d) = 1 - d/(h+2), d_i,
+                                  d_j its distance in node pitches from the
+                                  domain's block, normalised over the patches.
+                                  Needs piston_removal off (the alignment takes
+                                  its place); no adjoint.                         */
 } letkf_config;
 
 /* Sizes of one instance (or totals when instance = -1). */
@@ -342,8 +360,8 @@ int letkf_residual_variance_adjoint(letkf_handle *h, const void *xa_dev, const v
  * runs the Jacobi to min(jacobi_tol, 1e-6) (the forward's transform W only
  * needs the looser default).  Returns LETKF_E_INVAL when the device cannot
  * give the adjoint kernel its LDS, and for handles with a closed-loop
- * instance, an AR(2) model or the online refit (the frame it reverses is the
- * delay-free AR(1) one). */
+ * instance, an AR(2) model, the online refit or the blend-mode gather (the
+ * frame it reverses is the delay-free AR(1) one with the concatenation). */
 int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, uint32_t frame,
                   const void *y_dev, void *xbar_dev, double *theta_bar_dev, void *stream);
 

@@ -29,6 +29,7 @@ FP32, FP64 = 0, 1
 FLAG_NONFINITE, FLAG_NOCONV = 1, 2
 TRANSFORM_NS64, TRANSFORM_NS32, TRANSFORM_EVD = 0, 1, 2
 MODEL_PHASE, MODEL_CLOSED_LOOP = 0, 1
+GATHER_CONCAT, GATHER_BLEND = 0, 1
 
 
 class Config(C.Structure):
@@ -57,6 +58,7 @@ class Config(C.Structure):
         ("model", C.c_int32),
         ("ar2_coeff", C.c_double),
         ("refit_forgetting", C.c_double),
+        ("gather_mode", C.c_int32),
     ]
 
 
@@ -158,6 +160,7 @@ class InstanceSpec:
     model: int = MODEL_PHASE              # delay-free phase state, or the closed AO loop (Sec. 2.2)
     ar2_coeff: float = 0.0                # a2 of an AR(2) turbulence model (0: AR(1))
     refit_forgetting: float = 0.0         # online AR(1) refit with this forgetting factor (0: off)
+    gather_mode: int = 0                  # GATHER_CONCAT, or GATHER_BLEND (aligned, tent-weighted patches)
 
 
 def _config(spec: InstanceSpec, keep: list) -> Config:
@@ -195,6 +198,7 @@ def _config(spec: InstanceSpec, keep: list) -> Config:
     c.model = spec.model
     c.ar2_coeff = spec.ar2_coeff
     c.refit_forgetting = spec.refit_forgetting
+    c.gather_mode = spec.gather_mode
     return c
 
 

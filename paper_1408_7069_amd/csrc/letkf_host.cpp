@@ -38,6 +38,15 @@ extern "C" hipError_t letkf_launch_command(int fp64, const InstDesc *insts, int 
                                            const void *x, void *u1, void *u2, hipStream_t s);
 extern "C" const void *letkf_copy_kernel(int fp64);
 extern "C" const void *letkf_refit_sums_kernel(int fp64);
+extern "C" const void *letkf_blend_rhs_kernel(void);
+extern "C" const void *letkf_blend_solve_kernel(void);
+extern "C" const void *letkf_blend_gather_kernel(int fp64);
+extern "C" hipError_t letkf_launch_blend(int fp64, const InstDesc *insts, const DomItem *items, int n_items,
+                                         const int32_t *patch_node, const double *smean, const int32_t *boff,
+                                         const int32_t *bent, const int32_t *bitem, const double *bw,
+                                         const int32_t *dom_base, const int64_t *minv_off, const double *minv,
+                                         double *rhs, double *pi, const void *stage, void *x, uint32_t *frame,
+                                         int max_nodes, int n_inst, hipStream_t s);
 extern "C" const void *letkf_refit_finish_kernel(void);
 extern "C" int letkf_refit_stride(int max_nodes);
 extern "C" hipError_t letkf_launch_refit(int fp64, void *insts, void *rs, const void *x_now, const void *x_prev,
@@ -130,6 +139,8 @@ template <typename T> struct AnaArgsHost {
   const uint32_t *frame;
   const T *u_prev2;
   const T *x_prev;
+  T *stage;
+  double *stage_mean;
   double jtol;
   int32_t max_sweeps;
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
@@ -241,6 +252,11 @@ struct letkf_handle {
   bool any_refit = false;          // an instance refits its AR(1) model online
   void *d_xprev = nullptr;         // AR(2) / refit: the analysis ensemble of the frame before the current one
   RefitState *d_refit = nullptr;   // refit sums and settings per instance
+  bool any_blend = false;          // an instance gathers in blend mode
+  void *d_stage = nullptr;         // blend: analysed patch rows [patch entry][64]
+  double *d_smean = nullptr;       // blend: their member means
+  int32_t *d_boff = nullptr, *d_bent = nullptr, *d_bitem = nullptr;  // blend: node -> patch entries
+  double *d_bw = nullptr;          // blend: normalised weights of those entries
   double *d_rpart = nullptr;       // refit partial sums [instance][stride][4]
   void *d_u1 = nullptr, *d_u2 = nullptr;  // commands u_{k-1}, u_{k-2} per node
   int32_t *d_owner_item = nullptr;
@@ -383,12 +399,53 @@ int plan_instance(const letkf_config &c, InstGeom &g, std::string &err) {
   return LETKF_OK;
 }
 
+int pinv_by_components(std::vector<double> &M, int nd, std::vector<double> &out, std::string &err,
+                       const char *what);
+
+// Tent weight of patch node n in domain d for the blend-mode gather:
+// t(d_i) t(d_j), t(d) = 1 - d / (h + 2), d_i (d_j) the distance in node pitches
+// of the node's row (column) from the rows (columns) of the domain's block (the
+// last block row and column run to the grid edge).
+double blend_weight(const InstGeom &g, int d, int n) {
+  const int nb = (g.N + g.b - 1) / g.b;
+  double w = 1.0;
+  for (int ax = 0; ax < 2; ++ax) {
+    const int K = g.blocks[d][ax], v = g.node_ij[2 * n + ax];
+    const int lo = K * g.b, hi = K == nb - 1 ? g.N : (K + 1) * g.b - 1;
+    const int dist = std::max(0, std::max(lo - v, v - hi));
+    w *= 1.0 - dist / (g.h + 2.0);
+  }
+  return w;
+}
+
+// L^+ of the blend alignment of one instance: L is the graph Laplacian of the
+// domains weighted by the number of nodes their patches share (for every node
+// and every ordered pair of distinct patches holding it: L_ll += 1,
+// L_lq -= 1).
+int blend_minv(const InstGeom &g, std::vector<double> &out, std::string &err) {
+  const int nd = (int)g.owned.size();
+  if (nd > 4096) {
+    err = "the blend-mode gather supports at most 4096 domains per instance";
+    return LETKF_E_INVAL;
+  }
+  std::vector<std::vector<int>> holders((size_t)g.n_nodes);
+  for (int d = 0; d < nd; ++d)
+    for (int32_t n : g.patch[d]) holders[n].push_back(d);
+  std::vector<double> M((size_t)nd * nd, 0.0);
+  for (const auto &hs : holders)
+    for (int l : hs)
+      for (int q : hs)
+        if (q != l) {
+          M[(size_t)l * nd + l] += 1.0;
+          M[(size_t)l * nd + q] -= 1.0;
+        }
+  return pinv_by_components(M, nd, out, err, "blend alignment");
+}
+
 // M^+ of the differential-piston fit of one instance, row-major nd x nd:
-// M = P^T D^T D P (P: node -> owning domain), made definite by adding mu on
-// every connected set of domains (the common piston of a set is not
-// measurable; the right-hand sides are orthogonal to it, so the solution is
-// the minimum-norm least-squares one), then inverted through its Cholesky
-// factor.
+// M = P^T D^T D P (P: node -> owning domain); the common piston of a
+// connected set of domains is not measurable and the right-hand sides are
+// orthogonal to it (pinv_by_components).
 int piston_minv(const InstGeom &g, std::vector<double> &out, std::string &err) {
   const int nd = (int)g.owned.size();
   if (nd > 4096) {
@@ -417,6 +474,17 @@ int piston_minv(const InstGeom &g, std::vector<double> &out, std::string &err) {
         for (int b = 0; b < n; ++b) M[(size_t)dl[a] * nd + dl[b]] += cv[a] * cv[b];
     }
   }
+  return pinv_by_components(M, nd, out, err, "differential-piston");
+}
+
+// Pseudo-inverse of a symmetric positive semi-definite nd x nd matrix whose
+// null space is the constant vector on each connected set of domains (the
+// sets from its nonzero off-diagonal entries): mu is added on every set to
+// make it definite, then it is inverted through its Cholesky factor.  Applied
+// to right-hand sides with zero sum on every set this gives the minimum-norm
+// least-squares solution.  M is overwritten.
+int pinv_by_components(std::vector<double> &M, int nd, std::vector<double> &out, std::string &err,
+                       const char *what) {
   std::vector<int> comp(nd);
   for (int d = 0; d < nd; ++d) comp[d] = d;
   std::function<int(int)> root = [&](int d) { return comp[d] == d ? d : (comp[d] = root(comp[d])); };
@@ -437,7 +505,7 @@ int piston_minv(const InstGeom &g, std::vector<double> &out, std::string &err) {
     double djj = M[(size_t)j * nd + j];
     for (int k = 0; k < j; ++k) djj -= M[(size_t)j * nd + k] * M[(size_t)j * nd + k];
     if (!(djj > 0.0)) {
-      err = "differential-piston normal matrix is not definite";
+      err = std::string(what) + " normal matrix is not definite";
       return LETKF_E_INVAL;
     }
     const double ljj = std::sqrt(djj);
@@ -489,6 +557,10 @@ int validate(const letkf_config &c, int idx, std::string &err) {
   else if (c.refit_forgetting > 0.0 && c.ar2_coeff != 0.0) err = o.str() + "the online refit fits the AR(1) model only";
   else if (c.refit_forgetting > 0.0 && !(c.ar_coeff >= 0.0 && c.ar_coeff < 1.0))
     err = o.str() + "the online refit needs ar_coeff in [0, 1)";
+  else if (c.gather_mode != LETKF_GATHER_CONCAT && c.gather_mode != LETKF_GATHER_BLEND)
+    err = o.str() + "unknown gather_mode";
+  else if (c.gather_mode == LETKF_GATHER_BLEND && c.piston_removal)
+    err = o.str() + "the blend-mode gather aligns the patch pistons itself: piston_removal must be off";
   else if (c.noise_bank && (c.bank_screens < 1 || c.bank_side < c.n_sub + 1 ||
                             (c.bank_side & (c.bank_side - 1)) != 0))
     err = o.str() + "noise bank needs >= 1 screen and a power-of-two side >= N + 1";
@@ -519,7 +591,8 @@ void free_handle(letkf_handle *h) {
                   h->d_slots, h->d_dom_base, h->d_ones, h->d_stats, h->d_xpbar, h->d_ybar,
                   h->d_xbbar, h->d_dbar, h->d_theta, h->d_owner_item, h->d_minv_off, h->d_minv,
                   h->d_prhs, h->d_pi, h->d_xmean, h->d_u1, h->d_u2, h->d_xprev,
-                  h->d_refit, h->d_rpart};
+                  h->d_refit, h->d_rpart, h->d_stage, h->d_smean, h->d_boff, h->d_bent,
+                  h->d_bitem, h->d_bw};
   for (void *p : ptrs)
     if (p) hipFree(p);
   for (auto &e : h->tev) {
@@ -566,6 +639,8 @@ AnaArgsHost<T> make_args(letkf_handle *h, bool fused, const void *V, const void 
   A.x_mean = h->any_piston ? (T *)h->d_xmean : nullptr;
   A.u_prev2 = h->any_loop ? (const T *)h->d_u2 : nullptr;
   A.x_prev = h->any_ar2 ? (const T *)h->d_xprev : nullptr;
+  A.stage = h->any_blend ? (T *)h->d_stage : nullptr;
+  A.stage_mean = h->d_smean;
   A.flags = h->d_flags;
   A.frame = h->d_frame;
   A.jtol = h->jtol;
@@ -627,6 +702,13 @@ int launch_piston_seq(letkf_handle *h, std::initializer_list<int> which, const v
 // of the AR(1) model from x and the frame's input ensemble x_prev.
 int launch_frame_tail(letkf_handle *h, const void *y, void *x, const void *x_prev, uint32_t *frame,
                       hipStream_t s) {
+  if (h->any_blend) {
+    HIPCHK(letkf_launch_blend(h->fp64, h->d_desc, h->d_items, (int)h->items.size(), h->d_patch, h->d_smean,
+                              h->d_boff, h->d_bent, h->d_bitem, h->d_bw, h->d_dom_base, h->d_minv_off, h->d_minv,
+                              h->d_prhs, h->d_pi, h->d_stage, x, h->any_piston ? nullptr : frame, h->max_nodes,
+                              h->n_inst, s));
+    frame = h->any_piston ? frame : nullptr;  // advanced by the blend gather
+  }
   if (!h->any_piston) {
     if (frame) HIPCHK(letkf_launch_frame_advance(frame, s));
   } else {
@@ -709,6 +791,33 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
     HIPCHK(hipGraphCreate(&h->graph[p], 0));
     HIPCHK(hipGraphAddKernelNode(&h->gnode[p], h->graph[p], nullptr, 0, &kp));
     hipGraphNode_t last = h->gnode[p];
+    if (h->any_blend) {
+      // blend-mode gather: alignment right-hand sides, pistons, weighted gather
+      // (with the frame counter unless the piston kernels follow)
+      int n_items = (int)h->items.size();
+      void *xo = h->d_xa[1 - p];
+      uint32_t *fr = h->any_piston ? nullptr : h->d_frame;
+      const unsigned gi = (unsigned)((n_items + 3) / 4);
+      void *b1[] = {&h->d_desc, &h->d_items, &n_items, &h->d_patch, &h->d_smean, &h->d_boff, &h->d_bent, &h->d_prhs};
+      void *b2[] = {&h->d_desc, &h->d_items, &n_items, &h->d_dom_base, &h->d_minv_off, &h->d_minv, &h->d_prhs,
+                    &h->d_pi};
+      void *b3[] = {&h->d_desc, &h->d_boff, &h->d_bent, &h->d_bitem, &h->d_bw, &h->d_stage, &h->d_pi, &xo, &fr};
+      const void *fn[3] = {letkf_blend_rhs_kernel(), letkf_blend_solve_kernel(), letkf_blend_gather_kernel(h->fp64)};
+      void **ka[3] = {b1, b2, b3};
+      const dim3 gd[3] = {dim3(gi), dim3(gi), dim3((unsigned)((h->max_nodes + 3) / 4), (unsigned)h->n_inst)};
+      for (int t = 0; t < 3; ++t) {
+        hipKernelNodeParams kb{};
+        kb.blockDim = dim3(letkf_analysis_threads());
+        kb.gridDim = gd[t];
+        kb.func = (void *)fn[t];
+        kb.kernelParams = ka[t];
+        kb.extra = nullptr;
+        kb.sharedMemBytes = 0;
+        hipGraphNode_t nb;
+        HIPCHK(hipGraphAddKernelNode(&nb, h->graph[p], &last, 1, &kb));
+        last = nb;
+      }
+    }
     if (h->any_piston) {
       // piston right-hand sides, then pistons applied and the frame counter
       h->gpargs[p][0] = prhs;
@@ -726,7 +835,7 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
       q1.sharedMemBytes = 0;
       HIPCHK(hipGraphAddKernelNode(&h->gpnode[p][1], h->graph[p], &h->gpnode[p][0], 1, &q1));
       last = h->gpnode[p][1];
-    } else {
+    } else if (!h->any_blend) {
       // the frame counter of the bank draws
       hipKernelNodeParams kp2{};
       void *a2[] = {&h->d_frame};
@@ -901,6 +1010,8 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     d.a2 = c.ar2_coeff;
     h->any_ar2 = h->any_ar2 || d.a2 != 0.0;
     d.vscale = 1.0;
+    d.blend = c.gather_mode == LETKF_GATHER_BLEND ? 1 : 0;
+    h->any_blend = h->any_blend || d.blend;
     RefitState rs{};
     rs.f = c.refit_forgetting;
     rs.a0 = c.ar_coeff;
@@ -994,7 +1105,8 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
                                                                : letkf_analysis_fwd_scratch_doubles();
     h->fwd_off[6] = (int32_t)f; f = align16(f + scratch * 8);
     h->fwd_off[0] = (int32_t)f;
-    const size_t ub = align16(f + (size_t)h->max_own * kXsStride * T);
+    // (blend mode updates every patch row: all of them outlive stage 2)
+    const size_t ub = align16(f + (size_t)(h->any_blend ? h->max_patch : h->max_own) * kXsStride * T);
     const size_t rows_end = f + (size_t)h->max_patch * kXsStride * T;  // end of the patch rows
     const size_t ys_bytes = p4 * kYsStride * T;
     const size_t spill = rows_end > ub ? align16(rows_end - ub) : 0;
@@ -1070,13 +1182,44 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   }
   for (int i = 0; i < n_instances; ++i) {
     minv_off.push_back((int64_t)minv.size());
-    if (!h->desc[i].piston) continue;
+    if (!h->desc[i].piston && !h->desc[i].blend) continue;
     std::vector<double> mi;
-    if (piston_minv(h->geom[i], mi, err) != LETKF_OK) {
+    if ((h->desc[i].piston ? piston_minv(h->geom[i], mi, err) : blend_minv(h->geom[i], mi, err)) != LETKF_OK) {
       free_handle(h);
       return fail(LETKF_E_INVAL, "instance " + std::to_string(i) + ": " + err);
     }
     minv.insert(minv.end(), mi.begin(), mi.end());
+  }
+
+  // blend-mode gather: per node of a blend instance, its patch entries (item
+  // order), their items and normalised tent weights
+  std::vector<int32_t> boff(1, 0), bent, bitem;
+  std::vector<double> bw;
+  if (h->any_blend) {
+    std::vector<std::vector<std::pair<int32_t, double>>> lists((size_t)h->total_nodes);
+    std::vector<int32_t> ent_item;
+    for (size_t k = 0; k < h->items.size(); ++k) {
+      const DomItem &it = h->items[k];
+      if (!h->desc[it.inst].blend) continue;
+      const InstGeom &g = h->geom[it.inst];
+      const auto &P = g.patch[it.dom];
+      for (size_t r = 0; r < P.size(); ++r)
+        lists[(size_t)(h->desc[it.inst].node_off + P[r])].push_back(
+            {(int32_t)(it.patch_off + r), blend_weight(g, it.dom, P[r])});
+    }
+    std::vector<int32_t> item_of(patch.size(), 0);
+    for (size_t k = 0; k < h->items.size(); ++k)
+      for (int r = 0; r < h->items[k].n_patch; ++r) item_of[(size_t)h->items[k].patch_off + r] = (int32_t)k;
+    for (const auto &lst : lists) {
+      double sw = 0.0;
+      for (const auto &e : lst) sw += e.second;
+      for (const auto &e : lst) {
+        bent.push_back(e.first);
+        bitem.push_back(item_of[(size_t)e.first]);
+        bw.push_back(e.second / sw);
+      }
+      boff.push_back((int32_t)bent.size());
+    }
   }
 
   int rc = LETKF_OK;
@@ -1114,7 +1257,10 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
       (rc = to_device(&h->d_owner_item, owner_item)) || (rc = to_device(&h->d_minv_off, minv_off)) ||
       (rc = to_device(&h->d_minv, minv)) ||
       (rc = to_device(&h->d_prhs, std::vector<double>(std::max<size_t>(h->items.size(), 1), 0.0))) ||
-      (rc = to_device(&h->d_pi, std::vector<double>(std::max<size_t>(h->items.size(), 1), 0.0)))) {
+      (rc = to_device(&h->d_pi, std::vector<double>(std::max<size_t>(h->items.size(), 1), 0.0))) ||
+      (h->any_blend && ((rc = to_device(&h->d_boff, boff)) || (rc = to_device(&h->d_bent, bent)) ||
+                        (rc = to_device(&h->d_bitem, bitem)) || (rc = to_device(&h->d_bw, bw)) ||
+                        (rc = to_device(&h->d_smean, std::vector<double>(patch.size(), 0.0)))))) {
     free_handle(h);
     return rc;
   }
@@ -1135,6 +1281,14 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   }
   hipMemset(h->d_frame, 0, 16);
   hipMemset(h->d_flags, 0, std::max<size_t>(h->items.size(), 1) * 4);
+  if (h->any_blend) {
+    const size_t sb = std::max<size_t>(patch.size() * 64 * T, 16);
+    if (hipMalloc(&h->d_stage, sb) != hipSuccess) {
+      free_handle(h);
+      return fail(LETKF_E_NOMEM, "hipMalloc of the blend staging rows failed");
+    }
+    hipMemset(h->d_stage, 0, sb);
+  }
   if (h->any_ar2 || h->any_refit) {
     if (hipMalloc(&h->d_xprev, std::max<size_t>(xbytes, 16)) != hipSuccess) {
       free_handle(h);
@@ -1656,6 +1810,7 @@ int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, u
     return fail(LETKF_E_INVAL, "NULL argument");
   if (h->any_loop) return fail(LETKF_E_INVAL, "no adjoint for the closed-loop model");
   if (h->any_ar2) return fail(LETKF_E_INVAL, "no adjoint for the AR(2) model");
+  if (h->any_blend) return fail(LETKF_E_INVAL, "no adjoint for the blend-mode gather");
   if (h->any_refit) return fail(LETKF_E_INVAL, "no adjoint with the online refit");
   int rc = check_noise(h, V_dev);
   if (rc) return rc;

@@ -930,6 +930,8 @@ template <typename T> struct AnaArgs {
   const uint32_t *frame;  // frame counter of the bank draws (device)
   const T *u_prev2;       // closed loop: the command u_{k-2} per node (NULL: none)
   const T *x_prev;        // AR(2): the analysis ensemble of the frame before x_in (NULL: none)
+  T *stage;               // blend: analysed patch rows [patch entry][64] (NULL: no blend instance)
+  double *stage_mean;     // blend: their member means [patch entry]
   double jtol;
   int32_t max_sweeps;
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
@@ -1161,7 +1163,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   const DomItem it = A.items[item];
   const InstDesc in = A.inst[it.inst];
   const int m = in.m;
-  const int nown = it.n_own;
+  const int nown = it.n_own, np = it.n_patch;
   T *xs = (T *)(smem + A.off_xs);
   T *xm = (T *)(smem + A.off_xm);
   int *pn = (int *)(smem + A.off_pn);
@@ -1241,40 +1243,49 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     __syncthreads();
   }
 
-  // ---- 7. owned rows: X_a = (x_b + X' w) 1^T + sqrt(rho) X' W ----
+  // ---- 7. owned rows (blend: every patch row): X_a = (x_b + X' w) 1^T + sqrt(rho) X' W ----
   const bool keep_forecast = bad || !conv;
+  const bool blend = in.blend != 0 && A.stage;
+  const int nupd = blend ? np : nown;
   if (tid == 0) A.flags[item] = flag;
-  if (tid < nown) {
+  if (tid < nupd) {
     const double mu = (double)xm[tid];
     double s = mu;
     for (int k = 0; k < m; ++k) s = fma((double)xs[tid * kXsStride + k] - mu, sm[S_WV + k], s);
     sm[S_XAM + tid] = s;
-    // the piston fit reads this mean; in the closed loop it is the residual
-    // x_a - N u_{k-2} that the slopes y_k see
-    const T uo = (in.model == 1 && A.u_prev2) ? ((const T *)(pn + 128))[tid] : (T)0;
-    if (A.x_mean) A.x_mean[in.node_off + pn[tid]] = (keep_forecast ? xm[tid] : (T)s) - uo;
+    if (blend) {
+      A.stage_mean[it.patch_off + tid] = keep_forecast ? mu : s;
+    } else {
+      // the piston fit reads this mean; in the closed loop it is the residual
+      // x_a - N u_{k-2} that the slopes y_k see
+      const T uo = (in.model == 1 && A.u_prev2) ? ((const T *)(pn + 128))[tid] : (T)0;
+      if (A.x_mean) A.x_mean[in.node_off + pn[tid]] = (keep_forecast ? xm[tid] : (T)s) - uo;
+    }
   }
   __syncthreads();
   const T srho = (T)sqrt(in.rho);
   const int c16 = lane & 15, k4 = lane >> 4;
   const int J = q;  // this wave's 16 members
-  for (int I = 0; I * 16 < nown; ++I) {
+  for (int I = 0; I * 16 < nupd; ++I) {
     typename Mfma<T>::V o = Mfma<T>::zero();
     const int ia = 16 * I + c16;
-    const T mu = ia < nown ? xm[ia] : (T)0;
+    const T mu = ia < nupd ? xm[ia] : (T)0;
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       const int k = 4 * kk + k4;
-      const T av = (ia < nown && k < m) ? xs[ia * kXsStride + k] - mu : (T)0;
+      const T av = (ia < nupd && k < m) ? xs[ia * kXsStride + k] - mu : (T)0;
       o = Mfma<T>::mac(av, wf[kk], o);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * I + Mfma<T>::row(lane, r);
       const int j = 16 * J + c16;
-      if (i < nown && j < m) {
+      if (i < nupd && j < m) {
         const T v = keep_forecast ? xs[i * kXsStride + j] : (T)sm[S_XAM + i] + srho * o[r];
-        A.x_out[in.x_off + (int64_t)pn[i] * m + j] = v;
+        if (blend)
+          A.stage[(int64_t)(it.patch_off + i) * 64 + j] = v;
+        else
+          A.x_out[in.x_off + (int64_t)pn[i] * m + j] = v;
       }
     }
   }
@@ -2025,6 +2036,73 @@ __global__ __launch_bounds__(kThreads) void k_refit_finish(InstDesc *insts, Refi
   }
 }
 
+// Blend-mode gather (a variant of the Sec. 4.2 concatenation): every domain
+// has analysed all rows of its node patch into `stage` ([patch entry][64])
+// and their member means into `smean`.  The patches are first put on a
+// common piston: pi minimises the squared differences of the means of every
+// node held by two patches, i.e. L pi = rhs with L the graph Laplacian
+// weighted by the number of shared nodes (geometry only: its pseudo-inverse
+// is built once) and rhs_l = sum over the rows of patch l of the summed
+// differences (other patch's mean - this patch's mean) at that node.  Then
+// every node takes the normalised tent-weighted mean of its patch rows plus
+// their pistons.  The node -> (entry, item, weight) lists are in item order,
+// so every sum runs in a fixed order.
+
+// rhs[item], one wavefront per item (lane = patch row).
+__global__ __launch_bounds__(kThreads) void k_blend_rhs(const InstDesc *insts, const DomItem *items, int n_items,
+                                                        const int32_t *patch_node, const double *smean,
+                                                        const int32_t *boff, const int32_t *bent, double *rhs) {
+  const int item = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (item >= n_items) return;  // whole wavefront
+  const DomItem it = items[item];
+  const InstDesc in = insts[it.inst];
+  if (!in.blend) return;
+  double v = 0.0;
+  if (lane < it.n_patch) {
+    const int e0 = it.patch_off + lane;
+    const int64_t node = in.node_off + patch_node[e0];
+    const double self = smean[e0];
+    for (int k = boff[node]; k < boff[node + 1]; ++k) v += smean[bent[k]] - self;
+  }
+  v = wave_sum(v);
+  if (lane == 0) rhs[item] = v;
+}
+
+// pi[item] = row of L^+ times the instance's rhs, one wavefront per item.
+__global__ __launch_bounds__(kThreads) void k_blend_solve(const InstDesc *insts, const DomItem *items, int n_items,
+                                                          const int32_t *dom_base, const int64_t *minv_off,
+                                                          const double *minv, const double *rhs, double *pi) {
+  const int item = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (item >= n_items) return;  // whole wavefront
+  const DomItem it = items[item];
+  if (!insts[it.inst].blend) return;
+  const int b0 = dom_base[it.inst], nd = dom_base[it.inst + 1] - b0;
+  const double *row = minv + minv_off[it.inst] + (int64_t)(item - b0) * nd;
+  double v = 0.0;
+  for (int e = lane; e < nd; e += 64) v = fma(row[e], rhs[b0 + e], v);
+  v = wave_sum(v);
+  if (lane == 0) pi[item] = v;
+}
+
+// X_a(node) = sum_k w_k (stage row k + pi of its item), one wavefront per node
+// (lane = member), grid (ceil(max nodes / 4), instances); the frame counter
+// of the bank draws advances here when `frame` is given.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_blend_gather(const InstDesc *insts, const int32_t *boff,
+                                                           const int32_t *bent, const int32_t *bitem,
+                                                           const double *bw, const T *stage, const double *pi,
+                                                           T *x, uint32_t *frame) {
+  if (frame && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *frame += 1u;
+  const InstDesc in = insts[blockIdx.y];
+  const int g = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (!in.blend || g >= in.n_nodes || lane >= in.m) return;
+  const int64_t node = in.node_off + g;
+  double acc = 0.0;
+  for (int k = boff[node]; k < boff[node + 1]; ++k)
+    acc = fma(bw[k], (double)stage[(int64_t)bent[k] * 64 + lane] + pi[bitem[k]], acc);
+  x[in.x_off + (int64_t)g * in.m + lane] = (T)acc;
+}
+
 __global__ void k_frame_advance(uint32_t *frame) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *frame += 1u;
 }
@@ -2160,6 +2238,32 @@ extern "C" hipError_t letkf_launch_refit(int fp64, void *insts, void *rs, const 
                        (const RefitState *)rs, (const float *)x_now, (const float *)x_prev, part, stride);
   hipLaunchKernelGGL(k_refit_finish, dim3(n_inst), dim3(kThreads), 0, s, (InstDesc *)insts, (RefitState *)rs,
                      (const double *)part, stride);
+  return hipGetLastError();
+}
+
+extern "C" const void *letkf_blend_rhs_kernel(void) { return (const void *)k_blend_rhs; }
+extern "C" const void *letkf_blend_solve_kernel(void) { return (const void *)k_blend_solve; }
+extern "C" const void *letkf_blend_gather_kernel(int fp64) {
+  return fp64 ? (const void *)k_blend_gather<double> : (const void *)k_blend_gather<float>;
+}
+
+extern "C" hipError_t letkf_launch_blend(int fp64, const InstDesc *insts, const DomItem *items, int n_items,
+                                         const int32_t *patch_node, const double *smean, const int32_t *boff,
+                                         const int32_t *bent, const int32_t *bitem, const double *bw,
+                                         const int32_t *dom_base, const int64_t *minv_off, const double *minv,
+                                         double *rhs, double *pi, const void *stage, void *x, uint32_t *frame,
+                                         int max_nodes, int n_inst, hipStream_t s) {
+  const dim3 gi((n_items + kWaves - 1) / kWaves), gn((max_nodes + kWaves - 1) / kWaves, n_inst);
+  hipLaunchKernelGGL(k_blend_rhs, gi, dim3(kThreads), 0, s, insts, items, n_items, patch_node, smean, boff, bent,
+                     rhs);
+  hipLaunchKernelGGL(k_blend_solve, gi, dim3(kThreads), 0, s, insts, items, n_items, dom_base, minv_off, minv,
+                     (const double *)rhs, pi);
+  if (fp64)
+    hipLaunchKernelGGL(k_blend_gather<double>, gn, dim3(kThreads), 0, s, insts, boff, bent, bitem, bw,
+                       (const double *)stage, (const double *)pi, (double *)x, frame);
+  else
+    hipLaunchKernelGGL(k_blend_gather<float>, gn, dim3(kThreads), 0, s, insts, boff, bent, bitem, bw,
+                       (const float *)stage, (const double *)pi, (float *)x, frame);
   return hipGetLastError();
 }
 

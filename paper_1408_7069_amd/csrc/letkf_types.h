@@ -23,7 +23,7 @@ struct InstDesc {
   uint32_t instance;
   int32_t piston;      // 1: differential-piston removal after the gather
   int32_t model;       // 0: delay-free phase state; 1: closed loop (delayed slopes, DM terms)
-  int32_t pad1;
+  int32_t blend;       // 1: blend-mode gather (every patch row staged, aligned and blended)
   double a, rho, r_scale, taper_c;
   double a2;           // AR(2): X_b = a X_a(k) + a2 X_a(k-1) + V (0: AR(1))
   double vscale;       // factor on the model noise V (1; the online refit sets it)
