@@ -134,7 +134,9 @@ def model_variants(B, spec, wl_mod, w, y, truth, ij, K, W, frames=300, a0s=(0.9,
     mismatched a0 a loop over the staged slopes (true a = w.a) with model
     noise drawn for a0: the residual variance of the analysis mean over the
     second half with the model fixed at a0 and with the refit, and the
-    refit's final coefficient."""
+    refit's final coefficient; then the blend-mode gather: its frame time and
+    the same residual variance against the concatenation with the piston
+    step."""
     import dataclasses
     import torch
     out = {}
@@ -166,6 +168,22 @@ def model_variants(B, spec, wl_mod, w, y, truth, ij, K, W, frames=300, a0s=(0.9,
             g.close()
         loops.append(row)
     out.update({"true_a": w.a, "forgetting": forgetting, "loop_frames": T, "loops": loops})
+    # the blend-mode gather against the concatenation with the piston step
+    g = B.Letkf([dataclasses.replace(spec, gather_mode=B.GATHER_BLEND, piston=False)])
+    g.set_schedule(True, True)
+    blend = {"ms_per_step": round(time_steps(g, y, K, W), 5)}
+    g.close()
+    for name, kw in (("concat_piston", {}), ("blend", {"gather_mode": B.GATHER_BLEND, "piston": False})):
+        g = B.Letkf([dataclasses.replace(spec, **kw)])
+        g.set_schedule(True, True)
+        var = []
+        for k in range(T):
+            g.step(y[k])
+            if k >= T // 2:
+                var.append(float(torch.var(g.get_mean() - ph[k], unbiased=False)))
+        blend[name + "_residual_variance"] = round(float(np.mean(var)), 5)
+        g.close()
+    out["blend_gather"] = blend
     return out
 
 
