@@ -25,4 +25,7 @@ Modules
               model-noise scale that follows it (Sec. 4.2)
   blend       blend-mode gather: patch analyses put on a common piston and
               averaged with tent weights (a variant of the Sec. 4.2 gather)
+  cl          covariance localisation (Sec. 4): the patch covariance tapered
+              by a Schur product, Kalman gain in slope space, deterministic
+              EnKF anomalies
 """
