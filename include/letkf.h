@@ -93,6 +93,9 @@ extern "C" {
 /* letkf_config.gather_mode */
 #define LETKF_GATHER_CONCAT 0
 #define LETKF_GATHER_BLEND 1
+/* letkf_config.localisation */
+#define LETKF_LOCALISATION_DOMAIN 0
+#define LETKF_LOCALISATION_COVARIANCE 1
 
 /* Per-domain status bits (letkf_status); bits 8-15 hold the steps the
  * transform took (Newton-Schulz steps, or Jacobi sweeps begun). */
@@ -183,6 +186,27 @@ typedef struct letkf_config {
                                   domain's block, normalised over the patches.
                                   Needs piston_removal off (the alignment takes
                                   its place); no adjoint.                         */
+  int32_t localisation;        /* LETKF_LOCALISATION_DOMAIN (0): the local
+                                  analysis of Sec. 4.2 (ensemble transform per
+                                  domain).  LETKF_LOCALISATION_COVARIANCE (1):
+                                  covariance localisation (Sec. 4 names it):
+                                  per domain, over its node patch, the prior
+                                  covariance rho_xx o (rho X'X'^T / (m-1)) with
+                                  rho_xx the Gaspari-Cohn function of the node
+                                  distance over taper_c (0: no taper; the
+                                  observation weights are then not tapered),
+                                  the gain K = P D^T (D P D^T + R)^{-1} of the
+                                  owned rows from an FP64 Cholesky of the p_l x
+                                  p_l matrix, x_a = x_b + K d and the anomalies
+                                  sqrt(rho) (X' - K D X' / 2) (deterministic
+                                  EnKF); the transform field is ignored.  Same
+                                  for all instances of a handle; delay-free
+                                  model only, no blend-mode gather, no adjoint.  Needs LDS for the patch
+                                  rows and three FP64 arrays of about p_l^2,
+                                  patch x p_l and n_own x p_l doubles:
+                                  letkf_create fails with LETKF_E_INVAL when
+                                  the device has too little (b = 4, h = 1 fits
+                                  in both precisions).                            */
 } letkf_config;
 
 /* Sizes of one instance (or totals when instance = -1). */
@@ -360,8 +384,9 @@ int letkf_residual_variance_adjoint(letkf_handle *h, const void *xa_dev, const v
  * runs the Jacobi to min(jacobi_tol, 1e-6) (the forward's transform W only
  * needs the looser default).  Returns LETKF_E_INVAL when the device cannot
  * give the adjoint kernel its LDS, and for handles with a closed-loop
- * instance, an AR(2) model, the online refit or the blend-mode gather (the
- * frame it reverses is the delay-free AR(1) one with the concatenation). */
+ * instance, an AR(2) model, the online refit, the blend-mode gather or
+ * covariance localisation (the frame it reverses is the delay-free AR(1) one
+ * with the local analysis and the concatenation). */
 int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, uint32_t frame,
                   const void *y_dev, void *xbar_dev, double *theta_bar_dev, void *stream);
 

@@ -30,6 +30,7 @@ FLAG_NONFINITE, FLAG_NOCONV = 1, 2
 TRANSFORM_NS64, TRANSFORM_NS32, TRANSFORM_EVD = 0, 1, 2
 MODEL_PHASE, MODEL_CLOSED_LOOP = 0, 1
 GATHER_CONCAT, GATHER_BLEND = 0, 1
+LOCALISATION_DOMAIN, LOCALISATION_COVARIANCE = 0, 1
 
 
 class Config(C.Structure):
@@ -59,6 +60,7 @@ class Config(C.Structure):
         ("ar2_coeff", C.c_double),
         ("refit_forgetting", C.c_double),
         ("gather_mode", C.c_int32),
+        ("localisation", C.c_int32),
     ]
 
 
@@ -161,6 +163,7 @@ class InstanceSpec:
     ar2_coeff: float = 0.0                # a2 of an AR(2) turbulence model (0: AR(1))
     refit_forgetting: float = 0.0         # online AR(1) refit with this forgetting factor (0: off)
     gather_mode: int = 0                  # GATHER_CONCAT, or GATHER_BLEND (aligned, tent-weighted patches)
+    localisation: int = 0                 # LOCALISATION_DOMAIN, or LOCALISATION_COVARIANCE (Schur-tapered P)
 
 
 def _config(spec: InstanceSpec, keep: list) -> Config:
@@ -199,6 +202,7 @@ def _config(spec: InstanceSpec, keep: list) -> Config:
     c.ar2_coeff = spec.ar2_coeff
     c.refit_forgetting = spec.refit_forgetting
     c.gather_mode = spec.gather_mode
+    c.localisation = spec.localisation
     return c
 
 

@@ -144,6 +144,7 @@ template <typename T> struct AnaArgsHost {
   double jtol;
   int32_t max_sweeps;
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
+  int32_t off_clb, off_clr;
 };
 
 // Mirror of PistonArgs<T>.
@@ -215,6 +216,7 @@ struct letkf_handle {
   size_t lds = 0;
   int32_t off[9] = {0};      // LDS layout of the adjoint's forward stages
   int32_t fwd_off[9] = {0};  // LDS layout of the analysis
+  int32_t cl_off[2] = {0, 0};  // covariance localisation: offsets of B and of the solve's columns
   // device
   InstDesc *d_desc = nullptr;
   DomItem *d_items = nullptr;
@@ -559,6 +561,12 @@ int validate(const letkf_config &c, int idx, std::string &err) {
     err = o.str() + "the online refit needs ar_coeff in [0, 1)";
   else if (c.gather_mode != LETKF_GATHER_CONCAT && c.gather_mode != LETKF_GATHER_BLEND)
     err = o.str() + "unknown gather_mode";
+  else if (c.localisation != LETKF_LOCALISATION_DOMAIN && c.localisation != LETKF_LOCALISATION_COVARIANCE)
+    err = o.str() + "unknown localisation";
+  else if (c.localisation == LETKF_LOCALISATION_COVARIANCE && c.gather_mode == LETKF_GATHER_BLEND)
+    err = o.str() + "covariance localisation updates the owned rows only: no blend-mode gather";
+  else if (c.localisation == LETKF_LOCALISATION_COVARIANCE && c.model != LETKF_MODEL_PHASE)
+    err = o.str() + "covariance localisation runs with the delay-free phase state only";
   else if (c.gather_mode == LETKF_GATHER_BLEND && c.piston_removal)
     err = o.str() + "the blend-mode gather aligns the patch pistons itself: piston_removal must be off";
   else if (c.noise_bank && (c.bank_screens < 1 || c.bank_side < c.n_sub + 1 ||
@@ -640,6 +648,8 @@ AnaArgsHost<T> make_args(letkf_handle *h, bool fused, const void *V, const void 
   A.u_prev2 = h->any_loop ? (const T *)h->d_u2 : nullptr;
   A.x_prev = h->any_ar2 ? (const T *)h->d_xprev : nullptr;
   A.stage = h->any_blend ? (T *)h->d_stage : nullptr;
+  A.off_clb = h->cl_off[0];
+  A.off_clr = h->cl_off[1];
   A.stage_mean = h->d_smean;
   A.flags = h->d_flags;
   A.frame = h->d_frame;
@@ -958,6 +968,8 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
       return fail(LETKF_E_INVAL, "all instances of a handle must share the precision");
     if (cfgs[i].transform != cfgs[0].transform)
       return fail(LETKF_E_INVAL, "all instances of a handle must share the transform");
+    if (cfgs[i].localisation != cfgs[0].localisation)
+      return fail(LETKF_E_INVAL, "all instances of a handle must share the localisation");
   }
   if (cfgs[0].transform != LETKF_TRANSFORM_NS64 && cfgs[0].transform != LETKF_TRANSFORM_NS32 &&
       cfgs[0].transform != LETKF_TRANSFORM_EVD)
@@ -971,6 +983,8 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   h->max_sweeps = cfgs[0].max_sweeps > 0 ? cfgs[0].max_sweeps : 30;
   h->transform = cfgs[0].transform;
   if (h->fp64 && h->transform == LETKF_TRANSFORM_NS32) h->transform = LETKF_TRANSFORM_NS64;
+  // covariance localisation has its own kernel (no transform)
+  if (cfgs[0].localisation == LETKF_LOCALISATION_COVARIANCE) h->transform = kAnalysisCl;
   h->geom.resize(n_instances);
   std::vector<int32_t> patch, obs_sub, node_ij, subap_nodes;
   std::vector<uint32_t> obs_corner;
@@ -1120,6 +1134,19 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     h->fwd_off[7] = (int32_t)ub;
     h->fwd_off[8] = (int32_t)(ub + uf - ys_bytes);
     h->lds = align16(ub + uf);
+    if (h->transform == kAnalysisCl) {
+      // covariance localisation: every patch row (read again by the update),
+      // then S (first X'_P^T and P_loc), B and the solve's columns; no slope
+      // operand
+      const size_t pmax = 2 * (size_t)h->max_obs_sub, ld = pmax + 1;
+      const size_t rows = align16(f + (size_t)h->max_patch * kXsStride * T);
+      const size_t sreg = std::max({(size_t)64 * 65 * 8, (size_t)64 * kYsStride * 8, pmax * ld * 8});
+      h->fwd_off[7] = (int32_t)rows;
+      h->fwd_off[8] = (int32_t)rows;
+      h->cl_off[0] = (int32_t)align16(rows + sreg);
+      h->cl_off[1] = (int32_t)align16(h->cl_off[0] + (size_t)h->max_patch * ld * 8);
+      h->lds = align16(h->cl_off[1] + ((size_t)h->max_own + 1) * ld * 8);
+    }
   }
   {  // the adjoint kernel: a larger U area (FP64 64 x 64), Q, a second matrix, scratch
     size_t oa = align16(o + std::max(u, (size_t)64 * 65 * 8));
@@ -1227,6 +1254,16 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   if (e != hipSuccess) {
     free_handle(h);
     return fail(LETKF_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  }
+  {
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+        h->lds > (size_t)max_lds) {
+      const std::string msg = "the analysis needs " + std::to_string(h->lds) + " bytes of LDS, the device gives " +
+                              std::to_string(max_lds) + " (smaller domains or halo)";
+      free_handle(h);
+      return fail(LETKF_E_INVAL, msg);
+    }
   }
   for (int fused = 0; fused < 2; ++fused)
     hipFuncSetAttribute(letkf_analysis_kernel(h->fp64, fused, h->transform),
@@ -1811,6 +1848,7 @@ int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, u
   if (h->any_loop) return fail(LETKF_E_INVAL, "no adjoint for the closed-loop model");
   if (h->any_ar2) return fail(LETKF_E_INVAL, "no adjoint for the AR(2) model");
   if (h->any_blend) return fail(LETKF_E_INVAL, "no adjoint for the blend-mode gather");
+  if (h->transform == kAnalysisCl) return fail(LETKF_E_INVAL, "no adjoint for covariance localisation");
   if (h->any_refit) return fail(LETKF_E_INVAL, "no adjoint with the online refit");
   int rc = check_noise(h, V_dev);
   if (rc) return rc;

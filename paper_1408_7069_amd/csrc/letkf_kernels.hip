@@ -935,6 +935,7 @@ template <typename T> struct AnaArgs {
   double jtol;
   int32_t max_sweeps;
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
+  int32_t off_clb, off_clr;  // covariance localisation: B and the solve's columns
 };
 
 __device__ inline int xcd_item(int b, int grid) {
@@ -957,8 +958,9 @@ struct CoreStatus {
 
 // Stages 1-3: on return A~ = c I + Yt^T Yt (FP64, both triangles) at the start
 // of the U area, b = Yt^T sqrt(g) d in sm[S_VEC]; returns whether an
-// observation was not finite.
-template <typename T, bool FUSED, bool G32 = false>
+// observation was not finite.  CL (covariance localisation): stages 1-2 only,
+// without the taper on the observation weights and without the slope operand.
+template <typename T, bool FUSED, bool G32 = false, bool CL = false>
 __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &it, const InstDesc &in,
                                            uint32_t frame, unsigned char *smem) {
   const int tid = threadIdx.x;
@@ -1039,7 +1041,7 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
     const int ca = cw & 255, cb = (cw >> 8) & 255, cc = (cw >> 16) & 255, cd = cw >> 24;
     const T ybx = (T)0.5 * ((xm[cb] - xm[ca]) + (xm[cd] - xm[cc]));
     const T yby = (T)0.5 * ((xm[cc] - xm[ca]) + (xm[cd] - xm[cb]));
-    const double f = in.taper_c > 0.0 ? gaspari_cohn(A.obs_dist[it.obs_off + tid] / in.taper_c) : 1.0;
+    const double f = (!CL && in.taper_c > 0.0) ? gaspari_cohn(A.obs_dist[it.obs_off + tid] / in.taper_c) : 1.0;
     const double rx = A.r_diag[in.y_off + k], ry = A.r_diag[in.y_off + in.n_subaps + k];
     const double sgx = f / sqrt(in.r_scale * rx), sgy = f / sqrt(in.r_scale * ry);
     const double yx = (double)A.y[in.y_off + k], yy = (double)A.y[in.y_off + in.n_subaps + k];
@@ -1058,6 +1060,7 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
     yb[nobs + tid] = yby;
   }
   bad = __syncthreads_or(bad);
+  if constexpr (CL) return bad != 0;
   T *ys = (T *)(smem + A.off_ys);  // [p4][kYsStride], K-major MFMA operand
   for (int o = q; o < nobs; o += kWaves) {
     const uint32_t cw = A.obs_corner[it.obs_off + o];
@@ -1287,6 +1290,202 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         else
           A.x_out[in.x_off + (int64_t)pn[i] * m + j] = v;
       }
+    }
+  }
+}
+
+// ------------------------------------------------- covariance localisation
+// The localisation Sec. 4 names beside the local analysis: the prior
+// covariance tapered by a Schur product.  Per domain, over its node patch,
+//   P_loc = rho_xx o (kappa X'_P X'_P^T),  kappa = rho / (m - 1),
+// rho_xx the Gaspari-Cohn function of the node distance over c = taper_c
+// (c = 0: no taper); with the whitened local slope operator Dt (rows scaled
+// by 1 / sqrt(s r)) and the whitened innovation dd,
+//   B = P_loc Dt^T (patch x p),  S = Dt B + I (p x p, FP64 Cholesky),
+//   [K^T | v] = S^{-1} [B_own^T | dd],
+//   x_a = x_b + K dd,  X'_a = sqrt(rho) (X'_own - K Dt X'_P / 2)
+// (the deterministic EnKF update of the anomalies), written to the owned
+// rows.  LDS: the patch rows, then S (first X'_P^T and P_loc, both FP64), B
+// and the solve's columns (offsets from the host).
+constexpr int kEigCl = kAnalysisCl;
+
+template <typename T, bool FUSED>
+__global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+  const int q = tid >> 6, lane = tid & 63;
+  int item = A.xcd_order ? xcd_item((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  item += A.item_base;
+  if (item >= A.n_items) return;
+  const DomItem it = A.items[item];
+  const InstDesc in = A.inst[it.inst];
+  const int m = in.m, np = it.n_patch, nown = it.n_own, nobs = it.n_obs, p = 2 * nobs, ldp = p + 1;
+  T *xs = (T *)(smem + A.off_xs);
+  T *xm = (T *)(smem + A.off_xm);
+  const double *sg = (const double *)(smem + A.off_sg);
+  const double *dd = (const double *)(smem + A.off_dd);
+  uint32_t *cw = (uint32_t *)(smem + A.off_yb);  // corner words of the region's subapertures
+  int *pn = (int *)(smem + A.off_pn);
+  double *dg = (double *)(smem + A.off_s);       // pivots sqrt(S_kk) of the Cholesky
+  double *xt = (double *)(smem + A.off_u);       // X'_P^T in FP64, [member][kYsStride]
+  double *Pm = (double *)(smem + A.off_u);       // P_loc [64][kLaStride], then S [p][ldp]
+  double *Bm = (double *)(smem + A.off_clb);     // [patch row][ldp]
+  double *R = (double *)(smem + A.off_clr);      // column c at R + c ldp
+  const uint32_t frame = (FUSED && A.noise_bank) ? *A.frame : 0u;
+  bool bad = stage_gram<T, FUSED, false, true>(A, it, in, frame, smem);
+
+  // ---- 3. P_loc ----
+  if (tid < nobs) cw[tid] = A.obs_corner[it.obs_off + tid];
+  if (tid < np) {
+    const int64_t g = in.node_off + pn[tid];
+    pn[64 + tid] = A.node_ij[2 * g] | (A.node_ij[2 * g + 1] << 16);
+  }
+  for (int e = tid; e < 64 * 64; e += kThreads) {
+    const int k = e >> 6, r = e & 63;
+    xt[k * kYsStride + r] = (r < np && k < m) ? (double)xs[r * kXsStride + k] - (double)xm[r] : 0.0;
+  }
+  __syncthreads();
+  {
+    // in FP64 in both precisions: the slope stencil applied to P_loc below
+    // cancels most of its size (the phase is smooth), so an FP32 product's
+    // rounding would come out amplified
+    typename Mfma<double>::V acc[3];
+    syrk_share<double>(xt, kYsStride, 16, acc, q, lane);
+    __syncthreads();
+    syrk_store_f64<double>(acc, Pm, 0.0, q, lane);
+  }
+  __syncthreads();
+  const double kap = in.rho / (double)(m - 1), cw_taper = in.taper_c;
+  for (int e = tid; e < np * np; e += kThreads) {
+    const int i = e / np, j = e - i * np;
+    double t = kap;
+    if (cw_taper > 0.0) {
+      const int a = pn[64 + i], b = pn[64 + j];
+      const double di = (double)((a & 0xFFFF) - (b & 0xFFFF)), dj = (double)((a >> 16) - (b >> 16));
+      t *= gaspari_cohn(sqrt(di * di + dj * dj) / cw_taper);
+    }
+    Pm[i * kLaStride + j] *= t;
+  }
+  __syncthreads();
+
+  // ---- 4. B = P_loc Dt^T ----
+  for (int e = tid; e < np * p; e += kThreads) {
+    const int i = e / p, s = e - i * p;
+    const uint32_t w = cw[s < nobs ? s : s - nobs];
+    const int ca = w & 255, cb = (w >> 8) & 255, cc = (w >> 16) & 255, cd = w >> 24;
+    const double *Pi = Pm + i * kLaStride;
+    const double v = s < nobs ? (Pi[cb] - Pi[ca]) + (Pi[cd] - Pi[cc]) : (Pi[cc] - Pi[ca]) + (Pi[cd] - Pi[cb]);
+    Bm[i * ldp + s] = 0.5 * sg[s] * v;
+  }
+  __syncthreads();
+
+  // ---- 5. S = Dt B + I (lower triangle, over P_loc) and the right-hand sides ----
+  double *S = Pm;
+  for (int e = tid; e < p * p; e += kThreads) {
+    const int s = e / p, t = e - s * p;
+    if (t > s) continue;
+    const uint32_t w = cw[s < nobs ? s : s - nobs];
+    const int ca = w & 255, cb = (w >> 8) & 255, cc = (w >> 16) & 255, cd = w >> 24;
+    const double ba = Bm[ca * ldp + t], bb = Bm[cb * ldp + t], bc = Bm[cc * ldp + t], bd = Bm[cd * ldp + t];
+    const double v = s < nobs ? (bb - ba) + (bd - bc) : (bc - ba) + (bd - bb);
+    S[s * ldp + t] = 0.5 * sg[s] * v + (s == t ? 1.0 : 0.0);
+  }
+  for (int e = tid; e < (nown + 1) * p; e += kThreads) {
+    const int c = e / p, s = e - c * p;
+    R[c * ldp + s] = c < nown ? Bm[c * ldp + s] : dd[s];
+  }
+  __syncthreads();
+
+  // ---- 6. Cholesky S = L L^T in place, one barrier a column: step k
+  // updates the trailing triangle from the unscaled column k and scales
+  // column k - 1 by its pivot (no other access to that column in step k) ----
+  int fail = 0;
+  for (int k = 0; k < p; ++k) {
+    const double dkk = S[k * ldp + k];
+    fail |= !(dkk > 0.0);
+    if (k > 0) {
+      const double piv = dg[k - 1];
+      for (int i = k + tid; i < p; i += kThreads) S[i * ldp + k - 1] /= piv;
+      if (tid == 0) S[(k - 1) * ldp + k - 1] = piv;
+    }
+    if (tid == 0) dg[k] = sqrt(dkk);
+    const double inv = 1.0 / dkk;
+    const int n = p - k - 1;
+    for (int e = tid; e < n * n; e += kThreads) {
+      const int r = e / n, i = k + 1 + r, j = k + 1 + (e - r * n);
+      if (j <= i) S[i * ldp + j] -= S[i * ldp + k] * S[j * ldp + k] * inv;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && p > 0) S[(p - 1) * ldp + p - 1] = dg[p - 1];
+  bad = bad || fail;
+  __syncthreads();
+
+  // ---- 7. [K^T | v] = S^{-1} [B_own^T | dd]: eight lanes a column ----
+  const int nc = nown + 1, sub = tid & 7;
+  for (int c0 = 0; c0 < nc; c0 += kThreads / 8) {
+    const int c = c0 + (tid >> 3);
+    const bool act = c < nc && !bad;
+    double *col = R + (c < nc ? c : 0) * ldp;
+    for (int i = 0; i < p; ++i) {
+      double part = 0.0;
+      if (act)
+        for (int k = sub; k < i; k += 8) part = fma(S[i * ldp + k], col[k], part);
+      part += __shfl_xor(part, 1, 8);
+      part += __shfl_xor(part, 2, 8);
+      part += __shfl_xor(part, 4, 8);
+      if (act) {
+        const double yi = (col[i] - part) / S[i * ldp + i];
+        col[i] = yi;  // the same value from all eight lanes
+      }
+    }
+    for (int i = p - 1; i >= 0; --i) {
+      double part = 0.0;
+      if (act)
+        for (int k = i + 1 + sub; k < p; k += 8) part = fma(S[k * ldp + i], col[k], part);
+      part += __shfl_xor(part, 1, 8);
+      part += __shfl_xor(part, 2, 8);
+      part += __shfl_xor(part, 4, 8);
+      if (act) {
+        const double xi = (col[i] - part) / S[i * ldp + i];
+        col[i] = xi;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 8. owned rows: x_a = x_b + K dd, X'_a = sqrt(rho) (X' - K Dt X'_P / 2) ----
+  if (tid == 0) A.flags[item] = bad ? 1 : 0;
+  const double srho = sqrt(in.rho);
+  for (int i = q; i < nown; i += kWaves) {
+    const double *Ki = R + i * ldp;
+    double xa = (double)xm[i];
+    if (!bad)
+      for (int s = 0; s < p; ++s) xa = fma(Ki[s], dd[s], xa);
+    if (lane < m) {
+      double v;
+      if (bad) {
+        v = (double)xs[i * kXsStride + lane];
+      } else {
+        double corr = 0.0;
+        for (int s = 0; s < p; ++s) {
+          const uint32_t w = cw[s < nobs ? s : s - nobs];
+          const int ca = w & 255, cb = (w >> 8) & 255, cc = (w >> 16) & 255, cd = w >> 24;
+          const double pa = (double)xs[ca * kXsStride + lane] - (double)xm[ca];
+          const double pb = (double)xs[cb * kXsStride + lane] - (double)xm[cb];
+          const double pc = (double)xs[cc * kXsStride + lane] - (double)xm[cc];
+          const double pd = (double)xs[cd * kXsStride + lane] - (double)xm[cd];
+          const double yv = 0.5 * sg[s] * (s < nobs ? (pb - pa) + (pd - pc) : (pc - pa) + (pd - pb));
+          corr = fma(Ki[s], yv, corr);
+        }
+        v = xa + srho * (((double)xs[i * kXsStride + lane] - (double)xm[i]) - 0.5 * corr);
+      }
+      A.x_out[in.x_off + (int64_t)pn[i] * m + lane] = (T)v;
+    }
+    if (lane == 0 && A.x_mean) {
+      // the piston fit reads this mean (in the closed loop: x_a - N u_{k-2})
+      const T uo = (in.model == 1 && A.u_prev2) ? ((const T *)(pn + 128))[i] : (T)0;
+      A.x_mean[in.node_off + pn[i]] = (T)xa - uo;
     }
   }
 }
@@ -2175,6 +2374,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 using namespace letkf;
 
 template <typename T> static const void *analysis_kernel_of(int fused, int eig) {
+  if (eig == kEigCl)
+    return fused ? (const void *)k_analysis_cl<T, true> : (const void *)k_analysis_cl<T, false>;
   if (eig == kEigJacobi)
     return fused ? (const void *)k_analysis<T, true, kEigJacobi> : (const void *)k_analysis<T, false, kEigJacobi>;
   if (eig == kEigNs32 && sizeof(T) == 4)
