@@ -136,7 +136,7 @@ def model_variants(B, spec, wl_mod, w, y, truth, ij, K, W, frames=300, a0s=(0.9,
     second half with the model fixed at a0 and with the refit, and the
     refit's final coefficient; then the blend-mode gather: its frame time and
     the same residual variance against the concatenation with the piston
-    step."""
+    step; covariance localisation likewise against the local analysis."""
     import dataclasses
     import torch
     out = {}
@@ -184,6 +184,25 @@ def model_variants(B, spec, wl_mod, w, y, truth, ij, K, W, frames=300, a0s=(0.9,
         blend[name + "_residual_variance"] = round(float(np.mean(var)), 5)
         g.close()
     out["blend_gather"] = blend
+    # covariance localisation (2-pitch taper, pistons) against the local analysis
+    cl = {}
+    for name, kw in (("cl_taper2", {"localisation": B.LOCALISATION_COVARIANCE, "taper_c": 2.0}),
+                     ("cl_untapered", {"localisation": B.LOCALISATION_COVARIANCE, "taper_c": 0.0})):
+        g = B.Letkf([dataclasses.replace(spec, **kw)])
+        g.set_schedule(True, True)
+        if name == "cl_taper2":
+            cl["ms_per_step"] = round(time_steps(g, y, K, W), 5)
+            g.set_ensemble(torch.zeros(g.sizes["ensemble_elems"], dtype=torch.float32, device="cuda"))
+            g.set_frame(0)
+        var = []
+        for k in range(T):
+            g.step(y[k])
+            if k >= T // 2:
+                var.append(float(torch.var(g.get_mean() - ph[k], unbiased=False)))
+        cl[name + "_residual_variance"] = round(float(np.mean(var)), 5)
+        g.close()
+    cl["local_analysis_residual_variance"] = blend["concat_piston_residual_variance"]
+    out["covariance_localisation"] = cl
     return out
 
 
