@@ -640,6 +640,53 @@ __device__ inline void store_colblock(double *M, const ColBlock &B, int q, int l
 
 __device__ inline double sum4(const double *v) { return (v[0] + v[1]) + (v[2] + v[3]); }
 
+// Products of symmetric iterates by tiles: wave q computes the tiles (I, q) of
+// its column block for I = q and I in {1, 2}, {2, 3}, {3}, {0} (q = 0..3), and
+// stores each with its mirror (q, I); the ten tiles and their mirrors cover
+// the 4 x 4 tiles once, 3, 3, 2, 2 to a wave.
+// C = M B on this wave's tiles of its column block (the others are left as
+// they were); the tile choice is uniform across the wave.
+__device__ inline void mm_colblock_sym(const double *M, const ColBlock &B, ColBlock &C, int q, int lane) {
+  const int c16 = lane & 15, k4 = lane >> 4;
+  const int mask = (0x9CE7 >> (4 * q)) & 15;
+  bool on[4];
+#pragma unroll
+  for (int I = 0; I < 4; ++I) {
+    on[I] = (mask >> I) & 1;
+    if (on[I]) C[I] = Mfma<double>::zero();
+  }
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const double b = B[kk >> 2][kk & 3];
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+      if (on[I]) C[I] = Mfma<double>::mac(M[(16 * I + c16) * kLaStride + 4 * kk + k4], b, C[I]);
+  }
+}
+
+// Store this wave's tiles of its column block and their mirrors.
+__device__ inline void store_colblock_sym(double *M, const ColBlock &B, int q, int lane) {
+  const int c = 16 * q + (lane & 15), k4 = lane >> 4;
+  const int mask = (0x9CE7 >> (4 * q)) & 15;
+#pragma unroll
+  for (int I = 0; I < 4; ++I) {
+    if (!((mask >> I) & 1)) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * I + k4 + 4 * r;
+      M[row * kLaStride + c] = B[I][r];
+      if (I != q) M[c * kLaStride + row] = B[I][r];
+    }
+  }
+}
+
+__device__ inline void load_colblock(const double *M, ColBlock &B, int q, int lane) {
+#pragma unroll
+  for (int I = 0; I < 4; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) B[I][r] = M[(16 * I + (lane >> 4) + 4 * r) * kLaStride + 16 * q + (lane & 15)];
+}
+
 struct IsqrtStatus {
   int iters;       // products of the iteration taken (negative: no convergence)
   bool finite;
@@ -658,11 +705,19 @@ struct IsqrtStatus {
 // same image (l_{k+1}), so l_k grows by up to 27/4 a step while far from 1
 // and converges quadratically near it; a_k -> 1 there.  Z and Y are carried
 // as separate products (the coupled form is numerically stable; folding
-// Y = A Z, or symmetrising the iterates, is not).  The iteration stops once
+// Y = A Z is not).  The new Y and Z are symmetric polynomials in A, so each is
+// formed on ten of its sixteen 16 x 16 tiles and mirrored (a quarter of the
+// matrix-core work of a step); Z Y is formed in full, because mirroring it too
+// cost two digits of the result on the steady-state 80 x 80 matrices, while
+// mirroring Y and Z only kept W within 1e-12 of the eigendecomposition's.
+// SYM selects the tiled form (FP32 mode, whose W is rounded to FP32); FP64
+// mode forms every product in full (W within 2e-13).
+// The iteration stops once
 // the predicted residual after the step, 3/4 ||a_k Z_k Y_k - I||_F^2, is
 // <= tol.  On return Z is in Zc (this wave's column block) and in Zb (LDS);
 // A's area (Yb) has been overwritten.  Every wave takes the same decisions
 // (the residual is summed over the workgroup).
+template <bool SYM>
 __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, double lmin, double tol,
                                        int max_it, ColBlock &Zc, int q, int lane) {
   const int col = 16 * q + (lane & 15), k4 = lane >> 4;
@@ -693,7 +748,10 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
       Tc[I][r] = 0.5 * ((dg ? 3.0 : 0.0) - (al / s) * Yc[I][r]);
       Zc[I][r] = sa * Tc[I][r];
     }
-  mm_colblock(Yb, Tc, Yc, lane);
+  if (SYM)
+    mm_colblock_sym(Yb, Tc, Yc, q, lane);
+  else
+    mm_colblock(Yb, Tc, Yc, lane);
 #pragma unroll
   for (int I = 0; I < 4; ++I) Yc[I] *= sa / s;
   l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
@@ -701,9 +759,17 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
   bool conv = false, finite = true;
   for (;;) {
     __syncthreads();  // every read of Yb and Zb of the last step is done
-    if (!conv) store_colblock(Yb, Yc, q, lane);
-    store_colblock(Zb, Zc, q, lane);
-    __syncthreads();
+    if (SYM) {
+      if (!conv) store_colblock_sym(Yb, Yc, q, lane);
+      store_colblock_sym(Zb, Zc, q, lane);
+      __syncthreads();
+      if (!conv) load_colblock(Yb, Yc, q, lane);
+      load_colblock(Zb, Zc, q, lane);
+    } else {
+      if (!conv) store_colblock(Yb, Yc, q, lane);
+      store_colblock(Zb, Zc, q, lane);
+      __syncthreads();
+    }
     if (conv || !finite || it >= max_it) break;
     al = 3.0 / (1.0 + sqrt(l) + l);
     sa = sqrt(al);
@@ -727,8 +793,13 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
     finite = isfinite(d2);
     conv = finite && 0.75 * d2 <= tol;
     ColBlock Zn;
-    if (!conv) mm_colblock(Yb, Tc, Yc, lane);  // Y T (the last step needs only Z)
-    mm_colblock(Zb, Zc, Zn, lane);             // T Z
+    if (SYM) {
+      if (!conv) mm_colblock_sym(Yb, Tc, Yc, q, lane);  // Y T (the last step needs only Z)
+      mm_colblock_sym(Zb, Zc, Zn, q, lane);             // T Z
+    } else {
+      if (!conv) mm_colblock(Yb, Tc, Yc, lane);
+      mm_colblock(Zb, Zc, Zn, lane);
+    }
 #pragma unroll
     for (int I = 0; I < 4; ++I) {
       Yc[I] *= sa;
@@ -1227,7 +1298,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       double *Yb = (double *)(smem + A.off_u);  // A~, then the iteration's two matrices
       double *Zb = Yb + 64 * kLaStride;
       ColBlock Zc;
-      st = ns_isqrt(Yb, Zb, sm, c, A.jtol * 0.01, A.max_sweeps, Zc, q, lane);
+      st = ns_isqrt<sizeof(T) == 4>(Yb, Zb, sm, c, A.jtol * 0.01, A.max_sweeps, Zc, q, lane);
       if (q == 0) {
         sm[S_COL + lane] = dot64(Zb + lane * kLaStride, sm + S_VEC);
         wave_sync();
