@@ -640,42 +640,54 @@ __device__ inline void store_colblock(double *M, const ColBlock &B, int q, int l
 
 __device__ inline double sum4(const double *v) { return (v[0] + v[1]) + (v[2] + v[3]); }
 
-// Products of symmetric iterates by tiles: wave q computes the tiles (I, q) of
-// its column block for I = q and I in {1, 2}, {2, 3}, {3}, {0} (q = 0..3), and
-// stores each with its mirror (q, I); the ten tiles and their mirrors cover
-// the 4 x 4 tiles once, 3, 3, 2, 2 to a wave.
-// C = M B on this wave's tiles of its column block (the others are left as
-// they were); the tile choice is uniform across the wave.
-__device__ inline void mm_colblock_sym(const double *M, const ColBlock &B, ColBlock &C, int q, int lane) {
-  const int c16 = lane & 15, k4 = lane >> 4;
-  const int mask = (0x9CE7 >> (4 * q)) & 15;
-  bool on[4];
-#pragma unroll
-  for (int I = 0; I < 4; ++I) {
-    on[I] = (mask >> I) & 1;
-    if (on[I]) C[I] = Mfma<double>::zero();
-  }
-#pragma unroll
-  for (int kk = 0; kk < 16; ++kk) {
-    const double b = B[kk >> 2][kk & 3];
-#pragma unroll
-    for (int I = 0; I < 4; ++I)
-      if (on[I]) C[I] = Mfma<double>::mac(M[(16 * I + c16) * kLaStride + 4 * kk + k4], b, C[I]);
+// Products of symmetric iterates by tiles: wave q forms the tiles (I, q) of
+// its column block for I = q and I in {1, 2}, {2, 3}, {3}, {0} (q = 0..3),
+// and stores each with its mirror (q, I); the ten tiles and their mirrors
+// cover the 4 x 4 tiles once.  Every wave forms three tiles (waves 2 and 3
+// one more that is not stored), so the products run without branches.
+struct SymTiles {
+  int I[3];   // tile rows
+  int n;      // tiles stored
+};
+__device__ inline SymTiles sym_tiles(int q) {
+  switch (q) {
+    case 0: return SymTiles{{0, 1, 2}, 3};
+    case 1: return SymTiles{{1, 2, 3}, 3};
+    case 2: return SymTiles{{2, 3, 0}, 2};
+    default: return SymTiles{{3, 0, 1}, 2};
   }
 }
 
-// Store this wave's tiles of its column block and their mirrors.
-__device__ inline void store_colblock_sym(double *M, const ColBlock &B, int q, int lane) {
-  const int c = 16 * q + (lane & 15), k4 = lane >> 4;
-  const int mask = (0x9CE7 >> (4 * q)) & 15;
+// C[t] = rows I[t] of M times the column block B (three 16 x 16 tiles).
+__device__ inline void mm_tiles3(const double *M, const ColBlock &B, const SymTiles &st, f64x4 C[3], int lane) {
+  const int c16 = lane & 15, k4 = lane >> 4;
+  const double *r0 = M + (16 * st.I[0] + c16) * kLaStride + k4;
+  const double *r1 = M + (16 * st.I[1] + c16) * kLaStride + k4;
+  const double *r2 = M + (16 * st.I[2] + c16) * kLaStride + k4;
 #pragma unroll
-  for (int I = 0; I < 4; ++I) {
-    if (!((mask >> I) & 1)) continue;
+  for (int t = 0; t < 3; ++t) C[t] = Mfma<double>::zero();
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const double b = B[kk >> 2][kk & 3];
+    C[0] = Mfma<double>::mac(r0[4 * kk], b, C[0]);
+    C[1] = Mfma<double>::mac(r1[4 * kk], b, C[1]);
+    C[2] = Mfma<double>::mac(r2[4 * kk], b, C[2]);
+  }
+}
+
+// Store the stored tiles of C (scaled by sc) and their mirrors.
+__device__ inline void store_tiles3(double *M, const f64x4 C[3], const SymTiles &st, double sc, int q, int lane) {
+  const int c = 16 * q + (lane & 15), k4 = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (t >= st.n) break;
+    const int I = st.I[t];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * I + k4 + 4 * r;
-      M[row * kLaStride + c] = B[I][r];
-      if (I != q) M[c * kLaStride + row] = B[I][r];
+      const double v = sc * C[t][r];
+      M[row * kLaStride + c] = v;
+      if (I != q) M[c * kLaStride + row] = v;
     }
   }
 }
@@ -748,20 +760,27 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
       Tc[I][r] = 0.5 * ((dg ? 3.0 : 0.0) - (al / s) * Yc[I][r]);
       Zc[I][r] = sa * Tc[I][r];
     }
-  if (SYM)
-    mm_colblock_sym(Yb, Tc, Yc, q, lane);
-  else
+  f64x4 Yt[3], Zt[3];        // tiled form: this wave's tiles of the new Y and Z
+  const SymTiles st = sym_tiles(q);
+  double ysc = sa / s, zsc = 1.0;  // their scales, applied when stored
+  if constexpr (SYM) {
+    mm_tiles3(Yb, Tc, st, Yt, lane);
+  } else {
     mm_colblock(Yb, Tc, Yc, lane);
 #pragma unroll
-  for (int I = 0; I < 4; ++I) Yc[I] *= sa / s;
+    for (int I = 0; I < 4; ++I) Yc[I] *= sa / s;
+  }
   l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
   int it = 1;
   bool conv = false, finite = true;
   for (;;) {
     __syncthreads();  // every read of Yb and Zb of the last step is done
-    if (SYM) {
-      if (!conv) store_colblock_sym(Yb, Yc, q, lane);
-      store_colblock_sym(Zb, Zc, q, lane);
+    if constexpr (SYM) {
+      if (!conv) store_tiles3(Yb, Yt, st, ysc, q, lane);
+      if (it == 1)
+        store_colblock(Zb, Zc, q, lane);  // Z_1 = sqrt(a) T_0, formed in full
+      else
+        store_tiles3(Zb, Zt, st, zsc, q, lane);
       __syncthreads();
       if (!conv) load_colblock(Yb, Yc, q, lane);
       load_colblock(Zb, Zc, q, lane);
@@ -792,18 +811,19 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
     const double d2 = sum4(sm + S_RES);
     finite = isfinite(d2);
     conv = finite && 0.75 * d2 <= tol;
-    ColBlock Zn;
-    if (SYM) {
-      if (!conv) mm_colblock_sym(Yb, Tc, Yc, q, lane);  // Y T (the last step needs only Z)
-      mm_colblock_sym(Zb, Zc, Zn, q, lane);             // T Z
+    if constexpr (SYM) {
+      if (!conv) mm_tiles3(Yb, Tc, st, Yt, lane);  // Y T (the last step needs only Z)
+      mm_tiles3(Zb, Zc, st, Zt, lane);             // T Z
+      ysc = zsc = sa;
     } else {
+      ColBlock Zn;
       if (!conv) mm_colblock(Yb, Tc, Yc, lane);
       mm_colblock(Zb, Zc, Zn, lane);
-    }
 #pragma unroll
-    for (int I = 0; I < 4; ++I) {
-      Yc[I] *= sa;
-      Zc[I] = Zn[I] * sa;
+      for (int I = 0; I < 4; ++I) {
+        Yc[I] *= sa;
+        Zc[I] = Zn[I] * sa;
+      }
     }
     l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
     ++it;
