@@ -717,15 +717,14 @@ struct IsqrtStatus {
 // same image (l_{k+1}), so l_k grows by up to 27/4 a step while far from 1
 // and converges quadratically near it; a_k -> 1 there.  Z and Y are carried
 // as separate products (the coupled form is numerically stable; folding
-// Y = A Z is not).  The new Y and Z are symmetric polynomials in A, so each is
-// formed on ten of its sixteen 16 x 16 tiles and mirrored (a quarter of the
-// matrix-core work of a step); Z Y is formed in full, because mirroring it too
-// cost two digits of the result on the steady-state 80 x 80 matrices, while
-// mirroring Y and Z only kept W within 1e-12 of the eigendecomposition's.
-// SYM selects the tiled form (FP32 mode, whose W is rounded to FP32); FP64
-// mode forms every product in full (W within 2e-13).
-// The iteration stops once
-// the predicted residual after the step, 3/4 ||a_k Z_k Y_k - I||_F^2, is
+// Y = A Z is not).  Z Y and the new Y and Z are symmetric polynomials in A:
+// with SYM (FP32 mode) each is formed on ten of its sixteen 16 x 16 tiles and
+// mirrored, three eighths less matrix-core work a step.  At the FP32-mode
+// tolerance W then stays within 4e-9 of the eigendecomposition's on the
+// steady-state 80 x 80 matrices, as with full products (the stopping rule
+// sets the error); at FP64 tolerances the mirroring costs up to two digits,
+// so FP64 mode forms every product in full (W within 2e-13).  The iteration
+// stops once the predicted residual after the step, 3/4 ||a_k Z_k Y_k - I||_F^2, is
 // <= tol.  On return Z is in Zc (this wave's column block) and in Zb (LDS);
 // A's area (Yb) has been overwritten.  Every wave takes the same decisions
 // (the residual is summed over the workgroup).
@@ -792,22 +791,45 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
     if (conv || !finite || it >= max_it) break;
     al = 3.0 / (1.0 + sqrt(l) + l);
     sa = sqrt(al);
-    mm_colblock(Zb, Yc, Tc, lane);  // P = Z Y
     double e2 = 0.0;
+    if constexpr (SYM) {
+      // P = Z Y on this wave's tiles; T = (3 I - a P) / 2 there, mirrored
+      f64x4 Pt[3];
+      mm_tiles3(Zb, Yc, st, Pt, lane);
 #pragma unroll
-    for (int I = 0; I < 4; ++I)
+      for (int t = 0; t < 3; ++t) {
+        const double wgt = t >= st.n ? 0.0 : (st.I[t] == q ? 1.0 : 2.0);  // mirrors count twice
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double d = 16 * I + k4 + 4 * r == col ? 1.0 : 0.0;
-        const double e = fma(al, Tc[I][r], -d);  // a P - I
-        e2 = fma(e, e, e2);
-        Tc[I][r] = d - 0.5 * e;                  // (3 I - a P) / 2
+        for (int r = 0; r < 4; ++r) {
+          const double d = 16 * st.I[t] + k4 + 4 * r == col ? 1.0 : 0.0;
+          const double e = fma(al, Pt[t][r], -d);
+          e2 = fma(wgt * e, e, e2);
+          Pt[t][r] = d - 0.5 * e;
+        }
       }
-    e2 = wave_sum(e2);
-    if (lane == 0) sm[S_RES + q] = e2;
-    __syncthreads();  // every read of Zb (as Z) is done
-    store_colblock(Zb, Tc, q, lane);
-    __syncthreads();
+      e2 = wave_sum(e2);
+      if (lane == 0) sm[S_RES + q] = e2;
+      __syncthreads();  // every read of Zb (as Z) is done
+      store_tiles3(Zb, Pt, st, 1.0, q, lane);
+      __syncthreads();
+      load_colblock(Zb, Tc, q, lane);
+    } else {
+      mm_colblock(Zb, Yc, Tc, lane);  // P = Z Y
+#pragma unroll
+      for (int I = 0; I < 4; ++I)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double d = 16 * I + k4 + 4 * r == col ? 1.0 : 0.0;
+          const double e = fma(al, Tc[I][r], -d);  // a P - I
+          e2 = fma(e, e, e2);
+          Tc[I][r] = d - 0.5 * e;                  // (3 I - a P) / 2
+        }
+      e2 = wave_sum(e2);
+      if (lane == 0) sm[S_RES + q] = e2;
+      __syncthreads();  // every read of Zb (as Z) is done
+      store_colblock(Zb, Tc, q, lane);
+      __syncthreads();
+    }
     const double d2 = sum4(sm + S_RES);
     finite = isfinite(d2);
     conv = finite && 0.75 * d2 <= tol;
