@@ -1095,7 +1095,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   h->off[2] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * 8);
   h->off[3] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * 8);
   h->off[4] = (int32_t)o; o = align16(o + 2 * (size_t)h->max_obs_sub * T);
-  h->off[5] = (int32_t)o; o = align16(o + 128 * 4 + 64 * 8);  // patch nodes, their (i, j), u_{k-2}
+  h->off[5] = (int32_t)o; o = align16(o + 192 * 4 + 64 * 8);  // patch nodes, their (i, j), corners, u_{k-2}
   h->off[6] = (int32_t)o; o = align16(o + letkf_analysis_scratch_doubles() * 8);
   h->off[7] = (int32_t)o;
   h->off[8] = (int32_t)o;
@@ -1113,7 +1113,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     h->fwd_off[2] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * 8);
     h->fwd_off[3] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * 8);
     h->fwd_off[4] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * T);
-    h->fwd_off[5] = (int32_t)f; f = align16(f + 128 * 4 + 64 * 8);
+    h->fwd_off[5] = (int32_t)f; f = align16(f + 192 * 4 + 64 * 8);
     // (the Jacobi transform uses the whole scratch, the Newton-Schulz ones its head)
     const size_t scratch = h->transform == LETKF_TRANSFORM_EVD ? letkf_analysis_scratch_doubles()
                                                                : letkf_analysis_fwd_scratch_doubles();

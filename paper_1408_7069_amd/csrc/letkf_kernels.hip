@@ -170,6 +170,10 @@ __device__ inline double rsq_nr(double x, int steps) {
 // ------------------------------------------------------------ LDS scratch
 // Small FP64 scratch (offsets in doubles).  The forward analysis uses the
 // first kFwdScratch; the Jacobi paths (adjoint, batched eigensolver) all.
+// the patch-node area (ints): patch nodes [0, 64), their packed (i, j)
+// [64, 128), the corner words of the observation subapertures [128, 192),
+// then u_{k-2} at the patch nodes (64 elements of the state type)
+constexpr int kPnCw = 128, kPnU = 192;
 constexpr int S_VEC = 0;       // 64: b = Yt^T sqrt(g) d (residual / z of the solves)
 constexpr int S_WV = 64;       // 64: w
 constexpr int S_XAM = 128;     // 64: analysis mean of the owned rows
@@ -1069,6 +1073,86 @@ struct CoreStatus {
   int sweeps;  // Jacobi sweeps begun
 };
 
+// The bank noise of stage 1, member by member (lane = patch row): wave q
+// loads V[r][k] for its members k = q, q + 4, ... (bank_load, issued with the
+// rows' loads) and adds vs V to xs[r][k] once the rows are in LDS (bank_add).
+// One member's values lie in a small window of one screen, a few cache lines
+// per load, where a row of all members touches a line per member.  Member
+// k's draw is read from lane k.
+template <typename T>
+__device__ __forceinline__ void bank_load(const AnaArgs<T> &A, const InstDesc &in, const int *pn,
+                                          const BankDraw &bd, T val[16], int np, int q, int lane) {
+  const int m = in.m, rc = lane < np ? lane : 0;
+  const int ij = pn[64 + rc], ri = ij & 0xFFFF, rj = ij >> 16;
+  const int side = in.bank_side, mask = side - 1;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int k = q + 4 * t, kc = k < m ? k : 0;
+    const int64_t base = ((int64_t)__builtin_amdgcn_readlane((int)(bd.base >> 32), kc) << 32) |
+                         (uint32_t)__builtin_amdgcn_readlane((int)bd.base, kc);
+    const int oy = __builtin_amdgcn_readlane(bd.oy, kc), ox = __builtin_amdgcn_readlane(bd.ox, kc);
+    const int orient = __builtin_amdgcn_readlane(bd.orient, kc);
+    int u = (orient & 1) ? rj : ri;
+    int v = (orient & 1) ? ri : rj;
+    if (orient & 2) u = -u;
+    if (orient & 4) v = -v;
+    val[t] = (T)A.bank[base + (int64_t)((oy + u) & mask) * side + ((ox + v) & mask)];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void bank_add(const InstDesc &in, const T val[16], T vs, T *xs, int np, int q,
+                                         int lane) {
+  const int m = in.m;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int k = q + 4 * t;
+    if (k < m && lane < np) xs[lane * kXsStride + k] = fma_t(vs, val[t], xs[lane * kXsStride + k]);
+  }
+}
+
+// Stage 1's patch rows of X_b = a X_a + V (+ a2 X_a(k-1)): xs[r][member] for
+// this wave's rows r = q, q + 4, ... (up to 16).  Rows and members are
+// clamped to valid ones so that every load is issued unconditionally, back
+// to back; the values of clamped rows are not stored, those of members past
+// m are stored as zero.  With BANK the noise is loaded by bank_load along
+// with the rows and added by bank_add once the rows are in LDS.
+template <typename T, bool FUSED, bool BANK, bool PREV>
+__device__ __forceinline__ void stage_rows(const AnaArgs<T> &A, const InstDesc &in, const int *pn,
+                                           const BankDraw &bd, T a, T a2, T vs, T *xs, int np, int q,
+                                           int lane) {
+  const int m = in.m, ln = lane < m ? lane : 0;
+  T bv[16];
+  if constexpr (BANK) bank_load<T>(A, in, pn, bd, bv, np, q, lane);  // in flight with the rows
+  for (int r0 = q; r0 < np; r0 += 16 * kWaves) {
+    T xv[16], pv[16], nv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int r = r0 + u * kWaves, rc = r < np ? r : 0;
+      const int64_t e = in.x_off + (int64_t)pn[rc] * m + ln;
+      xv[u] = A.x_in[e];
+      if constexpr (PREV) pv[u] = A.x_prev[e];
+      if constexpr (FUSED && !BANK) nv[u] = A.v_in[e];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int r = r0 + u * kWaves;
+      if (r >= np) continue;
+      T v = xv[u];
+      if constexpr (FUSED) {
+        T noise = BANK ? (T)0 : vs * nv[u];
+        if constexpr (PREV) noise = fma_t(a2, pv[u], noise);  // the AR(2) term joins the noise
+        v = fma_t(a, xv[u], noise);
+      }
+      xs[r * kXsStride + lane] = lane < m ? v : (T)0;
+    }
+  }
+  if constexpr (BANK) {
+    __syncthreads();
+    bank_add<T>(in, bv, vs, xs, np, q, lane);
+  }
+}
+
 // Stages 1-3: on return A~ = c I + Yt^T Yt (FP64, both triangles) at the start
 // of the U area, b = Yt^T sqrt(g) d in sm[S_VEC]; returns whether an
 // observation was not finite.  CL (covariance localisation): stages 1-2 only,
@@ -1095,7 +1179,7 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
   // patch node of row `lane` and its grid coordinates (pn[64 + r]: i | j << 16)
   const bool use_bank = FUSED && A.noise_bank;
   // closed loop: the command u_{k-2} at the patch nodes (uc, after pn)
-  T *uc = (T *)(pn + 128);
+  T *uc = (T *)(pn + kPnU);
   const bool use_u = in.model == 1 && A.u_prev2;
   if (q == 0) {
     const int g = lane < np ? A.patch_node[it.patch_off + lane] : 0;
@@ -1104,40 +1188,23 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
     uc[lane] = use_u && lane < np ? A.u_prev2[in.node_off + g] : (T)0;
   }
   BankDraw bd{};
-  if (use_bank && lane < m) bd = bank_draw(in, frame, lane);
+  if (use_bank) bd = bank_draw(in, frame, lane < m ? lane : 0);  // lanes past m: member 0's (not stored)
   __syncthreads();
   const T a = (T)in.a;
   const bool use_prev = FUSED && A.x_prev && in.a2 != 0.0;
   const T a2 = (T)in.a2;
   const T vs = (T)in.vscale;
-  // four rows a pass, their loads issued together
-  for (int r0 = q; r0 < np; r0 += 4 * kWaves) {
-    T xv[4], nv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = r0 + u * kWaves;
-      xv[u] = (T)0;
-      nv[u] = (T)0;
-      if (r < np && lane < m) {
-        const int64_t e = in.x_off + (int64_t)pn[r] * m + lane;
-        xv[u] = A.x_in[e];
-        if (use_prev) nv[u] = a2 * A.x_prev[e];  // the AR(2) term joins the noise
-        if (FUSED) {
-          if (use_bank) {
-            const int ij = pn[64 + r];
-            nv[u] = fma_t(vs, (T)bank_value(A.bank, bd, ij & 0xFFFF, ij >> 16), nv[u]);
-          } else {
-            nv[u] = fma_t(vs, A.v_in[e], nv[u]);
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = r0 + u * kWaves;
-      if (r < np) xs[r * kXsStride + lane] = FUSED ? fma_t(a, xv[u], nv[u]) : xv[u];
-    }
-  }
+  // every row of the wave in one pass (up to 16), its loads issued back to
+  // back (the choices of noise source and history are made outside the loop:
+  // a load behind a branch is waited for before the next is issued)
+  if (!FUSED)
+    stage_rows<T, false, false, false>(A, in, pn, bd, a, a2, vs, xs, np, q, lane);
+  else if (use_bank)
+    use_prev ? stage_rows<T, true, true, true>(A, in, pn, bd, a, a2, vs, xs, np, q, lane)
+             : stage_rows<T, true, true, false>(A, in, pn, bd, a, a2, vs, xs, np, q, lane);
+  else
+    use_prev ? stage_rows<T, true, false, true>(A, in, pn, bd, a, a2, vs, xs, np, q, lane)
+             : stage_rows<T, true, false, false>(A, in, pn, bd, a, a2, vs, xs, np, q, lane);
   __syncthreads();
   if (tid < np) {
     T s = (T)0;
@@ -1150,6 +1217,7 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
   int bad = 0;
   if (tid < nobs) {
     const uint32_t cw = A.obs_corner[it.obs_off + tid];
+    ((uint32_t *)pn)[kPnCw + tid] = cw;  // kept for the slope operand below
     const int k = A.obs_sub[it.obs_off + tid];
     const int ca = cw & 255, cb = (cw >> 8) & 255, cc = (cw >> 16) & 255, cd = cw >> 24;
     const T ybx = (T)0.5 * ((xm[cb] - xm[ca]) + (xm[cd] - xm[cc]));
@@ -1175,8 +1243,9 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
   bad = __syncthreads_or(bad);
   if constexpr (CL) return bad != 0;
   T *ys = (T *)(smem + A.off_ys);  // [p4][kYsStride], K-major MFMA operand
+#pragma unroll 3
   for (int o = q; o < nobs; o += kWaves) {
-    const uint32_t cw = A.obs_corner[it.obs_off + o];
+    const uint32_t cw = ((const uint32_t *)pn)[kPnCw + o];
     const int ca = cw & 255, cb = (cw >> 8) & 255, cc = (cw >> 16) & 255, cd = cw >> 24;
     const T pa = xs[ca * kXsStride + lane], pb = xs[cb * kXsStride + lane];
     const T pc = xs[cc * kXsStride + lane], pd = xs[cd * kXsStride + lane];
@@ -1187,15 +1256,17 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
   }
   for (int o = p + q; o < p4; o += kWaves) ys[o * kYsStride + lane] = (T)0;
   __syncthreads();
-  if (q == 0) {  // b = Y^T sqrt(g) d, member = lane (p4 - p rows of ys are zero)
+  {  // b = Y^T sqrt(g) d, member = lane (p4 - p rows of ys are zero): wave q
+     // sums the row quads 4 q, 4 q + 16, ... into sm[S_VEC + 64 q] (free
+     // until the transform), wave 0 adds the four after the Gram's barrier
     double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
-    for (int s = 0; s < p4; s += 4) {
+    for (int s = 4 * q; s < p4; s += 16) {
       b0 = fma((double)ys[s * kYsStride + lane], s < p ? dd[s] : 0.0, b0);
       b1 = fma((double)ys[(s + 1) * kYsStride + lane], s + 1 < p ? dd[s + 1] : 0.0, b1);
       b2 = fma((double)ys[(s + 2) * kYsStride + lane], s + 2 < p ? dd[s + 2] : 0.0, b2);
       b3 = fma((double)ys[(s + 3) * kYsStride + lane], s + 3 < p ? dd[s + 3] : 0.0, b3);
     }
-    sm[S_VEC + lane] = (b0 + b1) + (b2 + b3);
+    sm[S_VEC + 64 * q + lane] = (b0 + b1) + (b2 + b3);
   }
 
   // ---- 3. Gram on the matrix cores ----
@@ -1211,6 +1282,9 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
     syrk_store_f64<T>(acc, La, c, q, lane);
   }
   __syncthreads();
+  // b's quarters summed (read first after the transform's next barrier)
+  if (q == 0) sm[S_VEC + lane] = (sm[S_VEC + lane] + sm[S_VEC + 64 + lane]) +
+                                 (sm[S_VEC + 128 + lane] + sm[S_VEC + 192 + lane]);
   return bad != 0;
 }
 
@@ -1374,7 +1448,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     } else {
       // the piston fit reads this mean; in the closed loop it is the residual
       // x_a - N u_{k-2} that the slopes y_k see
-      const T uo = (in.model == 1 && A.u_prev2) ? ((const T *)(pn + 128))[tid] : (T)0;
+      const T uo = (in.model == 1 && A.u_prev2) ? ((const T *)(pn + kPnU))[tid] : (T)0;
       if (A.x_mean) A.x_mean[in.node_off + pn[tid]] = (keep_forecast ? xm[tid] : (T)s) - uo;
     }
   }
@@ -1523,10 +1597,10 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
     }
     if (tid == 0) dg[k] = sqrt(dkk);
     const double inv = 1.0 / dkk;
-    const int n = p - k - 1;
-    for (int e = tid; e < n * n; e += kThreads) {
-      const int r = e / n, i = k + 1 + r, j = k + 1 + (e - r * n);
-      if (j <= i) S[i * ldp + j] -= S[i * ldp + k] * S[j * ldp + k] * inv;
+    // trailing triangle on a 16 x 16 grid of threads
+    for (int i = k + 1 + (tid >> 4); i < p; i += 16) {
+      const double sik = S[i * ldp + k] * inv;
+      for (int j = k + 1 + (tid & 15); j <= i; j += 16) S[i * ldp + j] -= sik * S[j * ldp + k];
     }
     __syncthreads();
   }
@@ -1567,7 +1641,42 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   }
   __syncthreads();
 
-  // ---- 8. owned rows: x_a = x_b + K dd, X'_a = sqrt(rho) (X' - K Dt X'_P / 2) ----
+  // ---- 8. M = K Dt (owned rows x patch), from each patch node's corner
+  // roles (at most four subapertures; found in subaperture order) ----
+  int *adj = (int *)dg;  // [64][4] (subaperture | role << 8), after the pivots
+  if (tid < np) {
+    int cnt = 0;
+    for (int o = 0; o < nobs && cnt < 4; ++o) {
+      const uint32_t w = cw[o];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if ((int)((w >> (8 * t)) & 255) == tid && cnt < 4) adj[tid * 4 + cnt++] = o | (t << 8);
+    }
+    for (; cnt < 4; ++cnt) adj[tid * 4 + cnt] = -1;
+  }
+  __syncthreads();
+  double *Mk = S;  // [own row][64]
+  if (!bad)
+    for (int e = tid; e < nown * 64; e += kThreads) {
+      const int i = e >> 6, n = e & 63;
+      double v = 0.0;
+      if (n < np) {
+        const double *Ki = R + i * ldp;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int a = adj[n * 4 + u];
+          if (a < 0) break;
+          const int o = a & 255, t = a >> 8;
+          const double cx = (t & 1) ? 0.5 : -0.5, cy = (t & 2) ? 0.5 : -0.5;  // roles a, b, c, d
+          v = fma(Ki[o] * sg[o], cx, v);
+          v = fma(Ki[nobs + o] * sg[nobs + o], cy, v);
+        }
+      }
+      Mk[i * 64 + n] = v;
+    }
+  __syncthreads();
+
+  // ---- 9. owned rows: x_a = x_b + K dd, X'_a = sqrt(rho) (X' - M X'_P / 2) ----
   if (tid == 0) A.flags[item] = bad ? 1 : 0;
   const double srho = sqrt(in.rho);
   for (int i = q; i < nown; i += kWaves) {
@@ -1581,23 +1690,15 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
         v = (double)xs[i * kXsStride + lane];
       } else {
         double corr = 0.0;
-        for (int s = 0; s < p; ++s) {
-          const uint32_t w = cw[s < nobs ? s : s - nobs];
-          const int ca = w & 255, cb = (w >> 8) & 255, cc = (w >> 16) & 255, cd = w >> 24;
-          const double pa = (double)xs[ca * kXsStride + lane] - (double)xm[ca];
-          const double pb = (double)xs[cb * kXsStride + lane] - (double)xm[cb];
-          const double pc = (double)xs[cc * kXsStride + lane] - (double)xm[cc];
-          const double pd = (double)xs[cd * kXsStride + lane] - (double)xm[cd];
-          const double yv = 0.5 * sg[s] * (s < nobs ? (pb - pa) + (pd - pc) : (pc - pa) + (pd - pb));
-          corr = fma(Ki[s], yv, corr);
-        }
+        for (int n = 0; n < np; ++n)
+          corr = fma(Mk[i * 64 + n], (double)xs[n * kXsStride + lane] - (double)xm[n], corr);
         v = xa + srho * (((double)xs[i * kXsStride + lane] - (double)xm[i]) - 0.5 * corr);
       }
       A.x_out[in.x_off + (int64_t)pn[i] * m + lane] = (T)v;
     }
     if (lane == 0 && A.x_mean) {
       // the piston fit reads this mean (in the closed loop: x_a - N u_{k-2})
-      const T uo = (in.model == 1 && A.u_prev2) ? ((const T *)(pn + 128))[i] : (T)0;
+      const T uo = (in.model == 1 && A.u_prev2) ? ((const T *)(pn + kPnU))[i] : (T)0;
       A.x_mean[in.node_off + pn[i]] = (T)xa - uo;
     }
   }
