@@ -1136,16 +1136,18 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     h->lds = align16(ub + uf);
     if (h->transform == kAnalysisCl) {
       // covariance localisation: every patch row (read again by the update),
-      // then S (first X'_P^T and P_loc), B and the solve's columns; no slope
-      // operand
+      // then one FP64 area for X'_P^T, P_loc and S (packed lower triangle) in
+      // turn, and B with a spare row (its owned rows and one more become the
+      // solve's columns); no slope operand.  FP32 at 80x80: under 80 KiB, two
+      // workgroups per CU
       const size_t pmax = 2 * (size_t)h->max_obs_sub, ld = pmax + 1;
       const size_t rows = align16(f + (size_t)h->max_patch * kXsStride * T);
-      const size_t sreg = std::max({(size_t)64 * 65 * 8, (size_t)64 * kYsStride * 8, pmax * ld * 8});
+      const size_t sreg = std::max({(size_t)64 * 65 * 8, (size_t)64 * kClXtStride * 8, pmax * (pmax + 1) / 2 * 8});
       h->fwd_off[7] = (int32_t)rows;
       h->fwd_off[8] = (int32_t)rows;
       h->cl_off[0] = (int32_t)align16(rows + sreg);
-      h->cl_off[1] = (int32_t)align16(h->cl_off[0] + (size_t)h->max_patch * ld * 8);
-      h->lds = align16(h->cl_off[1] + ((size_t)h->max_own + 1) * ld * 8);
+      h->cl_off[1] = h->cl_off[0];
+      h->lds = align16(h->cl_off[0] + ((size_t)h->max_patch + 1) * ld * 8);
     }
   }
   {  // the adjoint kernel: a larger U area (FP64 64 x 64), Q, a second matrix, scratch

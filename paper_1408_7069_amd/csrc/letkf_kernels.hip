@@ -1492,9 +1492,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 //   [K^T | v] = S^{-1} [B_own^T | dd],
 //   x_a = x_b + K dd,  X'_a = sqrt(rho) (X'_own - K Dt X'_P / 2)
 // (the deterministic EnKF update of the anomalies), written to the owned
-// rows.  LDS: the patch rows, then S (first X'_P^T and P_loc, both FP64), B
-// and the solve's columns (offsets from the host).
+// rows.  LDS: the patch rows, then one area for X'_P^T, P_loc and S in turn
+// (FP64; S as a packed lower triangle), and B, whose owned rows become the
+// solve's columns (offsets from the host).
 constexpr int kEigCl = kAnalysisCl;
+
+// index of (i, j), j <= i, in a packed lower triangle
+__device__ inline int tri(int i, int j) { return ((i * (i + 1)) >> 1) + j; }
 
 template <typename T, bool FUSED>
 __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
@@ -1514,10 +1518,9 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   uint32_t *cw = (uint32_t *)(smem + A.off_yb);  // corner words of the region's subapertures
   int *pn = (int *)(smem + A.off_pn);
   double *dg = (double *)(smem + A.off_s);       // pivots sqrt(S_kk) of the Cholesky
-  double *xt = (double *)(smem + A.off_u);       // X'_P^T in FP64, [member][kYsStride]
-  double *Pm = (double *)(smem + A.off_u);       // P_loc [64][kLaStride], then S [p][ldp]
-  double *Bm = (double *)(smem + A.off_clb);     // [patch row][ldp]
-  double *R = (double *)(smem + A.off_clr);      // column c at R + c ldp
+  double *xt = (double *)(smem + A.off_u);       // X'_P^T in FP64, [member][kClXtStride]
+  double *Pm = (double *)(smem + A.off_u);       // P_loc [64][kLaStride], then S (packed lower)
+  double *Bm = (double *)(smem + A.off_clb);     // [patch row][ldp]; rows 0..n_own the solve's columns
   const uint32_t frame = (FUSED && A.noise_bank) ? *A.frame : 0u;
   bool bad = stage_gram<T, FUSED, false, true>(A, it, in, frame, smem);
 
@@ -1529,7 +1532,7 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   }
   for (int e = tid; e < 64 * 64; e += kThreads) {
     const int k = e >> 6, r = e & 63;
-    xt[k * kYsStride + r] = (r < np && k < m) ? (double)xs[r * kXsStride + k] - (double)xm[r] : 0.0;
+    xt[k * kClXtStride + r] = (r < np && k < m) ? (double)xs[r * kXsStride + k] - (double)xm[r] : 0.0;
   }
   __syncthreads();
   {
@@ -1537,7 +1540,7 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
     // cancels most of its size (the phase is smooth), so an FP32 product's
     // rounding would come out amplified
     typename Mfma<double>::V acc[3];
-    syrk_share<double>(xt, kYsStride, 16, acc, q, lane);
+    syrk_share<double>(xt, kClXtStride, 16, acc, q, lane);
     __syncthreads();
     syrk_store_f64<double>(acc, Pm, 0.0, q, lane);
   }
@@ -1566,7 +1569,7 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   }
   __syncthreads();
 
-  // ---- 5. S = Dt B + I (lower triangle, over P_loc) and the right-hand sides ----
+  // ---- 5. S = Dt B + I, lower triangle packed, over P_loc ----
   double *S = Pm;
   for (int e = tid; e < p * p; e += kThreads) {
     const int s = e / p, t = e - s * p;
@@ -1575,71 +1578,69 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
     const int ca = w & 255, cb = (w >> 8) & 255, cc = (w >> 16) & 255, cd = w >> 24;
     const double ba = Bm[ca * ldp + t], bb = Bm[cb * ldp + t], bc = Bm[cc * ldp + t], bd = Bm[cd * ldp + t];
     const double v = s < nobs ? (bb - ba) + (bd - bc) : (bc - ba) + (bd - bb);
-    S[s * ldp + t] = 0.5 * sg[s] * v + (s == t ? 1.0 : 0.0);
-  }
-  for (int e = tid; e < (nown + 1) * p; e += kThreads) {
-    const int c = e / p, s = e - c * p;
-    R[c * ldp + s] = c < nown ? Bm[c * ldp + s] : dd[s];
+    S[tri(s, t)] = 0.5 * sg[s] * v + (s == t ? 1.0 : 0.0);
   }
   __syncthreads();
+  // the solve's columns: B's owned rows (patch rows 0..n_own - 1) as they
+  // stand, and dd in row n_own (a stencil row that S no longer needs, or the
+  // spare row after the patch)
+  for (int s = tid; s < p; s += kThreads) Bm[nown * ldp + s] = dd[s];
 
   // ---- 6. Cholesky S = L L^T in place, one barrier a column: step k
   // updates the trailing triangle from the unscaled column k and scales
   // column k - 1 by its pivot (no other access to that column in step k) ----
   int fail = 0;
   for (int k = 0; k < p; ++k) {
-    const double dkk = S[k * ldp + k];
+    const double dkk = S[tri(k, k)];
     fail |= !(dkk > 0.0);
     if (k > 0) {
       const double piv = dg[k - 1];
-      for (int i = k + tid; i < p; i += kThreads) S[i * ldp + k - 1] /= piv;
-      if (tid == 0) S[(k - 1) * ldp + k - 1] = piv;
+      for (int i = k + tid; i < p; i += kThreads) S[tri(i, k - 1)] /= piv;
+      if (tid == 0) S[tri(k - 1, k - 1)] = piv;
     }
     if (tid == 0) dg[k] = sqrt(dkk);
     const double inv = 1.0 / dkk;
     // trailing triangle on a 16 x 16 grid of threads
     for (int i = k + 1 + (tid >> 4); i < p; i += 16) {
-      const double sik = S[i * ldp + k] * inv;
-      for (int j = k + 1 + (tid & 15); j <= i; j += 16) S[i * ldp + j] -= sik * S[j * ldp + k];
+      const double sik = S[tri(i, k)] * inv;
+      double *Si = S + tri(i, 0);
+      for (int j = k + 1 + (tid & 15); j <= i; j += 16) Si[j] -= sik * S[tri(j, k)];
     }
     __syncthreads();
   }
-  if (tid == 0 && p > 0) S[(p - 1) * ldp + p - 1] = dg[p - 1];
+  if (tid == 0 && p > 0) S[tri(p - 1, p - 1)] = dg[p - 1];
   bad = bad || fail;
   __syncthreads();
 
-  // ---- 7. [K^T | v] = S^{-1} [B_own^T | dd]: eight lanes a column ----
+  // ---- 7. [K^T | v] = S^{-1} [B_own^T | dd] in place: eight lanes a column ----
   const int nc = nown + 1, sub = tid & 7;
   for (int c0 = 0; c0 < nc; c0 += kThreads / 8) {
     const int c = c0 + (tid >> 3);
     const bool act = c < nc && !bad;
-    double *col = R + (c < nc ? c : 0) * ldp;
+    double *col = Bm + (c < nc ? c : 0) * ldp;
     for (int i = 0; i < p; ++i) {
       double part = 0.0;
-      if (act)
-        for (int k = sub; k < i; k += 8) part = fma(S[i * ldp + k], col[k], part);
+      if (act) {
+        const double *Li = S + tri(i, 0);
+        for (int k = sub; k < i; k += 8) part = fma(Li[k], col[k], part);
+      }
       part += __shfl_xor(part, 1, 8);
       part += __shfl_xor(part, 2, 8);
       part += __shfl_xor(part, 4, 8);
-      if (act) {
-        const double yi = (col[i] - part) / S[i * ldp + i];
-        col[i] = yi;  // the same value from all eight lanes
-      }
+      if (act) col[i] = (col[i] - part) / S[tri(i, i)];  // the same value from all eight lanes
     }
     for (int i = p - 1; i >= 0; --i) {
       double part = 0.0;
       if (act)
-        for (int k = i + 1 + sub; k < p; k += 8) part = fma(S[k * ldp + i], col[k], part);
+        for (int k = i + 1 + sub; k < p; k += 8) part = fma(S[tri(k, i)], col[k], part);
       part += __shfl_xor(part, 1, 8);
       part += __shfl_xor(part, 2, 8);
       part += __shfl_xor(part, 4, 8);
-      if (act) {
-        const double xi = (col[i] - part) / S[i * ldp + i];
-        col[i] = xi;
-      }
+      if (act) col[i] = (col[i] - part) / S[tri(i, i)];
     }
   }
   __syncthreads();
+  const double *R = Bm;
 
   // ---- 8. M = K Dt (owned rows x patch), from each patch node's corner
   // roles (at most four subapertures; found in subaperture order) ----

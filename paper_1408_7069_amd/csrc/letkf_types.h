@@ -11,6 +11,7 @@ constexpr int kMaxPatch = 64;     // owned nodes + every corner of the region
 constexpr int kYsStride = 80;     // row stride of K-major MFMA operands (no bank conflicts)
 constexpr int kXsStride = 65;     // row stride of node rows (lane = row reads)
 constexpr int kAnalysisCl = 3;    // analysis-kernel selector of covariance localisation (after the transforms)
+constexpr int kClXtStride = 66;   // covariance localisation: row stride of the FP64 transposed patch
 
 // One adaptive-optics instance.
 struct InstDesc {
