@@ -542,19 +542,40 @@ template <typename T>
 __device__ inline void syrk_share(const T *M, int ld, int ksteps, typename Mfma<T>::V acc[3], int q,
                                   int lane) {
   const int c16 = lane & 15, k4 = lane >> 4;
-  int I[3], J[3];
+  int oi[3], oj[3];
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
     acc[u] = Mfma<T>::zero();
-    tile_of(q + 4 * u < 10 ? q + 4 * u : 0, I[u], J[u]);
+    int I, J;
+    // waves 2 and 3 hold two tiles: their third repeats the first and is
+    // not stored, so the loop carries no branch
+    tile_of(q + 4 * u < 10 ? q + 4 * u : q, I, J);
+    oi[u] = 16 * I + c16;
+    oj[u] = 16 * J + c16;
   }
-  const int nt = q < 2 ? 3 : 2;
-#pragma unroll 3
-  for (int kk = 0; kk < ksteps; ++kk) {
-    const T *row = M + (4 * kk + k4) * ld;
+  const T *row0 = M + k4 * ld;
+  int kk = 0;
+  // four K steps a pass: every operand load issued before the products
+  for (; kk + 4 <= ksteps; kk += 4) {
+    T a[4][3], b[4][3];
 #pragma unroll
-    for (int u = 0; u < 3; ++u)
-      if (u < nt) acc[u] = Mfma<T>::mac(row[16 * I[u] + c16], row[16 * J[u] + c16], acc[u]);
+    for (int t = 0; t < 4; ++t) {
+      const T *row = row0 + 4 * (kk + t) * ld;
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        a[t][u] = row[oi[u]];
+        b[t][u] = row[oj[u]];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < 3; ++u) acc[u] = Mfma<T>::mac(a[t][u], b[t][u], acc[u]);
+  }
+  for (; kk < ksteps; ++kk) {
+    const T *row = row0 + 4 * kk * ld;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) acc[u] = Mfma<T>::mac(row[oi[u]], row[oj[u]], acc[u]);
   }
 }
 
