@@ -1119,8 +1119,9 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
                                                                : letkf_analysis_fwd_scratch_doubles();
     h->fwd_off[6] = (int32_t)f; f = align16(f + scratch * 8);
     h->fwd_off[0] = (int32_t)f;
-    // (blend mode updates every patch row: all of them outlive stage 2)
-    const size_t ub = align16(f + (size_t)(h->any_blend ? h->max_patch : h->max_own) * kXsStride * T);
+    // (blend mode updates every patch row: the rows past the owned ones are
+    // staged again after the transform)
+    const size_t ub = align16(f + (size_t)h->max_own * kXsStride * T);
     const size_t rows_end = f + (size_t)h->max_patch * kXsStride * T;  // end of the patch rows
     const size_t ys_bytes = p4 * kYsStride * T;
     const size_t spill = rows_end > ub ? align16(rows_end - ub) : 0;

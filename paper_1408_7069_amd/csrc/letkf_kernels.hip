@@ -1123,12 +1123,12 @@ __device__ __forceinline__ void bank_load(const AnaArgs<T> &A, const InstDesc &i
 
 template <typename T>
 __device__ __forceinline__ void bank_add(const InstDesc &in, const T val[16], T vs, T *xs, int np, int q,
-                                         int lane) {
+                                         int lane, int r_lo) {
   const int m = in.m;
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int k = q + 4 * t;
-    if (k < m && lane < np) xs[lane * kXsStride + k] = fma_t(vs, val[t], xs[lane * kXsStride + k]);
+    if (k < m && lane >= r_lo && lane < np) xs[lane * kXsStride + k] = fma_t(vs, val[t], xs[lane * kXsStride + k]);
   }
 }
 
@@ -1141,11 +1141,11 @@ __device__ __forceinline__ void bank_add(const InstDesc &in, const T val[16], T 
 template <typename T, bool FUSED, bool BANK, bool PREV>
 __device__ __forceinline__ void stage_rows(const AnaArgs<T> &A, const InstDesc &in, const int *pn,
                                            const BankDraw &bd, T a, T a2, T vs, T *xs, int np, int q,
-                                           int lane) {
+                                           int lane, int r_lo) {
   const int m = in.m, ln = lane < m ? lane : 0;
   T bv[16];
   if constexpr (BANK) bank_load<T>(A, in, pn, bd, bv, np, q, lane);  // in flight with the rows
-  for (int r0 = q; r0 < np; r0 += 16 * kWaves) {
+  for (int r0 = r_lo + q; r0 < np; r0 += 16 * kWaves) {
     T xv[16], pv[16], nv[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -1170,8 +1170,26 @@ __device__ __forceinline__ void stage_rows(const AnaArgs<T> &A, const InstDesc &
   }
   if constexpr (BANK) {
     __syncthreads();
-    bank_add<T>(in, bv, vs, xs, np, q, lane);
+    bank_add<T>(in, bv, vs, xs, np, q, lane, r_lo);
   }
+}
+
+// Stage 1's patch rows r_lo .. n_patch - 1 of X_b (every choice of noise
+// source and history); the caller brackets it with barriers.
+template <typename T, bool FUSED>
+__device__ __forceinline__ void stage_patch_rows(const AnaArgs<T> &A, const InstDesc &in, const int *pn,
+                                                 const BankDraw &bd, T *xs, int np, int q, int lane, int r_lo) {
+  const bool use_bank = FUSED && A.noise_bank;
+  const bool use_prev = FUSED && A.x_prev && in.a2 != 0.0;
+  const T a = (T)in.a, a2 = (T)in.a2, vs = (T)in.vscale;
+  if (!FUSED)
+    stage_rows<T, false, false, false>(A, in, pn, bd, a, a2, vs, xs, np, q, lane, r_lo);
+  else if (use_bank)
+    use_prev ? stage_rows<T, true, true, true>(A, in, pn, bd, a, a2, vs, xs, np, q, lane, r_lo)
+             : stage_rows<T, true, true, false>(A, in, pn, bd, a, a2, vs, xs, np, q, lane, r_lo);
+  else
+    use_prev ? stage_rows<T, true, false, true>(A, in, pn, bd, a, a2, vs, xs, np, q, lane, r_lo)
+             : stage_rows<T, true, false, false>(A, in, pn, bd, a, a2, vs, xs, np, q, lane, r_lo);
 }
 
 // Stages 1-3: on return A~ = c I + Yt^T Yt (FP64, both triangles) at the start
@@ -1211,21 +1229,10 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
   BankDraw bd{};
   if (use_bank) bd = bank_draw(in, frame, lane < m ? lane : 0);  // lanes past m: member 0's (not stored)
   __syncthreads();
-  const T a = (T)in.a;
-  const bool use_prev = FUSED && A.x_prev && in.a2 != 0.0;
-  const T a2 = (T)in.a2;
-  const T vs = (T)in.vscale;
   // every row of the wave in one pass (up to 16), its loads issued back to
   // back (the choices of noise source and history are made outside the loop:
   // a load behind a branch is waited for before the next is issued)
-  if (!FUSED)
-    stage_rows<T, false, false, false>(A, in, pn, bd, a, a2, vs, xs, np, q, lane);
-  else if (use_bank)
-    use_prev ? stage_rows<T, true, true, true>(A, in, pn, bd, a, a2, vs, xs, np, q, lane)
-             : stage_rows<T, true, true, false>(A, in, pn, bd, a, a2, vs, xs, np, q, lane);
-  else
-    use_prev ? stage_rows<T, true, false, true>(A, in, pn, bd, a, a2, vs, xs, np, q, lane)
-             : stage_rows<T, true, false, false>(A, in, pn, bd, a, a2, vs, xs, np, q, lane);
+  stage_patch_rows<T, FUSED>(A, in, pn, bd, xs, np, q, lane, 0);
   __syncthreads();
   if (tid < np) {
     T s = (T)0;
@@ -1458,6 +1465,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   const bool keep_forecast = bad || !conv;
   const bool blend = in.blend != 0 && A.stage;
   const int nupd = blend ? np : nown;
+  if (blend && np > nown) {
+    // the rows past the owned ones shared LDS with the transform: stage them
+    // again (the same arithmetic on the same inputs, so the same values)
+    __syncthreads();
+    BankDraw bd{};
+    if (FUSED && A.noise_bank) bd = bank_draw(in, frame, lane < m ? lane : 0);
+    stage_patch_rows<T, FUSED>(A, in, pn, bd, xs, np, q, lane, nown);
+    __syncthreads();
+  }
   if (tid == 0) A.flags[item] = flag;
   if (tid < nupd) {
     const double mu = (double)xm[tid];
