@@ -205,3 +205,34 @@ def test_coherent_energy_loss_against_the_kf(fp64):
     e = M.coherent_energy(res[b:])
     loss = M.loss(ref["e_coh_kf"], e)
     assert -1.0 < loss < 3.0, (e, ref["e_coh_kf"], loss)
+
+
+def test_autotune_keeps_the_command_and_ar2_histories():
+    # tuning runs frames on the handle; afterwards the next frame equals the
+    # next frame of an identical handle that was not tuned (ensemble, AR(2)
+    # history, command history and frame counter restored)
+    bb = B()
+    case = Case(12, 0.28, 4, 1, 32, seed=49, piston=True)
+    n = case.G.n_nodes
+    X0 = _t((case.rng.standard_normal((n, 32)) * 0.5).astype(np.float32), np.float32)
+    u1 = _t(case.rng.standard_normal(n), np.float32)
+    u2 = _t(case.rng.standard_normal(n), np.float32)
+    ys = [_t(case.slopes(case.truth()), np.float32) for _ in range(2)]
+    Vs = [_t(case.noise(), np.float32) for _ in range(2)]
+    for kw in ({"model": bb.MODEL_CLOSED_LOOP}, {"ar_coeff": 1.24, "ar2_coeff": -0.26}):
+        out = []
+        for tune in (False, True):
+            f = bb.Letkf([case.spec(bb, **kw)])
+            f.set_ensemble(X0)
+            if "model" in kw:
+                f.set_command(u1, u2)
+            f.step(ys[0], V=Vs[0])        # a history that differs from the ensemble
+            if tune:
+                f.autotune(ys[1], V=Vs[1], frames=3)
+            f.step(ys[1], V=Vs[1])
+            torch.cuda.synchronize()
+            out.append((f.get_ensemble().cpu().numpy(), f.get_frame(),
+                        f.get_command().cpu().numpy() if "model" in kw else None))
+        assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1], kw
+        if "model" in kw:
+            assert np.array_equal(out[0][2], out[1][2])
