@@ -471,11 +471,11 @@ def main():
     achieved = total / (kernel_ms * 1e-3) / 1e12
     # what the matrix cores executed for the inverse square root: per domain
     # one product at the first step, three at each later one but the last
-    # (two); in FP32 mode each product of symmetric iterates runs on twelve of
-    # its sixteen 16 x 16 tiles (three a wave, ten of them kept)
+    # (two); in FP32 mode each product of symmetric iterates runs on ten of
+    # its sixteen 16 x 16 tiles (three to waves 0 and 1, two to waves 2 and 3)
     steps = (f.status()[1] >> 8) & 255
     products = np.maximum(3 * steps.astype(np.int64) - 3, 1)
-    ns_flops = float(products.sum()) * 2.0 * 64 ** 3 * 12 / 16
+    ns_flops = float(products.sum()) * 2.0 * 64 ** 3 * 10 / 16
     ns_tflops = ns_flops / (kernel_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(),

@@ -141,12 +141,6 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-__device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
 // LDS traffic of one wavefront only: in-order within the wave, so a compiler
 // barrier suffices between the writes and the reads of other lanes.
 __device__ inline void wave_sync() {
@@ -155,12 +149,7 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// 1/x and 1/sqrt(x) from the hardware estimates refined by Newton steps.
-__device__ inline double rcp_nr(double x, int steps) {
-  double y = __builtin_amdgcn_rcp(x);
-  for (int i = 0; i < steps; ++i) y = fma(y, fma(-x, y, 1.0), y);
-  return y;
-}
+// 1/sqrt(x) from the hardware estimate refined by Newton steps.
 __device__ inline double rsq_nr(double x, int steps) {
   double y = __builtin_amdgcn_rsq(x);
   for (int i = 0; i < steps; ++i) y = y * fma(-0.5 * x * y, y, 1.5);
@@ -193,7 +182,6 @@ constexpr int kXchBytes = kWaves * 8 * 64 * 8;   // one block of every wave in f
 // block 7 - q in Y[0..7] (ascending columns), lane = row.
 __device__ inline int pos_x(int q, int j) { return 8 * q + j; }
 __device__ inline int pos_y(int q, int j) { return 56 - 8 * q + j; }
-__device__ inline int block_owner(int b) { return b < 4 ? b : 7 - b; }
 
 // Lane permutation within 16-lane rows (every source lane valid).
 template <int CTRL> __device__ inline double dpp_f64(double v) {
@@ -668,8 +656,7 @@ __device__ inline double sum4(const double *v) { return (v[0] + v[1]) + (v[2] + 
 // Products of symmetric iterates by tiles: wave q forms the tiles (I, q) of
 // its column block for I = q and I in {1, 2}, {2, 3}, {3}, {0} (q = 0..3),
 // and stores each with its mirror (q, I); the ten tiles and their mirrors
-// cover the 4 x 4 tiles once.  Every wave forms three tiles (waves 2 and 3
-// one more that is not stored), so the products run without branches.
+// cover the 4 x 4 tiles once, three to waves 0 and 1, two to waves 2 and 3.
 struct SymTiles {
   int I[3];   // tile rows
   int n;      // tiles stored
@@ -683,21 +670,30 @@ __device__ inline SymTiles sym_tiles(int q) {
   }
 }
 
-// C[t] = rows I[t] of M times the column block B (three 16 x 16 tiles).
-__device__ inline void mm_tiles3(const double *M, const ColBlock &B, const SymTiles &st, f64x4 C[3], int lane) {
+// C[t] = rows I[t] of M times the column block B (NT 16 x 16 tiles).
+template <int NT>
+__device__ inline void mm_tiles_n(const double *M, const ColBlock &B, const SymTiles &st, f64x4 C[3], int lane) {
   const int c16 = lane & 15, k4 = lane >> 4;
-  const double *r0 = M + (16 * st.I[0] + c16) * kLaStride + k4;
-  const double *r1 = M + (16 * st.I[1] + c16) * kLaStride + k4;
-  const double *r2 = M + (16 * st.I[2] + c16) * kLaStride + k4;
+  const double *r[NT];
 #pragma unroll
-  for (int t = 0; t < 3; ++t) C[t] = Mfma<double>::zero();
+  for (int t = 0; t < 3; ++t) C[t] = Mfma<double>::zero();  // an unformed tile reads as zero
+#pragma unroll
+  for (int t = 0; t < NT; ++t) r[t] = M + (16 * st.I[t] + c16) * kLaStride + k4;
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
     const double b = B[kk >> 2][kk & 3];
-    C[0] = Mfma<double>::mac(r0[4 * kk], b, C[0]);
-    C[1] = Mfma<double>::mac(r1[4 * kk], b, C[1]);
-    C[2] = Mfma<double>::mac(r2[4 * kk], b, C[2]);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) C[t] = Mfma<double>::mac(r[t][4 * kk], b, C[t]);
   }
+}
+
+// This wave's tiles (three for waves 0 and 1, two for waves 2 and 3; one
+// branch outside the product).
+__device__ inline void mm_tiles3(const double *M, const ColBlock &B, const SymTiles &st, f64x4 C[3], int lane) {
+  if (st.n == 3)
+    mm_tiles_n<3>(M, B, st, C, lane);
+  else
+    mm_tiles_n<2>(M, B, st, C, lane);
 }
 
 // Store the stored tiles of C (scaled by sc) and their mirrors.
