@@ -164,6 +164,8 @@ template <typename T> struct PistonArgsHost {
   double *rhs;
   double *pi;
   T *x;
+  const int32_t *term_off;
+  const PistonTerm *terms;
 };
 
 // Mirror of AdjArgs<T>.
@@ -264,6 +266,8 @@ struct letkf_handle {
   int32_t *d_owner_item = nullptr;
   int64_t *d_minv_off = nullptr;
   double *d_minv = nullptr, *d_prhs = nullptr, *d_pi = nullptr;
+  int32_t *d_pterm_off = nullptr;  // piston right-hand-side terms per item
+  PistonTerm *d_pterms = nullptr;
   void *d_xmean = nullptr;
   std::vector<unsigned char> gpargs[2][2];  // graph: rhs args, solve/apply args
   hipGraphNode_t gpnode[2][3] = {};
@@ -600,7 +604,7 @@ void free_handle(letkf_handle *h) {
                   h->d_xbbar, h->d_dbar, h->d_theta, h->d_owner_item, h->d_minv_off, h->d_minv,
                   h->d_prhs, h->d_pi, h->d_xmean, h->d_u1, h->d_u2, h->d_xprev,
                   h->d_refit, h->d_rpart, h->d_stage, h->d_smean, h->d_boff, h->d_bent,
-                  h->d_bitem, h->d_bw};
+                  h->d_bitem, h->d_bw, h->d_pterm_off, h->d_pterms};
   for (void *p : ptrs)
     if (p) hipFree(p);
   for (auto &e : h->tev) {
@@ -678,6 +682,8 @@ PistonArgsHost<T> make_piston_args(letkf_handle *h, const void *y, void *x) {
   P.rhs = h->d_prhs;
   P.pi = h->d_pi;
   P.x = (T *)x;
+  P.term_off = h->d_pterm_off;
+  P.terms = h->d_pterms;
   return P;
 }
 
@@ -1221,6 +1227,50 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     minv.insert(minv.end(), mi.begin(), mi.end());
   }
 
+  // piston right-hand sides: per item, the subapertures its domain shares
+  // with others and the summed coefficients of its own corners
+  std::vector<int32_t> pterm_off(1, 0);
+  std::vector<PistonTerm> pterms;
+  for (int i = 0; i < n_instances; ++i) {
+    const InstGeom &g = h->geom[i];
+    const int nd = (int)g.owned.size();
+    std::vector<std::vector<PistonTerm>> per((size_t)nd);
+    if (h->desc[i].piston) {
+      for (int qs = 0; qs < g.n_subaps; ++qs) {
+        const int32_t *cn = &g.subap_nodes[4 * qs];
+        int dl[4], n = 0;
+        float cx[4], cy[4];
+        for (int t = 0; t < 4; ++t) {
+          const int d = g.owner[cn[t]];
+          int k = 0;
+          while (k < n && dl[k] != d) ++k;
+          if (k == n) {
+            dl[n] = d;
+            cx[n] = cy[n] = 0.0f;
+            ++n;
+          }
+          cx[k] += (t & 1) ? 0.5f : -0.5f;
+          cy[k] += (t & 2) ? 0.5f : -0.5f;
+        }
+        if (n < 2) continue;  // inside one domain: the coefficients sum to zero
+        for (int k = 0; k < n; ++k) {
+          if (cx[k] == 0.0f && cy[k] == 0.0f) continue;
+          PistonTerm pt;
+          for (int t = 0; t < 4; ++t) pt.c[t] = (int32_t)(h->desc[i].node_off + cn[t]);
+          pt.yx = (int32_t)(h->desc[i].y_off + qs);
+          pt.yy = (int32_t)(h->desc[i].y_off + g.n_subaps + qs);
+          pt.cx = cx[k];
+          pt.cy = cy[k];
+          per[(size_t)dl[k]].push_back(pt);
+        }
+      }
+    }
+    for (int d = 0; d < nd; ++d) {
+      pterms.insert(pterms.end(), per[(size_t)d].begin(), per[(size_t)d].end());
+      pterm_off.push_back((int32_t)pterms.size());
+    }
+  }
+
   // blend-mode gather: per node of a blend instance, its patch entries (item
   // order), their items and normalised tent weights
   std::vector<int32_t> boff(1, 0), bent, bitem;
@@ -1298,6 +1348,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
       (rc = to_device(&h->d_minv, minv)) ||
       (rc = to_device(&h->d_prhs, std::vector<double>(std::max<size_t>(h->items.size(), 1), 0.0))) ||
       (rc = to_device(&h->d_pi, std::vector<double>(std::max<size_t>(h->items.size(), 1), 0.0))) ||
+      (rc = to_device(&h->d_pterm_off, pterm_off)) || (rc = to_device(&h->d_pterms, pterms)) ||
       (h->any_blend && ((rc = to_device(&h->d_boff, boff)) || (rc = to_device(&h->d_bent, bent)) ||
                         (rc = to_device(&h->d_bitem, bitem)) || (rc = to_device(&h->d_bw, bw)) ||
                         (rc = to_device(&h->d_smean, std::vector<double>(patch.size(), 0.0)))))) {

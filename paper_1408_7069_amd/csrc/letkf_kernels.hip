@@ -2214,30 +2214,28 @@ template <typename T> struct PistonArgs {
   double *rhs;                 // per item (forward: P^T D^T residual; adjoint: P^T Z_bar 1)
   double *pi;                  // per item (forward: pistons; adjoint: M^+ of the sums)
   T *x;                        // ensemble updated in place
+  const int32_t *term_off;     // per item: its right-hand-side terms (+ total)
+  const PistonTerm *terms;
 };
 
-// rhs[item] = sum over the owned nodes of (D^T (y - D x_mean))_node.
+// rhs[item] = sum over the owned nodes of (D^T (y - D x_mean))_node: only
+// the subapertures the domain shares with others contribute (the corners'
+// coefficients of a subaperture inside one domain sum to zero), each with
+// the summed coefficients of the domain's own corners, from a table built at
+// create (two dependent loads: the terms, then the means and slopes).
 template <typename T> __global__ void k_piston_rhs(const PistonArgs<T> P) {
   const int item = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (item >= P.n_items) return;
-  const DomItem it = P.items[item];
-  const InstDesc in = P.inst[it.inst];
+  const int t0 = P.term_off[item], t1 = P.term_off[item + 1];
   double v = 0.0;
-  if (in.piston && lane < it.n_own) {
-    const int64_t gn = in.node_off + P.patch_node[it.patch_off + lane];
-    const int64_t sub0 = in.y_off / 2;
-    for (int role = 0; role < 4; ++role) {
-      const int s = P.node_adj[4 * gn + role];
-      if (s < 0) continue;
-      const int32_t *c = P.subap_nodes + 4 * (int64_t)s;
-      const double xa = (double)P.x_mean[in.node_off + c[0]], xb = (double)P.x_mean[in.node_off + c[1]];
-      const double xc = (double)P.x_mean[in.node_off + c[2]], xd = (double)P.x_mean[in.node_off + c[3]];
-      const int64_t k = s - sub0;
-      const double ex = (double)P.y[in.y_off + k] - 0.5 * ((xb - xa) + (xd - xc));
-      const double ey = (double)P.y[in.y_off + in.n_subaps + k] - 0.5 * ((xc - xa) + (xd - xb));
-      v += ((role & 1) ? 0.5 : -0.5) * ex + ((role & 2) ? 0.5 : -0.5) * ey;
-    }
+  for (int t = t0 + lane; t < t1; t += 64) {
+    const PistonTerm pt = P.terms[t];
+    const double xa = (double)P.x_mean[pt.c[0]], xb = (double)P.x_mean[pt.c[1]];
+    const double xc = (double)P.x_mean[pt.c[2]], xd = (double)P.x_mean[pt.c[3]];
+    const double ex = (double)P.y[pt.yx] - 0.5 * ((xb - xa) + (xd - xc));
+    const double ey = (double)P.y[pt.yy] - 0.5 * ((xc - xa) + (xd - xb));
+    v = fma((double)pt.cx, ex, fma((double)pt.cy, ey, v));
   }
   v = wave_sum(v);
   if (lane == 0) P.rhs[item] = v;
@@ -2285,21 +2283,34 @@ template <typename T> __global__ void k_piston_finish(const PistonArgs<T> P, uin
   const DomItem it = P.items[item];
   const InstDesc in = P.inst[it.inst];
   if (!in.piston) return;
-  if (q == 0) {
-    const int b0 = P.dom_base[it.inst], nd = P.dom_base[it.inst + 1] - b0;
-    const double *row = P.minv + P.minv_off[it.inst] + (int64_t)(item - b0) * nd;
-    double v = 0.0;
-    for (int e = lane; e < nd; e += 64) v = fma(row[e], P.rhs[b0 + e], v);
-    v = wave_sum(v);
-    if (lane == 0) pi_s = v;
-  }
-  __syncthreads();
-  const double pv = pi_s;
-  const int m = in.m;
-  for (int e = tid; e < it.n_own * m; e += kThreads) {
-    const int i = e / m, j = e - i * m;
-    const int64_t x = in.x_off + (int64_t)P.patch_node[it.patch_off + i] * m + j;
-    P.x[x] = (T)((double)P.x[x] + pv);
+  // the owned rows are loaded (eight elements a thread a pass) while wave 0
+  // forms the piston
+  const int m = in.m, ne = it.n_own * m;
+  for (int e0 = 0; e0 < ne; e0 += 8 * kThreads) {
+    T xv[8];
+    int64_t xi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kThreads + tid, ec = e < ne ? e : 0;
+      const int i = ec / m, j = ec - i * m;
+      xi[u] = in.x_off + (int64_t)P.patch_node[it.patch_off + i] * m + j;
+      xv[u] = P.x[xi[u]];
+    }
+    if (e0 == 0) {
+      if (q == 0) {
+        const int b0 = P.dom_base[it.inst], nd = P.dom_base[it.inst + 1] - b0;
+        const double *row = P.minv + P.minv_off[it.inst] + (int64_t)(item - b0) * nd;
+        double v = 0.0;
+        for (int e = lane; e < nd; e += 64) v = fma(row[e], P.rhs[b0 + e], v);
+        v = wave_sum(v);
+        if (lane == 0) pi_s = v;
+      }
+      __syncthreads();
+    }
+    const double pv = pi_s;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (e0 + u * kThreads + tid < ne) P.x[xi[u]] = (T)((double)xv[u] + pv);
   }
 }
 

@@ -41,6 +41,15 @@ struct RefitState {
   int64_t frames;      // frames folded in
 };
 
+// One term of a domain's piston right-hand side: a subaperture two or more
+// domains share, with the summed stencil coefficients (x and y slope) of the
+// domain's own corners.
+struct PistonTerm {
+  int32_t c[4];        // global node index of corners a, b, c, d
+  int32_t yx, yy;      // global slope index of its x and y slope
+  float cx, cy;        // coefficients (multiples of 1/2)
+};
+
 // One (instance, domain) work item.  Patch entries 0..n_own-1 are the owned
 // nodes in ascending order; the rest are the other corners of the region.
 struct DomItem {
