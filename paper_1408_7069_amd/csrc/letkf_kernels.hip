@@ -1492,13 +1492,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   for (int I = 0; I * 16 < nupd; ++I) {
     typename Mfma<T>::V o = Mfma<T>::zero();
     const int ia = 16 * I + c16;
-    const T mu = ia < nupd ? xm[ia] : (T)0;
+    const bool rowok = ia < nupd;
+    const int iac = rowok ? ia : 0;  // loads from a valid row, the value dropped after
+    const T mu = xm[iac];
+    T av[16];
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
+    for (int kk = 0; kk < 16; ++kk) {  // every load before the products
       const int k = 4 * kk + k4;
-      const T av = (ia < nupd && k < m) ? xs[ia * kXsStride + k] - mu : (T)0;
-      o = Mfma<T>::mac(av, wf[kk], o);
+      const T v = xs[iac * kXsStride + k];
+      av[kk] = (rowok && k < m) ? v - mu : (T)0;
     }
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) o = Mfma<T>::mac(av[kk], wf[kk], o);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * I + Mfma<T>::row(lane, r);
