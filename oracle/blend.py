@@ -94,12 +94,14 @@ def gather(parts, weights_list, n_nodes) -> np.ndarray:
     return num / den[:, None]
 
 
-def analysis(geom, doms, Xb, y, r_diag, params: ol.Params) -> np.ndarray:
-    """Local analyses of every patch, aligned and blended."""
+def analysis(geom, doms, Xb, y, r_diag, params: ol.Params, u_prev2=None) -> np.ndarray:
+    """Local analyses of every patch, aligned and blended.  u_prev2 given: the
+    closed loop's observation, y_bar = D x_b - D N u_{k-2} (Sec. 2.2)."""
+    from . import delayed as DL
     Xb = np.asarray(Xb, np.float64)
     xb, Xp = ol.ensemble_stats(Xb)
     Yp = geo.apply_slopes(geom, Xp)
-    d = np.asarray(y, np.float64) - geo.apply_slopes(geom, xb)
+    d = np.asarray(y, np.float64) - DL.predicted_slopes(geom, xb, u_prev2)
     parts, oms = [], []
     for dom in doms:
         Y, dl, g = ol.local_inputs(geom, dom, Yp, d, r_diag, params)
