@@ -145,6 +145,7 @@ template <typename T> struct AnaArgsHost {
   int32_t max_sweeps;
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
   int32_t off_clb, off_clr;
+  int32_t round_items;
 };
 
 // Mirror of PistonArgs<T>.
@@ -219,6 +220,7 @@ struct letkf_handle {
   int32_t off[9] = {0};      // LDS layout of the adjoint's forward stages
   int32_t fwd_off[9] = {0};  // LDS layout of the analysis
   int32_t cl_off[2] = {0, 0};  // covariance localisation: offsets of B and of the solve's columns
+  int32_t round_items = 32;   // work items of one dispatch round per XCD (the CUs of one XCD)
   // device
   InstDesc *d_desc = nullptr;
   DomItem *d_items = nullptr;
@@ -654,6 +656,7 @@ AnaArgsHost<T> make_args(letkf_handle *h, bool fused, const void *V, const void 
   A.stage = h->any_blend ? (T *)h->d_stage : nullptr;
   A.off_clb = h->cl_off[0];
   A.off_clr = h->cl_off[1];
+  A.round_items = h->round_items;
   A.stage_mean = h->d_smean;
   A.flags = h->d_flags;
   A.frame = h->d_frame;
@@ -1317,6 +1320,12 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
       free_handle(h);
       return fail(LETKF_E_INVAL, msg);
     }
+  }
+  {
+    // one dispatch round of workgroups per XCD: its CUs (eight XCDs)
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && n_cu >= 8)
+      h->round_items = n_cu / 8;
   }
   for (int fused = 0; fused < 2; ++fused)
     hipFuncSetAttribute(letkf_analysis_kernel(h->fp64, fused, h->transform),

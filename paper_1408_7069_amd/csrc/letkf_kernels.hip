@@ -654,20 +654,18 @@ __device__ inline void store_colblock(double *M, const ColBlock &B, int q, int l
 __device__ inline double sum4(const double *v) { return (v[0] + v[1]) + (v[2] + v[3]); }
 
 // Products of symmetric iterates by tiles: wave q forms the tiles (I, q) of
-// its column block for I = q and I in {1, 2}, {2, 3}, {3}, {0} (q = 0..3),
-// and stores each with its mirror (q, I); the ten tiles and their mirrors
-// cover the 4 x 4 tiles once, three to waves 0 and 1, two to waves 2 and 3.
+// its column block for I = q, q + 1 (mod 4), and, for the two waves rot and
+// rot + 1, also I = q + 2, storing each with its mirror (q, I).  Any rot gives
+// the ten tiles of the upper triangle once: (q, q + 1) for every q, and the
+// two pairs two apart from the waves rot and rot + 1.  Those two waves form
+// three tiles, the others two; rot moves that extra tile between waves (and
+// so between SIMDs) without changing the count.
 struct SymTiles {
   int I[3];   // tile rows
   int n;      // tiles stored
 };
-__device__ inline SymTiles sym_tiles(int q) {
-  switch (q) {
-    case 0: return SymTiles{{0, 1, 2}, 3};
-    case 1: return SymTiles{{1, 2, 3}, 3};
-    case 2: return SymTiles{{2, 3, 0}, 2};
-    default: return SymTiles{{3, 0, 1}, 2};
-  }
+__device__ inline SymTiles sym_tiles(int q, int rot) {
+  return SymTiles{{q, (q + 1) & 3, (q + 2) & 3}, ((q - rot) & 3) < 2 ? 3 : 2};
 }
 
 // C[t] = rows I[t] of M times the column block B (NT 16 x 16 tiles).
@@ -687,8 +685,7 @@ __device__ inline void mm_tiles_n(const double *M, const ColBlock &B, const SymT
   }
 }
 
-// This wave's tiles (three for waves 0 and 1, two for waves 2 and 3; one
-// branch outside the product).
+// This wave's tiles (three or two; one branch outside the product).
 __device__ inline void mm_tiles3(const double *M, const ColBlock &B, const SymTiles &st, f64x4 C[3], int lane) {
   if (st.n == 3)
     mm_tiles_n<3>(M, B, st, C, lane);
@@ -740,7 +737,11 @@ struct IsqrtStatus {
 // as separate products (the coupled form is numerically stable; folding
 // Y = A Z is not).  Z Y and the new Y and Z are symmetric polynomials in A:
 // with SYM (FP32 mode) each is formed on ten of its sixteen 16 x 16 tiles and
-// mirrored, three eighths less matrix-core work a step.  At the FP32-mode
+// mirrored, three eighths less matrix-core work a step.  Z Y and Y T take the
+// three-tile roles on the waves rot, rot + 1 and T Z on the other two, so the
+// pair Y T, T Z (between the same two barriers) costs every wave five tiles;
+// rot is chosen per work item so that two work items sharing a CU put their
+// three-tile waves of Z Y on different SIMDs.  At the FP32-mode
 // tolerance W then stays within 4e-9 of the eigendecomposition's on the
 // steady-state 80 x 80 matrices, as with full products (the stopping rule
 // sets the error); at FP64 tolerances the mirroring costs up to two digits,
@@ -751,7 +752,7 @@ struct IsqrtStatus {
 // (the residual is summed over the workgroup).
 template <bool SYM>
 __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, double lmin, double tol,
-                                       int max_it, ColBlock &Zc, int q, int lane) {
+                                       int max_it, ColBlock &Zc, int q, int lane, int rot) {
   const int col = 16 * q + (lane & 15), k4 = lane >> 4;
   ColBlock Yc, Tc;
   double ss = 0.0;
@@ -781,7 +782,7 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
       Zc[I][r] = sa * Tc[I][r];
     }
   f64x4 Yt[3], Zt[3];        // tiled form: this wave's tiles of the new Y and Z
-  const SymTiles st = sym_tiles(q);
+  const SymTiles st = sym_tiles(q, rot), stz = sym_tiles(q, rot + 2);
   double ysc = sa / s, zsc = 1.0;  // their scales, applied when stored
   if constexpr (SYM) {
     mm_tiles3(Yb, Tc, st, Yt, lane);
@@ -800,7 +801,7 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
       if (it == 1)
         store_colblock(Zb, Zc, q, lane);  // Z_1 = sqrt(a) T_0, formed in full
       else
-        store_tiles3(Zb, Zt, st, zsc, q, lane);
+        store_tiles3(Zb, Zt, stz, zsc, q, lane);
       __syncthreads();
       if (!conv) load_colblock(Yb, Yc, q, lane);
       load_colblock(Zb, Zc, q, lane);
@@ -856,7 +857,7 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
     conv = finite && 0.75 * d2 <= tol;
     if constexpr (SYM) {
       if (!conv) mm_tiles3(Yb, Tc, st, Yt, lane);  // Y T (the last step needs only Z)
-      mm_tiles3(Zb, Zc, st, Zt, lane);             // T Z
+      mm_tiles3(Zb, Zc, stz, Zt, lane);            // T Z
       ysc = zsc = sa;
     } else {
       ColBlock Zn;
@@ -1070,6 +1071,7 @@ template <typename T> struct AnaArgs {
   int32_t max_sweeps;
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
   int32_t off_clb, off_clr;  // covariance localisation: B and the solve's columns
+  int32_t round_items;        // work items of one dispatch round per XCD (CUs per XCD)
 };
 
 __device__ inline int xcd_item(int b, int grid) {
@@ -1438,7 +1440,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       double *Yb = (double *)(smem + A.off_u);  // A~, then the iteration's two matrices
       double *Zb = Yb + 64 * kLaStride;
       ColBlock Zc;
-      st = ns_isqrt<sizeof(T) == 4>(Yb, Zb, sm, c, A.jtol * 0.01, A.max_sweeps, Zc, q, lane);
+      // Work items are dealt to the XCDs in contiguous runs (xcd_item); the
+      // items past the first round_items of a run start in the second
+      // dispatch round and share a CU with one of the first, whose waves
+      // occupy the SIMDs one place further on: rot = 1 there keeps the
+      // two items' three-tile waves apart.  A function of the item alone, so
+      // every launch form takes the same roundings.
+      const int per = (A.n_items + 7) >> 3;
+      const int rot = ((item % per) / A.round_items) & 1;
+      st = ns_isqrt<sizeof(T) == 4>(Yb, Zb, sm, c, A.jtol * 0.01, A.max_sweeps, Zc, q, lane, rot);
       if (q == 0) {
         sm[S_COL + lane] = dot64(Zb + lane * kLaStride, sm + S_VEC);
         wave_sync();
