@@ -167,6 +167,7 @@ template <typename T> struct PistonArgsHost {
   T *x;
   const int32_t *term_off;
   const PistonTerm *terms;
+  const PistonItem *pitem;
 };
 
 // Mirror of AdjArgs<T>.
@@ -270,6 +271,8 @@ struct letkf_handle {
   double *d_minv = nullptr, *d_prhs = nullptr, *d_pi = nullptr;
   int32_t *d_pterm_off = nullptr;  // piston right-hand-side terms per item
   PistonTerm *d_pterms = nullptr;
+  PistonItem *d_pitem = nullptr;   // per item: what the piston step reads
+  bool pterm_fixed = false;        // terms at a fixed stride of 64 an item
   void *d_xmean = nullptr;
   std::vector<unsigned char> gpargs[2][2];  // graph: rhs args, solve/apply args
   hipGraphNode_t gpnode[2][3] = {};
@@ -606,7 +609,7 @@ void free_handle(letkf_handle *h) {
                   h->d_xbbar, h->d_dbar, h->d_theta, h->d_owner_item, h->d_minv_off, h->d_minv,
                   h->d_prhs, h->d_pi, h->d_xmean, h->d_u1, h->d_u2, h->d_xprev,
                   h->d_refit, h->d_rpart, h->d_stage, h->d_smean, h->d_boff, h->d_bent,
-                  h->d_bitem, h->d_bw, h->d_pterm_off, h->d_pterms};
+                  h->d_bitem, h->d_bw, h->d_pterm_off, h->d_pterms, h->d_pitem};
   for (void *p : ptrs)
     if (p) hipFree(p);
   for (auto &e : h->tev) {
@@ -685,7 +688,8 @@ PistonArgsHost<T> make_piston_args(letkf_handle *h, const void *y, void *x) {
   P.rhs = h->d_prhs;
   P.pi = h->d_pi;
   P.x = (T *)x;
-  P.term_off = h->d_pterm_off;
+  P.term_off = h->pterm_fixed ? nullptr : h->d_pterm_off;
+  P.pitem = h->d_pitem;
   P.terms = h->d_pterms;
   return P;
 }
@@ -1229,6 +1233,20 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     }
     minv.insert(minv.end(), mi.begin(), mi.end());
   }
+  std::vector<PistonItem> pitem(std::max<size_t>(h->items.size(), 1), PistonItem{});
+  for (size_t k = 0; k < h->items.size(); ++k) {
+    const DomItem &it = h->items[k];
+    const InstDesc &ds = h->desc[(size_t)it.inst];
+    PistonItem &pr = pitem[k];
+    pr.b0 = h->dom_base[(size_t)it.inst];
+    pr.nd = (int32_t)h->geom[(size_t)it.inst].owned.size();
+    pr.row = minv_off[(size_t)it.inst] + (int64_t)(k - (size_t)pr.b0) * pr.nd;
+    pr.x_off = ds.x_off;
+    pr.patch_off = it.patch_off;
+    pr.n_own = it.n_own;
+    pr.m = ds.m;
+    pr.piston = ds.piston ? 1 : 0;
+  }
 
   // piston right-hand sides: per item, the subapertures its domain shares
   // with others and the summed coefficients of its own corners
@@ -1272,6 +1290,21 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
       pterms.insert(pterms.end(), per[(size_t)d].begin(), per[(size_t)d].end());
       pterm_off.push_back((int32_t)pterms.size());
     }
+  }
+  // at most 64 terms an item: the same terms at a fixed stride of 64 (one
+  // load fewer before the means), the rest with coefficients 0 at node 0
+  h->pterm_fixed = true;
+  for (size_t k = 0; k + 1 < pterm_off.size(); ++k)
+    if (pterm_off[k + 1] - pterm_off[k] > 64) h->pterm_fixed = false;
+  if (h->pterm_fixed) {
+    PistonTerm none{};
+    for (int t = 0; t < 4; ++t) none.c[t] = 0;
+    none.yx = none.yy = 0;
+    none.cx = none.cy = 0.0f;
+    std::vector<PistonTerm> fixed(std::max<size_t>(h->items.size(), 1) * 64, none);
+    for (size_t k = 0; k + 1 < pterm_off.size(); ++k)
+      for (int t = pterm_off[k]; t < pterm_off[k + 1]; ++t) fixed[k * 64 + (size_t)(t - pterm_off[k])] = pterms[(size_t)t];
+    pterms.swap(fixed);
   }
 
   // blend-mode gather: per node of a blend instance, its patch entries (item
@@ -1358,6 +1391,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
       (rc = to_device(&h->d_prhs, std::vector<double>(std::max<size_t>(h->items.size(), 1), 0.0))) ||
       (rc = to_device(&h->d_pi, std::vector<double>(std::max<size_t>(h->items.size(), 1), 0.0))) ||
       (rc = to_device(&h->d_pterm_off, pterm_off)) || (rc = to_device(&h->d_pterms, pterms)) ||
+      (rc = to_device(&h->d_pitem, pitem)) ||
       (h->any_blend && ((rc = to_device(&h->d_boff, boff)) || (rc = to_device(&h->d_bent, bent)) ||
                         (rc = to_device(&h->d_bitem, bitem)) || (rc = to_device(&h->d_bw, bw)) ||
                         (rc = to_device(&h->d_smean, std::vector<double>(patch.size(), 0.0)))))) {

@@ -2229,28 +2229,41 @@ template <typename T> struct PistonArgs {
   double *rhs;                 // per item (forward: P^T D^T residual; adjoint: P^T Z_bar 1)
   double *pi;                  // per item (forward: pistons; adjoint: M^+ of the sums)
   T *x;                        // ensemble updated in place
-  const int32_t *term_off;     // per item: its right-hand-side terms (+ total)
+  const int32_t *term_off;     // per item: its right-hand-side terms (+ total); NULL: 64 a item
   const PistonTerm *terms;
+  const PistonItem *pitem;     // per item: what the piston step reads
 };
 
 // rhs[item] = sum over the owned nodes of (D^T (y - D x_mean))_node: only
 // the subapertures the domain shares with others contribute (the corners'
 // coefficients of a subaperture inside one domain sum to zero), each with
 // the summed coefficients of the domain's own corners, from a table built at
-// create (two dependent loads: the terms, then the means and slopes).
+// create: at a fixed stride of 64 an item when every item has at most 64
+// (one load before the means and slopes; unused entries have coefficients
+// 0 and node 0), else through per-item offsets.
 template <typename T> __global__ void k_piston_rhs(const PistonArgs<T> P) {
   const int item = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (item >= P.n_items) return;
-  const int t0 = P.term_off[item], t1 = P.term_off[item + 1];
+  int t0, t1, st;
+  if (P.term_off) {
+    t0 = P.term_off[item];
+    t1 = P.term_off[item + 1];
+    st = 64;
+  } else {
+    t0 = 64 * item;
+    t1 = t0 + 64;
+    st = 64;
+  }
   double v = 0.0;
-  for (int t = t0 + lane; t < t1; t += 64) {
+  for (int t = t0 + lane; t < t1; t += st) {
     const PistonTerm pt = P.terms[t];
     const double xa = (double)P.x_mean[pt.c[0]], xb = (double)P.x_mean[pt.c[1]];
     const double xc = (double)P.x_mean[pt.c[2]], xd = (double)P.x_mean[pt.c[3]];
     const double ex = (double)P.y[pt.yx] - 0.5 * ((xb - xa) + (xd - xc));
     const double ey = (double)P.y[pt.yy] - 0.5 * ((xc - xa) + (xd - xb));
-    v = fma((double)pt.cx, ex, fma((double)pt.cy, ey, v));
+    // (an unused entry adds nothing, also where its slopes are not finite)
+    if (pt.cx != 0.0f || pt.cy != 0.0f) v = fma((double)pt.cx, ex, fma((double)pt.cy, ey, v));
   }
   v = wave_sum(v);
   if (lane == 0) P.rhs[item] = v;
@@ -2288,19 +2301,21 @@ template <typename T> __global__ void k_piston_apply(const PistonArgs<T> P) {
 }
 
 // pi of each domain (a row of M^+ times rhs) added to every member of its
-// owned nodes: one workgroup per item.  Item 0 also advances the frame counter
-// of the bank draws when `frame` is given (the last step of the frame).
+// owned nodes: one workgroup per item, the row's products spread over the
+// workgroup (a few loads a thread, all in flight at once) while the owned rows
+// load.  Item 0 also advances the frame counter of the bank draws when
+// `frame` is given (the last step of the frame).
 template <typename T> __global__ void k_piston_finish(const PistonArgs<T> P, uint32_t *frame) {
-  __shared__ double pi_s;
+  __shared__ double pi_w[kWaves];
   const int item = blockIdx.x;
   const int tid = threadIdx.x, q = tid >> 6, lane = tid & 63;
   if (frame && item == 0 && tid == 0) *frame += 1u;
-  const DomItem it = P.items[item];
-  const InstDesc in = P.inst[it.inst];
-  if (!in.piston) return;
-  // the owned rows are loaded (eight elements a thread a pass) while wave 0
-  // forms the piston
-  const int m = in.m, ne = it.n_own * m;
+  const PistonItem pr = P.pitem[item];  // one load before the row and the owned rows
+  if (!pr.piston) return;
+  // the owned rows are loaded (eight elements a thread a pass) while the
+  // workgroup forms the piston
+  const int m = pr.m, ne = pr.n_own * m;
+  double pv = 0.0;
   for (int e0 = 0; e0 < ne; e0 += 8 * kThreads) {
     T xv[8];
     int64_t xi[8];
@@ -2308,21 +2323,18 @@ template <typename T> __global__ void k_piston_finish(const PistonArgs<T> P, uin
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + u * kThreads + tid, ec = e < ne ? e : 0;
       const int i = ec / m, j = ec - i * m;
-      xi[u] = in.x_off + (int64_t)P.patch_node[it.patch_off + i] * m + j;
+      xi[u] = pr.x_off + (int64_t)P.patch_node[pr.patch_off + i] * m + j;
       xv[u] = P.x[xi[u]];
     }
     if (e0 == 0) {
-      if (q == 0) {
-        const int b0 = P.dom_base[it.inst], nd = P.dom_base[it.inst + 1] - b0;
-        const double *row = P.minv + P.minv_off[it.inst] + (int64_t)(item - b0) * nd;
-        double v = 0.0;
-        for (int e = lane; e < nd; e += 64) v = fma(row[e], P.rhs[b0 + e], v);
-        v = wave_sum(v);
-        if (lane == 0) pi_s = v;
-      }
+      const double *row = P.minv + pr.row;
+      double v = 0.0;
+      for (int e = tid; e < pr.nd; e += kThreads) v = fma(row[e], P.rhs[pr.b0 + e], v);
+      v = wave_sum(v);
+      if (lane == 0) pi_w[q] = v;
       __syncthreads();
+      pv = sum4(pi_w);
     }
-    const double pv = pi_s;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (e0 + u * kThreads + tid < ne) P.x[xi[u]] = (T)((double)xv[u] + pv);

@@ -50,6 +50,16 @@ struct PistonTerm {
   float cx, cy;        // coefficients (multiples of 1/2)
 };
 
+// What the piston step of one work item reads, in one record: its row of
+// M^+, where its owned rows are, and its instance's domains.
+struct PistonItem {
+  int64_t row;         // offset of the item's row of M^+ in the M^+ array
+  int64_t x_off;       // the instance's offset into the ensemble
+  int32_t b0, nd;      // the instance's first item and number of domains
+  int32_t patch_off, n_own;
+  int32_t m, piston;   // ensemble size; 0: no piston removal for the instance
+};
+
 // One (instance, domain) work item.  Patch entries 0..n_own-1 are the owned
 // nodes in ascending order; the rest are the other corners of the region.
 struct DomItem {
