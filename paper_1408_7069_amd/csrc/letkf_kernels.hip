@@ -1634,59 +1634,118 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   // spare row after the patch)
   for (int s = tid; s < p; s += kThreads) Bm[nown * ldp + s] = dd[s];
 
-  // ---- 6. Cholesky S = L L^T in place, one barrier a column: step k
-  // updates the trailing triangle from the unscaled column k and scales
-  // column k - 1 by its pivot (no other access to that column in step k) ----
+  // ---- 6. Cholesky S = L L^T in place (packed lower triangle), by panels
+  // of 16 columns: wave 0 factors a panel in registers (rows k0 + lane and
+  // k0 + 64 + lane; the entries of column c2 of the panel at row k0 + c2 come
+  // from lane c2 by readlane), then every wave subtracts the panel's product
+  // from the trailing triangle: two barriers a panel.  dg[k] = 1 / L_kk ----
   int fail = 0;
-  for (int k = 0; k < p; ++k) {
-    const double dkk = S[tri(k, k)];
-    fail |= !(dkk > 0.0);
-    if (k > 0) {
-      const double piv = dg[k - 1];
-      for (int i = k + tid; i < p; i += kThreads) S[tri(i, k - 1)] /= piv;
-      if (tid == 0) S[tri(k - 1, k - 1)] = piv;
+  for (int k0 = 0; k0 < p; k0 += 16) {
+    const int kb = min(16, p - k0), k1 = k0 + kb;
+    if (q == 0) {
+      const int r0 = k0 + lane, r1 = r0 + 64;
+      double L0[16], L1[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        L0[c] = (c < kb && r0 < p && k0 + c <= r0) ? S[tri(r0, k0 + c)] : 0.0;
+        L1[c] = (c < kb && r1 < p) ? S[tri(r1, k0 + c)] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        if (c < kb) {
+          const double d = bcast_lane(L0[c], c);  // the pivot (row k0 + c)
+          fail |= !(d > 0.0);
+          const double ljj = sqrt(d), inv = 1.0 / ljj;
+          L0[c] = lane == c ? ljj : (lane > c ? L0[c] * inv : L0[c]);
+          L1[c] *= inv;
+          if (lane == c) dg[k0 + c] = inv;
+#pragma unroll
+          for (int c2 = c + 1; c2 < 16; ++c2) {
+            const double lc = bcast_lane(L0[c], c2);  // L[k0 + c2][k0 + c]
+            L0[c2] = lane >= c2 ? fma(-L0[c], lc, L0[c2]) : L0[c2];
+            L1[c2] = fma(-L1[c], lc, L1[c2]);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        if (c < kb && r0 < p && k0 + c <= r0) S[tri(r0, k0 + c)] = L0[c];
+        if (c < kb && r1 < p) S[tri(r1, k0 + c)] = L1[c];
+      }
     }
-    if (tid == 0) dg[k] = sqrt(dkk);
-    const double inv = 1.0 / dkk;
-    // trailing triangle on a 16 x 16 grid of threads
-    for (int i = k + 1 + (tid >> 4); i < p; i += 16) {
-      const double sik = S[tri(i, k)] * inv;
-      double *Si = S + tri(i, 0);
-      for (int j = k + 1 + (tid & 15); j <= i; j += 16) Si[j] -= sik * S[tri(j, k)];
+    __syncthreads();
+    // trailing triangle (rows and columns from k1) on a 16 x 16 grid: the
+    // panel is full (kb = 16) wherever a trailing triangle is left
+    for (int a = tid >> 4; a < p - k1; a += 16) {
+      const int i = k1 + a;
+      const double *Li = S + tri(i, k0);
+      double li[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) li[j] = Li[j];
+      for (int b = tid & 15; b <= a; b += 16) {
+        const double *Lc = S + tri(k1 + b, k0);
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; j += 2) {
+          s0 = fma(li[j], Lc[j], s0);
+          s1 = fma(li[j + 1], Lc[j + 1], s1);
+        }
+        S[tri(i, k1 + b)] -= s0 + s1;
+      }
     }
     __syncthreads();
   }
-  if (tid == 0 && p > 0) S[tri(p - 1, p - 1)] = dg[p - 1];
-  bad = bad || fail;
-  __syncthreads();
+  bad = bad || __syncthreads_or(fail);
 
-  // ---- 7. [K^T | v] = S^{-1} [B_own^T | dd] in place: eight lanes a column ----
-  const int nc = nown + 1, sub = tid & 7;
-  for (int c0 = 0; c0 < nc; c0 += kThreads / 8) {
-    const int c = c0 + (tid >> 3);
-    const bool act = c < nc && !bad;
-    double *col = Bm + (c < nc ? c : 0) * ldp;
-    for (int i = 0; i < p; ++i) {
-      double part = 0.0;
-      if (act) {
-        const double *Li = S + tri(i, 0);
-        for (int k = sub; k < i; k += 8) part = fma(Li[k], col[k], part);
+  // ---- 7. [K^T | v] = S^{-1} [B_own^T | dd] in place: wave q takes the
+  // columns q, q + 4, ... (eight at a time), each in registers (rows lane and
+  // 64 + lane); per row i, x_i = v_i / L_ii goes to every lane by readlane and
+  // the column (forward) or row (backward) of L is read once for all of them ----
+  const int nc = nown + 1;
+  if (!bad)
+    for (int cb = q; cb < nc; cb += 4 * 8) {
+      double v0[8], v1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = cb + 4 * u;
+        const double *col = Bm + (c < nc ? c : 0) * ldp;
+        v0[u] = c < nc && lane < p ? col[lane] : 0.0;
+        v1[u] = c < nc && lane + 64 < p ? col[lane + 64] : 0.0;
       }
-      part += __shfl_xor(part, 1, 8);
-      part += __shfl_xor(part, 2, 8);
-      part += __shfl_xor(part, 4, 8);
-      if (act) col[i] = (col[i] - part) / S[tri(i, i)];  // the same value from all eight lanes
+      for (int i = 0; i < p; ++i) {  // L y = b: column i of L below the diagonal
+        const double inv = dg[i];
+        const double l0 = lane > i && lane < p ? S[tri(lane, i)] : 0.0;
+        const double l1 = lane + 64 > i && lane + 64 < p ? S[tri(lane + 64, i)] : 0.0;
+        const int li = i & 63;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double x = bcast_lane(i < 64 ? v0[u] : v1[u], li) * inv;
+          v0[u] = i < 64 && lane == li ? x : fma(-l0, x, v0[u]);
+          v1[u] = i >= 64 && lane == li ? x : fma(-l1, x, v1[u]);
+        }
+      }
+      for (int i = p - 1; i >= 0; --i) {  // L^T x = y: row i of L left of the diagonal
+        const double inv = dg[i];
+        const double l0 = lane < i ? S[tri(i, lane)] : 0.0;
+        const double l1 = lane + 64 < i ? S[tri(i, lane + 64)] : 0.0;
+        const int li = i & 63;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double x = bcast_lane(i < 64 ? v0[u] : v1[u], li) * inv;
+          v0[u] = i < 64 && lane == li ? x : fma(-l0, x, v0[u]);
+          v1[u] = i >= 64 && lane == li ? x : fma(-l1, x, v1[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = cb + 4 * u;
+        if (c < nc) {
+          double *col = Bm + c * ldp;
+          if (lane < p) col[lane] = v0[u];
+          if (lane + 64 < p) col[lane + 64] = v1[u];
+        }
+      }
     }
-    for (int i = p - 1; i >= 0; --i) {
-      double part = 0.0;
-      if (act)
-        for (int k = i + 1 + sub; k < p; k += 8) part = fma(S[tri(k, i)], col[k], part);
-      part += __shfl_xor(part, 1, 8);
-      part += __shfl_xor(part, 2, 8);
-      part += __shfl_xor(part, 4, 8);
-      if (act) col[i] = (col[i] - part) / S[tri(i, i)];
-    }
-  }
   __syncthreads();
   const double *R = Bm;
 
