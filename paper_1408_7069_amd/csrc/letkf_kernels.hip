@@ -1712,29 +1712,53 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
         v0[u] = c < nc && lane < p ? col[lane] : 0.0;
         v1[u] = c < nc && lane + 64 < p ? col[lane + 64] : 0.0;
       }
-      for (int i = 0; i < p; ++i) {  // L y = b: column i of L below the diagonal
+      // (in two halves, rows below 64 in v0 and the rest in v1: where x_i
+      // comes from and which half changes are then known in each)
+      const int nu = min(8, (nc - cb + 3) >> 2);  // this wave's columns in the chunk
+      const int ph = min(p, 64);
+      for (int i = 0; i < ph; ++i) {  // L y = b, rows < 64: column i of L below the diagonal
         const double inv = dg[i];
         const double l0 = lane > i && lane < p ? S[tri(lane, i)] : 0.0;
-        const double l1 = lane + 64 > i && lane + 64 < p ? S[tri(lane + 64, i)] : 0.0;
-        const int li = i & 63;
+        const double l1 = lane + 64 < p ? S[tri(lane + 64, i)] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const double x = bcast_lane(i < 64 ? v0[u] : v1[u], li) * inv;
-          v0[u] = i < 64 && lane == li ? x : fma(-l0, x, v0[u]);
-          v1[u] = i >= 64 && lane == li ? x : fma(-l1, x, v1[u]);
-        }
+        for (int u = 0; u < 8; ++u)
+          if (u < nu) {
+            const double x = bcast_lane(v0[u], i) * inv;
+            v0[u] = lane == i ? x : fma(-l0, x, v0[u]);
+            v1[u] = fma(-l1, x, v1[u]);
+          }
       }
-      for (int i = p - 1; i >= 0; --i) {  // L^T x = y: row i of L left of the diagonal
+      for (int i = 64; i < p; ++i) {  // rows >= 64: only v1 changes
+        const double inv = dg[i];
+        const double l1 = lane + 64 > i && lane + 64 < p ? S[tri(lane + 64, i)] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (u < nu) {
+            const double x = bcast_lane(v1[u], i - 64) * inv;
+            v1[u] = lane == i - 64 ? x : fma(-l1, x, v1[u]);
+          }
+      }
+      for (int i = p - 1; i >= 64; --i) {  // L^T x = y, rows >= 64: row i of L left of the diagonal
+        const double inv = dg[i];
+        const double l0 = S[tri(i, lane)];
+        const double l1 = lane + 64 < i ? S[tri(i, lane + 64)] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (u < nu) {
+            const double x = bcast_lane(v1[u], i - 64) * inv;
+            v1[u] = lane == i - 64 ? x : fma(-l1, x, v1[u]);
+            v0[u] = fma(-l0, x, v0[u]);
+          }
+      }
+      for (int i = ph - 1; i >= 0; --i) {  // rows < 64: only v0 changes
         const double inv = dg[i];
         const double l0 = lane < i ? S[tri(i, lane)] : 0.0;
-        const double l1 = lane + 64 < i ? S[tri(i, lane + 64)] : 0.0;
-        const int li = i & 63;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const double x = bcast_lane(i < 64 ? v0[u] : v1[u], li) * inv;
-          v0[u] = i < 64 && lane == li ? x : fma(-l0, x, v0[u]);
-          v1[u] = i >= 64 && lane == li ? x : fma(-l1, x, v1[u]);
-        }
+        for (int u = 0; u < 8; ++u)
+          if (u < nu) {
+            const double x = bcast_lane(v0[u], i) * inv;
+            v0[u] = lane == i ? x : fma(-l0, x, v0[u]);
+          }
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
