@@ -1548,6 +1548,76 @@ constexpr int kEigCl = kAnalysisCl;
 // index of (i, j), j <= i, in a packed lower triangle
 __device__ inline int tri(int i, int j) { return ((i * (i + 1)) >> 1) + j; }
 
+// S^{-1} (S = L L^T, L packed lower with 1 / L_ii in dg) applied in place to
+// the columns cb, cb + 4, ..., cb + 4 (NU - 1) of Bm (row stride ldp; those
+// past nc are neither read nor written), each in one wave's registers (rows
+// lane and 64 + lane): per row i, x_i = v_i / L_ii goes to every lane by
+// readlane, and the column (forward) or row (backward) of L is read once for
+// all the columns.  In two halves, rows below 64 in v0 and the rest in v1:
+// where x_i comes from and which half changes are then fixed in each.
+template <int NU>
+__device__ inline void cl_solve_columns(double *Bm, const double *S, const double *dg, int cb, int nc,
+                                        int ldp, int p, int lane) {
+  double v0[NU], v1[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int c = cb + 4 * u;
+    const double *col = Bm + (c < nc ? c : 0) * ldp;
+    v0[u] = c < nc && lane < p ? col[lane] : 0.0;
+    v1[u] = c < nc && lane + 64 < p ? col[lane + 64] : 0.0;
+  }
+  const int ph = min(p, 64);
+  for (int i = 0; i < ph; ++i) {  // L y = b, rows < 64: column i of L below the diagonal
+    const double inv = dg[i];
+    const double l0 = lane > i && lane < p ? S[tri(lane, i)] : 0.0;
+    const double l1 = lane + 64 < p ? S[tri(lane + 64, i)] : 0.0;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const double x = bcast_lane(v0[u], i) * inv;
+      v0[u] = lane == i ? x : fma(-l0, x, v0[u]);
+      v1[u] = fma(-l1, x, v1[u]);
+    }
+  }
+  for (int i = 64; i < p; ++i) {  // rows >= 64: only v1 changes
+    const double inv = dg[i];
+    const double l1 = lane + 64 > i && lane + 64 < p ? S[tri(lane + 64, i)] : 0.0;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const double x = bcast_lane(v1[u], i - 64) * inv;
+      v1[u] = lane == i - 64 ? x : fma(-l1, x, v1[u]);
+    }
+  }
+  for (int i = p - 1; i >= 64; --i) {  // L^T x = y, rows >= 64: row i of L left of the diagonal
+    const double inv = dg[i];
+    const double l0 = S[tri(i, lane)];
+    const double l1 = lane + 64 < i ? S[tri(i, lane + 64)] : 0.0;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const double x = bcast_lane(v1[u], i - 64) * inv;
+      v1[u] = lane == i - 64 ? x : fma(-l1, x, v1[u]);
+      v0[u] = fma(-l0, x, v0[u]);
+    }
+  }
+  for (int i = ph - 1; i >= 0; --i) {  // rows < 64: only v0 changes
+    const double inv = dg[i];
+    const double l0 = lane < i ? S[tri(i, lane)] : 0.0;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const double x = bcast_lane(v0[u], i) * inv;
+      v0[u] = lane == i ? x : fma(-l0, x, v0[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int c = cb + 4 * u;
+    if (c < nc) {
+      double *col = Bm + c * ldp;
+      if (lane < p) col[lane] = v0[u];
+      if (lane + 64 < p) col[lane + 64] = v1[u];
+    }
+  }
+}
+
 template <typename T, bool FUSED>
 __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1698,77 +1768,19 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   bad = bad || __syncthreads_or(fail);
 
   // ---- 7. [K^T | v] = S^{-1} [B_own^T | dd] in place: wave q takes the
-  // columns q, q + 4, ... (eight at a time), each in registers (rows lane and
-  // 64 + lane); per row i, x_i = v_i / L_ii goes to every lane by readlane and
-  // the column (forward) or row (backward) of L is read once for all of them ----
+  // columns q, q + 4, ..., up to eight at a time (cl_solve_columns) ----
   const int nc = nown + 1;
   if (!bad)
     for (int cb = q; cb < nc; cb += 4 * 8) {
-      double v0[8], v1[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int c = cb + 4 * u;
-        const double *col = Bm + (c < nc ? c : 0) * ldp;
-        v0[u] = c < nc && lane < p ? col[lane] : 0.0;
-        v1[u] = c < nc && lane + 64 < p ? col[lane + 64] : 0.0;
-      }
-      // (in two halves, rows below 64 in v0 and the rest in v1: where x_i
-      // comes from and which half changes are then known in each)
       const int nu = min(8, (nc - cb + 3) >> 2);  // this wave's columns in the chunk
-      const int ph = min(p, 64);
-      for (int i = 0; i < ph; ++i) {  // L y = b, rows < 64: column i of L below the diagonal
-        const double inv = dg[i];
-        const double l0 = lane > i && lane < p ? S[tri(lane, i)] : 0.0;
-        const double l1 = lane + 64 < p ? S[tri(lane + 64, i)] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (u < nu) {
-            const double x = bcast_lane(v0[u], i) * inv;
-            v0[u] = lane == i ? x : fma(-l0, x, v0[u]);
-            v1[u] = fma(-l1, x, v1[u]);
-          }
-      }
-      for (int i = 64; i < p; ++i) {  // rows >= 64: only v1 changes
-        const double inv = dg[i];
-        const double l1 = lane + 64 > i && lane + 64 < p ? S[tri(lane + 64, i)] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (u < nu) {
-            const double x = bcast_lane(v1[u], i - 64) * inv;
-            v1[u] = lane == i - 64 ? x : fma(-l1, x, v1[u]);
-          }
-      }
-      for (int i = p - 1; i >= 64; --i) {  // L^T x = y, rows >= 64: row i of L left of the diagonal
-        const double inv = dg[i];
-        const double l0 = S[tri(i, lane)];
-        const double l1 = lane + 64 < i ? S[tri(i, lane + 64)] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (u < nu) {
-            const double x = bcast_lane(v1[u], i - 64) * inv;
-            v1[u] = lane == i - 64 ? x : fma(-l1, x, v1[u]);
-            v0[u] = fma(-l0, x, v0[u]);
-          }
-      }
-      for (int i = ph - 1; i >= 0; --i) {  // rows < 64: only v0 changes
-        const double inv = dg[i];
-        const double l0 = lane < i ? S[tri(i, lane)] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (u < nu) {
-            const double x = bcast_lane(v0[u], i) * inv;
-            v0[u] = lane == i ? x : fma(-l0, x, v0[u]);
-          }
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int c = cb + 4 * u;
-        if (c < nc) {
-          double *col = Bm + c * ldp;
-          if (lane < p) col[lane] = v0[u];
-          if (lane + 64 < p) col[lane + 64] = v1[u];
-        }
-      }
+      if (nu <= 2)
+        cl_solve_columns<2>(Bm, S, dg, cb, nc, ldp, p, lane);
+      else if (nu <= 4)
+        cl_solve_columns<4>(Bm, S, dg, cb, nc, ldp, p, lane);
+      else if (nu <= 6)
+        cl_solve_columns<6>(Bm, S, dg, cb, nc, ldp, p, lane);
+      else
+        cl_solve_columns<8>(Bm, S, dg, cb, nc, ldp, p, lane);
     }
   __syncthreads();
   const double *R = Bm;
