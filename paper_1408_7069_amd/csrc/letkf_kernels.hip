@@ -1826,16 +1826,28 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   for (int i = q; i < nown; i += kWaves) {
     const double *Ki = R + i * ldp;
     double xa = (double)xm[i];
-    if (!bad)
-      for (int s = 0; s < p; ++s) xa = fma(Ki[s], dd[s], xa);
+    if (!bad) {  // K_i dd: the slopes dealt to the lanes, summed over the wave
+      double part = 0.0;
+      for (int s = lane; s < p; s += 64) part = fma(Ki[s], dd[s], part);
+      xa += wave_sum(part);
+    }
     if (lane < m) {
       double v;
       if (bad) {
         v = (double)xs[i * kXsStride + lane];
       } else {
-        double corr = 0.0;
-        for (int n = 0; n < np; ++n)
-          corr = fma(Mk[i * 64 + n], (double)xs[n * kXsStride + lane] - (double)xm[n], corr);
+        // M_i X'_P for this member, four partial sums
+        const double *Mi = Mk + i * 64;
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+        int n = 0;
+        for (; n + 3 < np; n += 4) {
+          c0 = fma(Mi[n], (double)xs[n * kXsStride + lane] - (double)xm[n], c0);
+          c1 = fma(Mi[n + 1], (double)xs[(n + 1) * kXsStride + lane] - (double)xm[n + 1], c1);
+          c2 = fma(Mi[n + 2], (double)xs[(n + 2) * kXsStride + lane] - (double)xm[n + 2], c2);
+          c3 = fma(Mi[n + 3], (double)xs[(n + 3) * kXsStride + lane] - (double)xm[n + 3], c3);
+        }
+        for (; n < np; ++n) c0 = fma(Mi[n], (double)xs[n * kXsStride + lane] - (double)xm[n], c0);
+        const double corr = (c0 + c1) + (c2 + c3);
         v = xa + srho * (((double)xs[i * kXsStride + lane] - (double)xm[i]) - 0.5 * corr);
       }
       A.x_out[in.x_off + (int64_t)pn[i] * m + lane] = (T)v;
