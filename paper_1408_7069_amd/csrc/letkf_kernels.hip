@@ -1786,17 +1786,16 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   const double *R = Bm;
 
   // ---- 8. M = K Dt (owned rows x patch), from each patch node's corner
-  // roles (at most four subapertures; found in subaperture order) ----
-  int *adj = (int *)dg;  // [64][4] (subaperture | role << 8), after the pivots
-  if (tid < np) {
-    int cnt = 0;
-    for (int o = 0; o < nobs && cnt < 4; ++o) {
-      const uint32_t w = cw[o];
+  // roles: on the grid a node is corner a, b, c or d of at most one
+  // subaperture each, so every observation writes its four corners' entries
+  // at once (no two write the same) ----
+  int *adj = (int *)dg;  // [64][4]: the subaperture where node n is corner a, b, c, d (-1: none)
+  for (int e = tid; e < 64 * 4; e += kThreads) adj[e] = -1;
+  __syncthreads();
+  if (tid < nobs) {
+    const uint32_t w = cw[tid];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if ((int)((w >> (8 * t)) & 255) == tid && cnt < 4) adj[tid * 4 + cnt++] = o | (t << 8);
-    }
-    for (; cnt < 4; ++cnt) adj[tid * 4 + cnt] = -1;
+    for (int t = 0; t < 4; ++t) adj[(int)((w >> (8 * t)) & 255) * 4 + t] = tid;
   }
   __syncthreads();
   double *Mk = S;  // [own row][64]
@@ -1807,11 +1806,10 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
       if (n < np) {
         const double *Ki = R + i * ldp;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int a = adj[n * 4 + u];
-          if (a < 0) break;
-          const int o = a & 255, t = a >> 8;
-          const double cx = (t & 1) ? 0.5 : -0.5, cy = (t & 2) ? 0.5 : -0.5;  // roles a, b, c, d
+        for (int u = 0; u < 4; ++u) {  // roles a, b, c, d
+          const int o = adj[n * 4 + u];
+          if (o < 0) continue;
+          const double cx = (u & 1) ? 0.5 : -0.5, cy = (u & 2) ? 0.5 : -0.5;
           v = fma(Ki[o] * sg[o], cx, v);
           v = fma(Ki[nobs + o] * sg[nobs + o], cy, v);
         }
