@@ -1725,7 +1725,7 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
         if (c < kb) {
           const double d = bcast_lane(L0[c], c);  // the pivot (row k0 + c)
           fail |= !(d > 0.0);
-          const double ljj = sqrt(d), inv = 1.0 / ljj;
+          const double inv = rsq_nr(d, 2), ljj = d * inv;  // 1 / sqrt(d) refined twice
           L0[c] = lane == c ? ljj : (lane > c ? L0[c] * inv : L0[c]);
           L1[c] *= inv;
           if (lane == c) dg[k0 + c] = inv;
