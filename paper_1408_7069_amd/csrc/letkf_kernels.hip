@@ -1633,7 +1633,8 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   T *xm = (T *)(smem + A.off_xm);
   const double *sg = (const double *)(smem + A.off_sg);
   const double *dd = (const double *)(smem + A.off_dd);
-  uint32_t *cw = (uint32_t *)(smem + A.off_yb);  // corner words of the region's subapertures
+  // corner words of the region's subapertures, as stage 2 left them
+  const uint32_t *cw = (const uint32_t *)(smem + A.off_pn) + kPnCw;
   int *pn = (int *)(smem + A.off_pn);
   double *dg = (double *)(smem + A.off_s);       // pivots sqrt(S_kk) of the Cholesky
   double *xt = (double *)(smem + A.off_u);       // X'_P^T in FP64, [member][kClXtStride]
@@ -1643,8 +1644,9 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   bool bad = stage_gram<T, FUSED, false, true>(A, it, in, frame, smem);
 
   // ---- 3. P_loc ----
-  if (tid < nobs) cw[tid] = A.obs_corner[it.obs_off + tid];
-  if (tid < np) {
+  // the patch nodes' grid coordinates (stage 1 leaves them when the noise
+  // comes from the bank)
+  if (!(FUSED && A.noise_bank) && tid < np) {
     const int64_t g = in.node_off + pn[tid];
     pn[64 + tid] = A.node_ij[2 * g] | (A.node_ij[2 * g + 1] << 16);
   }
