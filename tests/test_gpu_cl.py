@@ -59,6 +59,38 @@ def test_cl_frames(path, fp64, tol, geom):
         prev = got
 
 
+@pytest.mark.parametrize("path", ["graph", "plain"])
+@pytest.mark.parametrize("fp64,tol", [(True, 1e-10), (False, 1e-4)])
+def test_cl_frames_large_domains(path, fp64, tol):
+    """5 x 5 domains on a square 15 x 15 grid: up to 36 owned nodes, so 37
+    right-hand sides in the solves (a chunk of eight a wave and a second one),
+    and up to 49 observation subapertures, p = 98 slopes (past row 64; seven
+    Cholesky panels, the last a short one)."""
+    case = Case(15, None, 5, 1, 48, seed=83, fp64=fp64, taper_c=3.0, piston=True)
+    assert max(len(d.owned) for d in case.doms) + 1 > 32
+    assert 2 * max(len(d.obs_subaps) for d in case.doms) > 64
+    bb = B()
+    f = bb.Letkf([case.spec(bb, localisation=bb.LOCALISATION_COVARIANCE)])
+    f.set_schedule(path == "graph", True)
+    X0 = (case.rng.standard_normal((case.G.n_nodes, case.m)) * 0.5 + case.truth()[:, None]).astype(case.dt)
+    f.set_ensemble(_t(X0, case.dt))
+    prev = np.asarray(X0, np.float64)
+    for k in range(2):
+        V, y = case.noise(), case.slopes(case.truth())
+        if path == "plain":
+            f.step_plain(_t(y, case.dt), V=_t(V, case.dt))
+        else:
+            f.step(_t(y, case.dt), V=_t(V, case.dt))
+        torch.cuda.synchronize()
+        got = _ens(f, case.m)
+        ref = CL.step(case.G, case.doms, prev, np.asarray(V, np.float64), np.asarray(y, np.float64), case.r,
+                      case.prm)
+        assert rel_err(got.mean(1), ref.mean(1)) <= tol, k
+        assert rel_err(got, ref) <= tol, k
+        assert f.status()[0] == bb.OK
+        prev = got
+
+
 def test_full_size_cl_frame():
     # 80x80, 28 % obscuration, m = 64, 2-pitch taper, bank noise, graph
     # replay, pistons
