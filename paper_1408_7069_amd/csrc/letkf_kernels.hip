@@ -1548,6 +1548,8 @@ constexpr int kEigCl = kAnalysisCl;
 // index of (i, j), j <= i, in a packed lower triangle
 __device__ inline int tri(int i, int j) { return ((i * (i + 1)) >> 1) + j; }
 
+constexpr int kClPanel = 8;  // columns of a Cholesky panel (covariance localisation)
+
 // S^{-1} (S = L L^T, L packed lower with 1 / L_ii in dg) applied in place to
 // the columns cb, cb + 4, ..., cb + 4 (NU - 1) of Bm (row stride ldp; those
 // past nc are neither read nor written), each in one wave's registers (rows
@@ -1707,23 +1709,25 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   for (int s = tid; s < p; s += kThreads) Bm[nown * ldp + s] = dd[s];
 
   // ---- 6. Cholesky S = L L^T in place (packed lower triangle), by panels
-  // of 16 columns: wave 0 factors a panel in registers (rows k0 + lane and
-  // k0 + 64 + lane; the entries of column c2 of the panel at row k0 + c2 come
-  // from lane c2 by readlane), then every wave subtracts the panel's product
-  // from the trailing triangle: two barriers a panel.  dg[k] = 1 / L_kk ----
+  // of kClPanel columns: wave 0 factors a panel in registers (rows k0 + lane
+  // and k0 + 64 + lane; the entries of column c2 of the panel at row k0 + c2
+  // come from lane c2 by readlane), then every wave subtracts the panel's
+  // product from the trailing triangle: two barriers a panel (eight columns:
+  // the panel's serial work, which grows with its width, against the barriers).
+  // dg[k] = 1 / L_kk ----
   int fail = 0;
-  for (int k0 = 0; k0 < p; k0 += 16) {
-    const int kb = min(16, p - k0), k1 = k0 + kb;
+  for (int k0 = 0; k0 < p; k0 += kClPanel) {
+    const int kb = min(kClPanel, p - k0), k1 = k0 + kb;
     if (q == 0) {
       const int r0 = k0 + lane, r1 = r0 + 64;
-      double L0[16], L1[16];
+      double L0[kClPanel], L1[kClPanel];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
+      for (int c = 0; c < kClPanel; ++c) {
         L0[c] = (c < kb && r0 < p && k0 + c <= r0) ? S[tri(r0, k0 + c)] : 0.0;
         L1[c] = (c < kb && r1 < p) ? S[tri(r1, k0 + c)] : 0.0;
       }
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
+      for (int c = 0; c < kClPanel; ++c) {
         if (c < kb) {
           const double d = bcast_lane(L0[c], c);  // the pivot (row k0 + c)
           fail |= !(d > 0.0);
@@ -1732,7 +1736,7 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
           L1[c] *= inv;
           if (lane == c) dg[k0 + c] = inv;
 #pragma unroll
-          for (int c2 = c + 1; c2 < 16; ++c2) {
+          for (int c2 = c + 1; c2 < kClPanel; ++c2) {
             const double lc = bcast_lane(L0[c], c2);  // L[k0 + c2][k0 + c]
             L0[c2] = lane >= c2 ? fma(-L0[c], lc, L0[c2]) : L0[c2];
             L1[c2] = fma(-L1[c], lc, L1[c2]);
@@ -1740,25 +1744,25 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
         }
       }
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
+      for (int c = 0; c < kClPanel; ++c) {
         if (c < kb && r0 < p && k0 + c <= r0) S[tri(r0, k0 + c)] = L0[c];
         if (c < kb && r1 < p) S[tri(r1, k0 + c)] = L1[c];
       }
     }
     __syncthreads();
     // trailing triangle (rows and columns from k1) on a 16 x 16 grid: the
-    // panel is full (kb = 16) wherever a trailing triangle is left
+    // panel is full (kb = kClPanel) wherever a trailing triangle is left
     for (int a = tid >> 4; a < p - k1; a += 16) {
       const int i = k1 + a;
       const double *Li = S + tri(i, k0);
-      double li[16];
+      double li[kClPanel];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) li[j] = Li[j];
+      for (int j = 0; j < kClPanel; ++j) li[j] = Li[j];
       for (int b = tid & 15; b <= a; b += 16) {
         const double *Lc = S + tri(k1 + b, k0);
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int j = 0; j < 16; j += 2) {
+        for (int j = 0; j < kClPanel; j += 2) {
           s0 = fma(li[j], Lc[j], s0);
           s1 = fma(li[j + 1], Lc[j + 1], s1);
         }
