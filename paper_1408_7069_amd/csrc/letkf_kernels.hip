@@ -1568,7 +1568,11 @@ __device__ inline void cl_solve_columns(double *Bm, const double *S, const doubl
     v0[u] = c < nc && lane < p ? col[lane] : 0.0;
     v1[u] = c < nc && lane + 64 < p ? col[lane + 64] : 0.0;
   }
+  // Row i keeps its value at step i (no later step of the sweep changes it),
+  // so each sweep leaves v_i and one product v_i / L_ii per row afterwards
+  // gives x_i, the same product step i broadcast.
   const int ph = min(p, 64);
+  const double d0 = lane < p ? dg[lane] : 0.0, d1 = lane + 64 < p ? dg[lane + 64] : 0.0;
   for (int i = 0; i < ph; ++i) {  // L y = b, rows < 64: column i of L below the diagonal
     const double inv = dg[i];
     const double l0 = lane > i && lane < p ? S[tri(lane, i)] : 0.0;
@@ -1576,7 +1580,7 @@ __device__ inline void cl_solve_columns(double *Bm, const double *S, const doubl
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const double x = bcast_lane(v0[u], i) * inv;
-      v0[u] = lane == i ? x : fma(-l0, x, v0[u]);
+      v0[u] = fma(-l0, x, v0[u]);
       v1[u] = fma(-l1, x, v1[u]);
     }
   }
@@ -1586,8 +1590,13 @@ __device__ inline void cl_solve_columns(double *Bm, const double *S, const doubl
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const double x = bcast_lane(v1[u], i - 64) * inv;
-      v1[u] = lane == i - 64 ? x : fma(-l1, x, v1[u]);
+      v1[u] = fma(-l1, x, v1[u]);
     }
+  }
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    v0[u] *= d0;
+    v1[u] *= d1;
   }
   for (int i = p - 1; i >= 64; --i) {  // L^T x = y, rows >= 64: row i of L left of the diagonal
     const double inv = dg[i];
@@ -1596,7 +1605,7 @@ __device__ inline void cl_solve_columns(double *Bm, const double *S, const doubl
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const double x = bcast_lane(v1[u], i - 64) * inv;
-      v1[u] = lane == i - 64 ? x : fma(-l1, x, v1[u]);
+      v1[u] = fma(-l1, x, v1[u]);
       v0[u] = fma(-l0, x, v0[u]);
     }
   }
@@ -1606,8 +1615,13 @@ __device__ inline void cl_solve_columns(double *Bm, const double *S, const doubl
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const double x = bcast_lane(v0[u], i) * inv;
-      v0[u] = lane == i ? x : fma(-l0, x, v0[u]);
+      v0[u] = fma(-l0, x, v0[u]);
     }
+  }
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    v0[u] *= d0;
+    v1[u] *= d1;
   }
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
