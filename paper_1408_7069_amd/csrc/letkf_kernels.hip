@@ -1749,10 +1749,13 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
           L0[c] = lane == c ? ljj : (lane > c ? L0[c] * inv : L0[c]);
           L1[c] *= inv;
           if (lane == c) dg[k0 + c] = inv;
+          // (lanes above column c2's diagonal take garbage here: never read
+          // by the steps, which read a column at its diagonal and below, and
+          // never stored)
 #pragma unroll
           for (int c2 = c + 1; c2 < kClPanel; ++c2) {
             const double lc = bcast_lane(L0[c], c2);  // L[k0 + c2][k0 + c]
-            L0[c2] = lane >= c2 ? fma(-L0[c], lc, L0[c2]) : L0[c2];
+            L0[c2] = fma(-L0[c], lc, L0[c2]);
             L1[c2] = fma(-L1[c], lc, L1[c2]);
           }
         }
