@@ -1707,14 +1707,18 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
 
   // ---- 5. S = Dt B + I, lower triangle packed, over P_loc ----
   double *S = Pm;
-  for (int e = tid; e < p * p; e += kThreads) {
-    const int s = e / p, t = e - s * p;
-    if (t > s) continue;
+  for (int e = tid; e < tri(p, 0); e += kThreads) {  // the packed entries in order
+    // row s of entry e: the largest s with tri(s, 0) <= e (the float root is
+    // exact to one, corrected by the two comparisons)
+    int s = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    s += tri(s + 1, 0) <= e ? 1 : 0;
+    s -= tri(s, 0) > e ? 1 : 0;
+    const int t = e - tri(s, 0);
     const uint32_t w = cw[s < nobs ? s : s - nobs];
     const int ca = w & 255, cb = (w >> 8) & 255, cc = (w >> 16) & 255, cd = w >> 24;
     const double ba = Bm[ca * ldp + t], bb = Bm[cb * ldp + t], bc = Bm[cc * ldp + t], bd = Bm[cd * ldp + t];
     const double v = s < nobs ? (bb - ba) + (bd - bc) : (bc - ba) + (bd - bb);
-    S[tri(s, t)] = 0.5 * sg[s] * v + (s == t ? 1.0 : 0.0);
+    S[e] = 0.5 * sg[s] * v + (s == t ? 1.0 : 0.0);
   }
   __syncthreads();
   // the solve's columns: B's owned rows (patch rows 0..n_own - 1) as they
