@@ -1682,8 +1682,13 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   }
   __syncthreads();
   const double kap = in.rho / (double)(m - 1), cw_taper = in.taper_c;
-  for (int e = tid; e < np * np; e += kThreads) {
-    const int i = e / np, j = e - i * np;
+  // one weight per pair (i >= j, the packed lower triangle's entries in
+  // order), applied to both entries: P_loc and the taper are symmetric
+  for (int e = tid; e < tri(np, 0); e += kThreads) {
+    int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    i += tri(i + 1, 0) <= e ? 1 : 0;
+    i -= tri(i, 0) > e ? 1 : 0;
+    const int j = e - tri(i, 0);
     double t = kap;
     if (cw_taper > 0.0) {
       const int a = pn[64 + i], b = pn[64 + j];
@@ -1691,6 +1696,7 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
       t *= gaspari_cohn(sqrt(di * di + dj * dj) / cw_taper);
     }
     Pm[i * kLaStride + j] *= t;
+    if (i != j) Pm[j * kLaStride + i] *= t;
   }
   __syncthreads();
 
