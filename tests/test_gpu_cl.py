@@ -91,6 +91,29 @@ def test_cl_frames_large_domains(path, fp64, tol):
         prev = got
 
 
+def test_cl_launch_forms_agree_bitwise():
+    """The covariance-localisation kernel gives the same bits from the graph,
+    direct launches (either item order) and one launch per domain: every
+    reduction in it has a fixed order."""
+    case = Case(15, None, 5, 1, 48, seed=84, taper_c=3.0, piston=True)
+    bb = B()
+    outs = []
+    for mode in ["plain", (True, True), (True, False), (False, True), (False, False)]:
+        f = bb.Letkf([case.spec(bb, localisation=bb.LOCALISATION_COVARIANCE)])
+        rng = np.random.default_rng(1)
+        for _k in range(2):
+            y = (rng.standard_normal(case.G.n_slopes) * 2).astype(np.float32)
+            if mode == "plain":
+                f.step_plain(_t(y, np.float32), V=None)
+            else:
+                f.set_schedule(*mode)
+                f.step(_t(y, np.float32), V=None)
+        torch.cuda.synchronize()
+        outs.append(f.get_ensemble().cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
 def test_full_size_cl_frame():
     # 80x80, 28 % obscuration, m = 64, 2-pitch taper, bank noise, graph
     # replay, pistons
