@@ -52,17 +52,95 @@ def measured_traffic():
     return float(kv["hbm_bytes_per_launch"])
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 FP32_MFMA_PEAK_TFLOPS = 157.3
+TRACE_FILE = os.path.join(ROOT, "profiles", "k_analysis_80x80_m64_trace.md")
 
 
 def algorithmic_flops(m: int, p_list, n_list) -> dict:
-    """Nominal work of one frame's analyses (per domain: Gram 2 m^2 p, symmetric
-    EVD with vectors 9 m^3, transform 2 m^3, update 2 n m^2 + 2 n m, the slope
-    stencil 4 p m and Y^T d 2 p m)."""
+    """Nominal work of one instance's analyses per frame.  Counted against the
+    roofline: the symmetric EVD with vectors, 9 m^3 per domain (FP64), the Gram
+    2 m^2 p_l and the update 2 n_l m^2 (FP32 matrix cores).  Reported beside it,
+    not counted: the transform W = Q Gamma^{-1/2} Q^T (2 m^3), the mean update
+    2 n_l m and the slope stencil with Y^T d (6 p_l m)."""
     p = np.asarray(p_list, dtype=np.float64)
     n = np.asarray(n_list, dtype=np.float64)
     d = len(p)
-    return {"gram": float(np.sum(2 * m * m * p)), "evd": 9.0 * m ** 3 * d, "transform": 2.0 * m ** 3 * d,
-            "update": float(np.sum(2 * n * m * m + 2 * n * m)), "stencil": float(np.sum(6 * p * m))}
+    return {"evd_fp64": 9.0 * m ** 3 * d, "gram_fp32": float(np.sum(2 * m * m * p)),
+            "update_fp32": float(np.sum(2 * n * m * m)),
+            "not_counted": {"transform_2m3": 2.0 * m ** 3 * d, "mean_update": float(np.sum(2 * n * m)),
+                            "stencil_and_ytd": float(np.sum(6 * p * m))}}
+
+
+def bound_seconds(fl: dict) -> float:
+    """Lower-bound time of the counted work at the MI355X peaks: the FP64 part
+    at 78.6 TFLOP/s, the FP32 matrix-core part at 157.3 TFLOP/s."""
+    return (fl["evd_fp64"] / (FP64_PEAK_TFLOPS * 1e12)
+            + (fl["gram_fp32"] + fl["update_fp32"]) / (FP32_MFMA_PEAK_TFLOPS * 1e12))
+
+
+def handle_bound(f) -> tuple[float, dict]:
+    """Sum of the per-instance lower bounds of a handle (each instance with its
+    own m, p_l and n_l), and the summed counts."""
+    t, tot = 0.0, {"evd_fp64": 0.0, "gram_fp32": 0.0, "update_fp32": 0.0}
+    for i, sp in enumerate(f.specs):
+        g = f.geometry(i)
+        fl = algorithmic_flops(sp.m, np.diff(g["obs_off"]), np.diff(g["own_off"]))
+        t += bound_seconds(fl)
+        for k in tot:
+            tot[k] += fl[k]
+    return t, tot
+
+
+def trace_kernel_ms():
+    """Average k_analysis duration of the committed rocprofv3 trace when it was
+    taken on the current kernel source, else None."""
+    if not os.path.exists(TRACE_FILE):
+        return None
+    txt = open(TRACE_FILE).read()
+    if f"kernel_sha256_16: {kernel_hash()}" not in txt:
+        return None
+    for line in txt.splitlines():
+        if line.startswith("trace_kernel_avg_us:"):
+            return float(line.split(":", 1)[1]) * 1e-3
+    return None
+
+
+def transform_name(B, t: int) -> str:
+    return {B.TRANSFORM_NS64: "NS64", B.TRANSFORM_NS32: "NS32", B.TRANSFORM_EVD: "EVD"}.get(
+        t, getattr(B, "TRANSFORM_NAMES", {}).get(t, str(t)))
+
+
+def schedule_label(sched) -> str:
+    g, order = sched
+    orders = {0: "row-major item order", 1: "XCD-contiguous item order",
+              2: "XCD-contiguous item order, cost-paired second dispatch round"}
+    return ("graph-replayed" if g else "directly launched") + ", " + orders.get(int(order), f"order {order}")
+
+
+def batched_line(B, spec, y, K, W, copies: int) -> dict:
+    """`copies` instances of the workload in one launch: frame time (graph
+    replay), the analysis kernel's duration (HIP events around its direct
+    launches) and the roofline fraction of both, sum(T_lb) over the instances
+    divided by that time."""
+    import torch
+    f = B.Letkf([spec] * copies)
+    yc = y.repeat(1, copies) if copies > 1 else y
+    f.set_schedule(True, 1)
+    ms = time_steps(f, yc, K, W)
+    f.set_ensemble(torch.zeros(f.sizes["ensemble_elems"], dtype=torch.float32, device="cuda"))
+    f.set_frame(0)
+    f.set_schedule(False, 1)
+    time_steps(f, yc, 0, W)
+    f.set_timing(True)
+    time_steps(f, yc, K, 0, offset=W)
+    kt = float(np.mean(f.analysis_times()))
+    f.set_timing(False)
+    t_lb, _ = handle_bound(f)
+    nd = int(f.sizes["n_domains"])
+    f.close()
+    return {"instances": copies, "domains": nd, "ms_per_step": round(ms, 4), "kernel_ms": round(kt, 4),
+            "local_analyses_per_s": round(nd * 1000.0 / ms, 1),
+            "t_lb_us": round(t_lb * 1e6, 3), "frac_kernel": round(t_lb / (kt * 1e-3), 4),
+            "frac_frame": round(t_lb / (ms * 1e-3), 4)}
 
 
 def transform_variants(B, spec, y, K, W):
@@ -283,9 +361,72 @@ def time_steps(f, y, K, W, plain=False, per_step=False, offset=0):
     return e0.elapsed_time(e1) / K
 
 
-def cpu_baseline(w, bank, seed, truth, sigma_noise, budget_s=12.0):
-    """The FP64 oracle on the same workload, one thread, frames until the budget.
-    Its slopes are made from the same true phase with the oracle's own operator."""
+def host_cpu() -> dict:
+    """CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+_POOL = {}
+
+
+def _pool_init(state):
+    from threadpoolctl import threadpool_limits
+    _POOL.update(state)
+    _POOL["limit"] = threadpool_limits(limits=1)
+
+
+def _pool_domains(idx):
+    """Local analyses (L1-L5) of the given domains of the staged frame."""
+    from oracle import letkf as ol
+    st = _POOL
+    prm, doms = st["prm"], st["doms"]
+    for k in idx:
+        dom = doms[k]
+        Y, dl, g = ol.local_inputs(st["G"], dom, st["Yp"], st["d"], st["r"], prm)
+        wv, Wm, _, _ = ol.local_weights(Y, dl, g, prm.rho)
+        ol.local_update(st["xb"][dom.owned], st["Xp"][dom.owned], wv, Wm, prm.rho)
+    return len(idx)
+
+
+def table2_domain_ms(reps: int = 200) -> float:
+    """The oracle's local update of one domain at the paper's Table 2 shape
+    (m = 101 members, n = 32 state entries, p = 128 slopes), one thread,
+    median over `reps` calls, in ms."""
+    from threadpoolctl import threadpool_limits
+    from oracle import letkf as ol
+    rng = np.random.default_rng(11)
+    m, n, p = 101, 32, 128
+    Xp = rng.standard_normal((n, m))
+    Xp -= Xp.mean(axis=1, keepdims=True)
+    Y = rng.standard_normal((p, m))
+    Y -= Y.mean(axis=1, keepdims=True)
+    d, g, xb = rng.standard_normal(p), np.full(p, 100.0), rng.standard_normal(n)
+    ts = []
+    with threadpool_limits(limits=1):
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            wv, Wm, _, _ = ol.local_weights(Y, d, g, 1.05)
+            ol.local_update(xb, Xp, wv, Wm, 1.05)
+            ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)) * 1e3
+
+
+def cpu_baseline(w, bank, seed, truth, sigma_noise, budget_s=10.0, pool_s=8.0):
+    """The FP64 oracle on the same workload: full frames on one thread until
+    the budget; then the local analyses of one staged frame spread over a
+    process pool (one single-threaded process per usable core, at most 16);
+    then one domain at the paper's Table 2 shape.  The oracle's slopes are made
+    from the same true phase with the oracle's own operator."""
+    import multiprocessing as mp
     from threadpoolctl import threadpool_limits
     from oracle import geometry as og
     from oracle import letkf as ol
@@ -307,9 +448,34 @@ def cpu_baseline(w, bank, seed, truth, sigma_noise, budget_s=12.0):
             if done >= len(y_host):
                 break
     dt = time.perf_counter() - t0
+    # the local analyses of the next frame over a process pool (spawned
+    # interpreters: numpy and the oracle only)
+    V = philox.bank_noise(bank, ij, w.m, seed, 0, done)
+    Xb = ol.forecast(Xa, V, prm.a)
+    xb, Xp = ol.ensemble_stats(Xb)
+    state = {"G": G, "doms": doms, "prm": prm, "r": r, "xb": xb, "Xp": Xp,
+             "Yp": og.apply_slopes(G, Xp), "d": y_host[done % len(y_host)] - og.apply_slopes(G, xb)}
+    cpu = host_cpu()
+    nproc = max(1, min(16, cpu["usable_cpus"] or 1))
+    chunks = [list(range(k, len(doms), nproc)) for k in range(nproc)]
+    with mp.get_context("spawn").Pool(nproc, initializer=_pool_init, initargs=(state,)) as pool:
+        pool.map(_pool_domains, chunks)          # warm-up (imports, BLAS set-up)
+        n_an, t1 = 0, time.perf_counter()
+        while n_an == 0 or time.perf_counter() - t1 < pool_s:
+            n_an += sum(pool.map(_pool_domains, chunks))
+        pool_dt = time.perf_counter() - t1
+    per_core = done * len(doms) / dt
     return {"value": done / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} frames of the same 80x80 m=64 workload (332 local analyses each), "
-                      f"NumPy FP64 with LAPACK eigh, one thread, {dt:.1f} s"}
+            "sample": f"{done} frames of the same 80x80 m=64 workload ({len(doms)} local analyses each, "
+                      f"piston step included), NumPy FP64 with LAPACK eigh, one thread, {dt:.1f} s",
+            "host": cpu,
+            "local_analyses_per_s_1core": round(per_core, 1),
+            "all_cores": {"processes": nproc, "local_analyses_per_s": round(n_an / pool_dt, 1),
+                          "frames_per_s_analyses_only": round(n_an / pool_dt / len(doms), 2),
+                          "sample": f"{n_an} local analyses (L1-L5 of one staged frame, repeated) in "
+                                    f"{pool_dt:.1f} s over {nproc} single-threaded processes"},
+            "table2_domain": {"shape": "m=101, n=32, p=128", "oracle_ms_1core": round(table2_domain_ms(), 4),
+                              "paper_ms": 0.94, "paper_hardware": "1 core of 2x Intel Xeon E5-2680 v2 (Table 2)"}}
 
 
 def other_workloads(B, wl, K, W):
@@ -344,9 +510,21 @@ def other_workloads(B, wl, K, W):
             f.slopes(phase, out=y[k])
             y[k] += torch.randn(f.sizes["n_slopes"], dtype=dt, device="cuda") * float(ws[0].sigma)
         ms = time_steps(f, y, K, W)
-        out[label] = {"instances": len(ws), "domains": int(f.sizes["n_domains"]),
-                      "ms_per_step": round(ms, 4), "frames_per_s": round(1000.0 / ms, 1),
-                      "local_analyses_per_s": round(f.sizes["n_domains"] * 1000.0 / ms, 1)}
+        row = {"instances": len(ws), "domains": int(f.sizes["n_domains"]),
+               "ms_per_step": round(ms, 4), "frames_per_s": round(1000.0 / ms, 1),
+               "local_analyses_per_s": round(f.sizes["n_domains"] * 1000.0 / ms, 1)}
+        if not f.fp64:
+            # the analysis kernel's own duration, and the roofline fraction with
+            # each instance's own m, p_l and n_l
+            f.set_schedule(False, 1)
+            f.set_timing(True)
+            time_steps(f, y, K, 0)
+            kt = float(np.mean(f.analysis_times()))
+            f.set_timing(False)
+            t_lb, _ = handle_bound(f)
+            row.update({"kernel_ms": round(kt, 4), "t_lb_us": round(t_lb * 1e6, 3),
+                        "frac_kernel": round(t_lb / (kt * 1e-3), 4), "frac_frame": round(t_lb / (ms * 1e-3), 4)})
+        out[label] = row
         f.close()
     return out
 
@@ -388,7 +566,8 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--plain-steps", type=int, default=5)
-    ap.add_argument("--copies", type=int, default=4, help="instances of the workload in one launch (batched throughput line)")
+    ap.add_argument("--copies", default="1,4,16,64",
+                    help="comma list: instances of the workload in one launch (batched throughput lines)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: timed steps only")
     ap.add_argument("--grad-frames", type=int, default=200, help="frames of the gradient timing (0 = skip)")
@@ -430,7 +609,7 @@ def main():
         print(json.dumps({"profile_run": True, "steps": K, "copy_bytes": COPY_BYTES}))
         return
 
-    sched = f.autotune(y[0], frames=10)
+    sched = f.autotune(y[0], frames=50)
     f.set_ensemble(torch.zeros(f.sizes["ensemble_elems"], dtype=torch.float32, device="cuda"))
     f.set_frame(0)
     ms = time_steps(f, y, K, W)
@@ -463,46 +642,44 @@ def main():
     time_steps(f, y, 0, W)
     plain_ms = time_steps(f, y, args.plain_steps, 0, plain=True, offset=W)
 
+    # roofline of the analysis kernel: the counted work's lower-bound time at
+    # the MI355X peaks over the kernel's own duration (HIP events around its
+    # direct launches; the committed rocprofv3 trace's average beside it)
+    t_lb, fl = handle_bound(f)
     g = f.geometry(0)
-    p_list = np.diff(g["obs_off"])
-    n_list = np.diff(g["own_off"])
-    fl = algorithmic_flops(w.m, p_list, n_list)
-    total = sum(fl.values())
-    achieved = total / (kernel_ms * 1e-3) / 1e12
-    # what the matrix cores executed for the inverse square root: per domain
-    # one product at the first step, three at each later one but the last
-    # (two); in FP32 mode each product of symmetric iterates runs on ten of
-    # its sixteen 16 x 16 tiles (three to waves 0 and 1, two to waves 2 and 3)
+    fl_all = algorithmic_flops(w.m, np.diff(g["obs_off"]), np.diff(g["own_off"]))
+    # achieved in FP64-equivalent TFLOP/s: the FP32 matrix-core work counted
+    # at half weight (its peak is twice the FP64 one), so achieved / 78.6 is
+    # exactly sum(T_lb) / t_kernel
+    fp64_equiv = fl["evd_fp64"] + 0.5 * (fl["gram_fp32"] + fl["update_fp32"])
+    achieved = fp64_equiv / (kernel_ms * 1e-3) / 1e12
+    tr_ms = trace_kernel_ms()
     steps = (f.status()[1] >> 8) & 255
-    products = np.maximum(3 * steps.astype(np.int64) - 3, 1)
-    ns_flops = float(products.sum()) * 2.0 * 64 ** 3 * 10 / 16
-    ns_tflops = ns_flops / (kernel_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
-            "kernel": "k_analysis<float,true,NS64>", "kernel_ms": round(kernel_ms, 4),
-            "flops_per_launch": total, "flops_breakdown": fl,
-            "newton_schulz": {"steps_mean": round(float(steps.mean()), 3),
-                              "fp64_mfma_flops_per_launch": ns_flops,
-                              "achieved_tflops": round(ns_tflops, 3),
-                              "frac_of_fp64_mfma_peak": round(ns_tflops / FP64_PEAK_TFLOPS, 4)}}
+            "kernel": f"k_analysis<float,true,{transform_name(B, spec.transform)}>",
+            "kernel_ms_events": round(kernel_ms, 4),
+            "kernel_ms_trace": None if tr_ms is None else round(tr_ms, 4),
+            "frac_trace": None if tr_ms is None else round(t_lb / (tr_ms * 1e-3), 4),
+            "frac_frame": round(t_lb / (ms * 1e-3), 4),
+            "t_lb_us": round(t_lb * 1e6, 3),
+            "counted_flops": fl, "not_counted_flops": fl_all["not_counted"],
+            "achieved_note": "FP64-equivalent: EVD 9m^3/domain at the FP64 peak plus Gram and "
+                             "update at half weight (FP32 matrix-core peak 157.3 = 2 x 78.6)",
+            "transform_steps_mean": round(float(steps.mean()), 3)}
 
-    # batched throughput: several copies of the workload in one launch
-    copies = None
-    if args.copies > 1:
-        fc = B.Letkf([spec] * args.copies)
-        yc = y[:, :].repeat(1, args.copies)
-        msc = time_steps(fc, yc, min(K, 200), W)
-        copies = {"instances": args.copies, "ms_per_step": round(msc, 4),
-                  "local_analyses_per_s": round(args.copies * n_dom * 1000.0 / msc, 1),
-                  "frac_of_fp64_peak": round(args.copies * total / (msc * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
-        fc.close()
+    # batched throughput: copies of the workload in one launch (per-domain
+    # cost does not depend on the telescope, so copies are the batch axis)
+    batched = []
+    for nc in ([int(c) for c in args.copies.split(",") if c] if args.copies else []):
+        batched.append(batched_line(B, spec, y, min(K, 100), W, nc))
+
+    others = other_workloads(B, wl, max(20, min(K, 100)), W) if args.other_workloads else None
 
     transforms = transform_variants(B, spec, y, K, W)
     loop = closed_loop_line(B, spec, wl, w, y, truth, ij, K, W)
     kfref = kf_reference_line(B, wl)
     models = model_variants(B, spec, wl, w, y, truth, ij, K, W)
-
-    others = other_workloads(B, wl, 100, 20) if args.other_workloads else None
 
     grad = None
     if args.grad_frames > 0:
@@ -513,15 +690,16 @@ def main():
         "warmup": W, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "80x80 SH, 28% obscuration, m=64, 4x4-subaperture domains, halo 1: "
-                               "332 local analyses per frame in one graph-replayed launch",
+                               f"{n_dom} local analyses per frame in one launch ({schedule_label(sched)}), "
+                               f"transform {transform_name(B, spec.transform)}",
                    "n_slopes": int(f.sizes["n_slopes"]), "n_nodes": int(f.sizes["n_nodes"]),
-                   "domains": int(n_dom), "schedule": {"graph": sched[0], "xcd_order": sched[1]}},
+                   "domains": int(n_dom), "schedule": {"graph": bool(sched[0]), "order": int(sched[1])}},
         "local_analyses_per_s": round(fps * n_dom, 1),
         "plain": {"ms_per_step": round(plain_ms, 4), "frames_per_s": round(1000.0 / plain_ms, 2),
                   "launches_per_step": int(n_dom)},
         "step_ms_p50": round(float(np.percentile(per, 50)), 4),
         "step_ms_p99": round(float(np.percentile(per, 99)), 4),
-        "batched_copies": copies,
+        "batched_copies": batched,
         "transforms": transforms,
         "closed_loop": loop,
         "kf_reference": kfref,

@@ -247,10 +247,14 @@ int letkf_query(letkf_handle *h, int32_t instance, letkf_sizes *out);
 int letkf_plan(const letkf_config *cfg, letkf_sizes *sizes, int32_t *node_ij, int32_t *owner,
                int32_t *obs_off, int32_t *obs_idx, int32_t *own_off, int32_t *own_idx);
 
-/* Integer maps of one instance (host buffers, any may be NULL):
+/* Integer maps of one instance (host buffers, any may be NULL), following the
+ * partition of Sec. 4.1 (the pupil cut into local domains, each with the
+ * observation region that surrounds it) on the Fried geometry of App. B:
  * node_ij[2n] grid (row, column) of each node; owner[n] domain of each node;
  * obs_off[nd+1] / obs_idx[obs_total] the local slope list of each domain
- * (global slope numbers); own_off[nd+1] / own_idx[n] its owned nodes. */
+ * (global slope numbers, the rows of the local observation operator of
+ * Sec. 4.2); own_off[nd+1] / own_idx[n] its owned nodes.  Bit-exact with
+ * letkf_plan.  LETKF_E_INVAL for a bad handle or instance. */
 int letkf_geometry(letkf_handle *h, int32_t instance, int32_t *node_ij, int32_t *owner,
                    int32_t *obs_off, int32_t *obs_idx, int32_t *own_off, int32_t *own_idx);
 
@@ -260,19 +264,34 @@ int letkf_geometry(letkf_handle *h, int32_t instance, int32_t *node_ij, int32_t 
 int letkf_forecast(letkf_handle *h, const void *V_dev, void *stream);
 
 /* Analysis of X_b with the slopes y_dev (all instances concatenated), all
- * domains of all instances in one launch; the owned rows form X_a. */
+ * domains of all instances in one launch; the owned rows form X_a.  Per
+ * domain this is the local update of Sec. 4.2 (the ensemble-transform form of
+ * Sec. 3.1.1 restricted to the domain's observation region: A~, w, W as in
+ * the preamble), then the concatenation of the owned rows and, when enabled,
+ * the differential-piston step of Sec. 4.4.  y_dev: device slopes, element
+ * type of the handle.  LETKF_E_STATE before a letkf_forecast; per-domain
+ * failures (non-finite slopes, no convergence) keep that domain's forecast
+ * and are reported by letkf_status, not by the return code. */
 int letkf_analyse(letkf_handle *h, const void *y_dev, void *stream);
 
-/* One whole frame (forecast fused into the analysis: each domain forms its own
- * node patch of X_b), replayed from a HIP graph built on the first call. */
+/* One whole frame: the member prediction of Sec. 3.1.2 (X_b = a X_a + V)
+ * fused into the local analyses of Sec. 4.2 (each domain forms its own node
+ * patch of X_b), the concatenation and the Sec. 4.4 piston step, replayed
+ * from a HIP graph built on the first call (or launched directly, per
+ * letkf_set_schedule).  V_dev: device ensemble-layout noise, or NULL to draw
+ * it from the noise bank; y_dev: device slopes.  Advances the frame counter.
+ * Errors as letkf_analyse. */
 int letkf_step(letkf_handle *h, const void *V_dev, const void *y_dev, void *stream);
 
 /* The same frame without batching: one launch per domain, no graph. */
 int letkf_step_plain(letkf_handle *h, const void *V_dev, const void *y_dev, void *stream);
 
 /* Copy the analysis ensemble / its member mean ([node] per instance) out, or
- * set the ensemble (restart, tests).  on_device != 0: dst/src are device
- * pointers on the handle's device; else host pointers.  Synchronous. */
+ * set the ensemble (restart, tests).  The member mean is the analysis estimate
+ * x^ of Sec. 3.1 (with the symmetric square-root transform the members
+ * average to it exactly).  on_device != 0: dst/src are device pointers on the
+ * handle's device; else host pointers.  Synchronous.  LETKF_E_INVAL for NULL
+ * pointers, LETKF_E_DEVICE when a copy fails. */
 int letkf_get_ensemble(letkf_handle *h, void *dst, int on_device);
 int letkf_set_ensemble(letkf_handle *h, const void *src, int on_device);
 int letkf_get_forecast(letkf_handle *h, void *dst, int on_device);
@@ -314,17 +333,41 @@ int letkf_set_params(letkf_handle *h, int32_t instance, double rho, double r_sca
  * instance: phase_dev [node] -> slopes_dev [slope], instances concatenated. */
 int letkf_slopes(letkf_handle *h, const void *phase_dev, void *slopes_dev, void *stream);
 
-/* Last-call timing knobs picked by letkf_autotune (or set by hand):
- * use_graph (0/1) for letkf_step and xcd_order (0/1) for the block to work
- * item mapping. */
-int letkf_set_schedule(letkf_handle *h, int32_t use_graph, int32_t xcd_order);
-int letkf_get_schedule(letkf_handle *h, int32_t *use_graph, int32_t *xcd_order);
+/* Order in which the workgroups of the analysis launch take the (instance,
+ * domain) work items (Sec. 4.1: the domains are independent, so any order
+ * gives the same result, bit for bit; only the time changes).
+ *   ROW         item = workgroup index.
+ *   XCD         the eight XCDs each take a contiguous run of items (the
+ *               dispatcher deals workgroups to the XCDs round-robin), so the
+ *               overlapping observation regions of neighbouring domains are
+ *               read through one L2.
+ *   XCD_PAIRED  as XCD, and within each run the items of the second dispatch
+ *               round (the workgroups that share a CU with one of the first
+ *               round) are the cheapest ones, each paired with the costliest
+ *               of them; the items that run alone on a CU are the costliest.
+ *               Cost of an item: its transform (m^3), Gram (m^2 p_l) and
+ *               staging (m x node patch) work. */
+#define LETKF_ORDER_ROW 0
+#define LETKF_ORDER_XCD 1
+#define LETKF_ORDER_XCD_PAIRED 2
 
-/* Time the step under each schedule on `stream` (frames frames each, using
- * the given V/y buffers) and keep the fastest; results are cached in
- * cache_path (text, one line per shape) when cache_path != NULL.  The filter
- * state (ensemble, frame counter, AR(2) and command histories, refitted
- * model) is restored afterwards. */
+/* Timing knobs picked by letkf_autotune (or set by hand): use_graph (0/1)
+ * for letkf_step, and the item order (LETKF_ORDER_*).  No knob changes a
+ * result: every work item computes the same values under any schedule.
+ * LETKF_E_INVAL for an unknown order. */
+int letkf_set_schedule(letkf_handle *h, int32_t use_graph, int32_t order);
+int letkf_get_schedule(letkf_handle *h, int32_t *use_graph, int32_t *order);
+
+/* Time letkf_step under every schedule (graph or direct launches x the three
+ * item orders) on `stream`, `frames` frames each after one warm-up frame,
+ * using the caller's V/y buffers (V_dev NULL: the noise bank), and keep the
+ * fastest.  With cache_path != NULL the choice is read from, or appended to,
+ * a text file with one line per configuration key (device, precision, work
+ * items, m, node patch, observation count, transform, localisation, model,
+ * gather mode, AR(2) and refit flags).  The filter state (ensemble, frame
+ * counter, AR(2) and command histories, refitted model and its sums) is
+ * restored afterwards, on error paths too.  LETKF_E_INVAL for frames < 1 or
+ * a NULL y_dev. */
 int letkf_autotune(letkf_handle *h, const void *V_dev, const void *y_dev, int32_t frames,
                    const char *cache_path, void *stream);
 

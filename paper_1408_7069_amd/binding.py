@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -31,6 +32,7 @@ TRANSFORM_NS64, TRANSFORM_NS32, TRANSFORM_EVD = 0, 1, 2
 MODEL_PHASE, MODEL_CLOSED_LOOP = 0, 1
 GATHER_CONCAT, GATHER_BLEND = 0, 1
 LOCALISATION_DOMAIN, LOCALISATION_COVARIANCE = 0, 1
+ORDER_ROW, ORDER_XCD, ORDER_XCD_PAIRED = 0, 1, 2
 
 
 class Config(C.Structure):
@@ -254,6 +256,9 @@ class Letkf:
         h = C.c_void_p()
         _check(lib.letkf_create(arr, len(specs), device, C.byref(h)), "letkf_create")
         self._h = h
+        # the destroy function is bound now, so that a handle still alive at
+        # interpreter exit is destroyed even after the module globals are gone
+        self._fin = weakref.finalize(self, lib.letkf_destroy, h)
         self.device = device
         self.specs = specs
         self.fp64 = specs[0].precision == FP64
@@ -261,12 +266,10 @@ class Letkf:
         self.inst_sizes = [self.query(i) for i in range(len(specs))]
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib.letkf_destroy(self._h)
-            self._h = None
-
-    def __del__(self):
-        self.close()
+        fin = getattr(self, "_fin", None)
+        if fin is not None:
+            fin()          # letkf_destroy, at most once
+        self._h = None
 
     # -- sizes and maps
     def query(self, instance: int = -1) -> dict:
@@ -381,13 +384,14 @@ class Letkf:
         _check(lib.letkf_slopes(self._h, _ptr(phase), _ptr(out), _stream(stream)), "letkf_slopes")
         return out
 
-    def set_schedule(self, use_graph: bool, xcd_order: bool):
-        _check(lib.letkf_set_schedule(self._h, int(use_graph), int(xcd_order)), "letkf_set_schedule")
+    def set_schedule(self, use_graph: bool, order: int):
+        """use_graph for letkf_step; order: ORDER_ROW, ORDER_XCD (True) or ORDER_XCD_PAIRED."""
+        _check(lib.letkf_set_schedule(self._h, int(use_graph), int(order)), "letkf_set_schedule")
 
     def get_schedule(self):
         g, x = C.c_int32(), C.c_int32()
         _check(lib.letkf_get_schedule(self._h, C.byref(g), C.byref(x)), "letkf_get_schedule")
-        return bool(g.value), bool(x.value)
+        return bool(g.value), int(x.value)
 
     def autotune(self, y, V=None, frames: int = 20, cache_path: str | None = None, stream=None):
         _check(lib.letkf_autotune(self._h, _ptr(V), _ptr(y), frames,

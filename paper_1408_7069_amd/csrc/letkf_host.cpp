@@ -146,6 +146,7 @@ template <typename T> struct AnaArgsHost {
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
   int32_t off_clb, off_clr;
   int32_t round_items;
+  const int32_t *order;  // grid slot -> work item (-1: none), or NULL
 };
 
 // Mirror of PistonArgs<T>.
@@ -238,7 +239,8 @@ struct letkf_handle {
   int cur = 0;
   bool have_xb = false;
   // graph replay of the fused frame, one per ping-pong parity
-  int use_graph = 1, xcd_order = 1;
+  int use_graph = 1, xcd_order = 1;  // xcd_order: the item order, LETKF_ORDER_*
+  int32_t *d_order = nullptr;         // slot -> item table of LETKF_ORDER_XCD_PAIRED
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipGraphNode_t gnode[2] = {nullptr, nullptr};
@@ -609,7 +611,7 @@ void free_handle(letkf_handle *h) {
                   h->d_xbbar, h->d_dbar, h->d_theta, h->d_owner_item, h->d_minv_off, h->d_minv,
                   h->d_prhs, h->d_pi, h->d_xmean, h->d_u1, h->d_u2, h->d_xprev,
                   h->d_refit, h->d_rpart, h->d_stage, h->d_smean, h->d_boff, h->d_bent,
-                  h->d_bitem, h->d_bw, h->d_pterm_off, h->d_pterms, h->d_pitem};
+                  h->d_bitem, h->d_bw, h->d_pterm_off, h->d_pterms, h->d_pitem, h->d_order};
   for (void *p : ptrs)
     if (p) hipFree(p);
   for (auto &e : h->tev) {
@@ -640,7 +642,8 @@ AnaArgsHost<T> make_args(letkf_handle *h, bool fused, const void *V, const void 
   A.items = h->d_items;
   A.item_base = 0;
   A.n_items = (int32_t)h->items.size();
-  A.xcd_order = h->xcd_order;
+  A.xcd_order = h->xcd_order != LETKF_ORDER_ROW ? 1 : 0;
+  A.order = h->xcd_order == LETKF_ORDER_XCD_PAIRED ? h->d_order : nullptr;
   A.noise_bank = (fused && V == nullptr) ? 1 : 0;
   A.patch_node = h->d_patch;
   A.obs_corner = h->d_obs_corner;
@@ -747,9 +750,46 @@ int launch_frame_tail(letkf_handle *h, const void *y, void *x, const void *x_pre
   return LETKF_OK;
 }
 
+// Slot -> item table of LETKF_ORDER_XCD_PAIRED.  Slot b goes to XCD b % 8
+// as its (b / 8)-th workgroup; XCD x takes the contiguous run of items
+// [x per, (x + 1) per) as in LETKF_ORDER_XCD.  Within a run of n items and R
+// CUs per XCD (two workgroups fit a CU): for R < n <= 2R the workgroups
+// R .. n - 1 share a CU with 0 .. n - R - 1, so the 2R - n costliest items take
+// the CUs they hold alone and the others are paired costliest with cheapest;
+// for longer runs the items go in order of falling cost (the dispatcher then
+// hands the next item to the first CU that frees up, longest first).
+std::vector<int32_t> paired_order(const letkf_handle *h) {
+  const int n = (int)h->items.size(), grid = 8 * ((n + 7) / 8), per = grid / 8, R = h->round_items;
+  std::vector<int32_t> tab((size_t)std::max(grid, 1), -1);
+  for (int x = 0; x < 8; ++x) {
+    std::vector<std::pair<double, int>> run;
+    for (int i = x * per; i < std::min(n, (x + 1) * per); ++i) {
+      const DomItem &it = h->items[i];
+      const double m = h->desc[it.inst].m / 64.0;
+      const double cost = 100.0 * m * m * m + 20.0 * m * m * (2.0 * it.n_obs / 72.0) + 15.0 * m * it.n_patch / 40.0;
+      run.push_back({-cost, i});
+    }
+    std::stable_sort(run.begin(), run.end());  // costliest first
+    const int nr = (int)run.size();
+    std::vector<int> slot_item(per, -1);
+    if (nr > R && nr <= 2 * R) {
+      const int n2 = nr - R;  // CUs holding two
+      for (int j = n2; j < R; ++j) slot_item[j] = run[j - n2].second;
+      for (int j = 0; j < n2; ++j) {
+        slot_item[j] = run[R - n2 + j].second;
+        slot_item[j + R] = run[nr - 1 - j].second;
+      }
+    } else {
+      for (int j = 0; j < nr; ++j) slot_item[j] = run[j].second;
+    }
+    for (int j = 0; j < per; ++j) tab[(size_t)8 * j + x] = slot_item[j];
+  }
+  return tab;
+}
+
 int grid_for(const letkf_handle *h) {
   const int n = (int)h->items.size();
-  return h->xcd_order ? 8 * ((n + 7) / 8) : n;
+  return h->xcd_order != LETKF_ORDER_ROW ? 8 * ((n + 7) / 8) : n;
 }
 
 int launch_analysis(letkf_handle *h, bool fused, const void *V, const void *y, int xa_in, int xa_out,
@@ -1391,7 +1431,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
       (rc = to_device(&h->d_prhs, std::vector<double>(std::max<size_t>(h->items.size(), 1), 0.0))) ||
       (rc = to_device(&h->d_pi, std::vector<double>(std::max<size_t>(h->items.size(), 1), 0.0))) ||
       (rc = to_device(&h->d_pterm_off, pterm_off)) || (rc = to_device(&h->d_pterms, pterms)) ||
-      (rc = to_device(&h->d_pitem, pitem)) ||
+      (rc = to_device(&h->d_pitem, pitem)) || (rc = to_device(&h->d_order, paired_order(h))) ||
       (h->any_blend && ((rc = to_device(&h->d_boff, boff)) || (rc = to_device(&h->d_bent, bent)) ||
                         (rc = to_device(&h->d_bitem, bitem)) || (rc = to_device(&h->d_bw, bw)) ||
                         (rc = to_device(&h->d_smean, std::vector<double>(patch.size(), 0.0)))))) {
@@ -1605,11 +1645,13 @@ int letkf_step_plain(letkf_handle *h, const void *V_dev, const void *y_dev, void
       auto A = make_args<double>(h, true, V_dev, y_dev, h->cur, 1 - h->cur);
       A.item_base = i;
       A.xcd_order = 0;
+      A.order = nullptr;
       HIPCHK(letkf_launch_analysis(&A, 1, 1, h->transform, 1, h->lds, s));
     } else {
       auto A = make_args<float>(h, true, V_dev, y_dev, h->cur, 1 - h->cur);
       A.item_base = i;
       A.xcd_order = 0;
+      A.order = nullptr;
       HIPCHK(letkf_launch_analysis(&A, 0, 1, h->transform, 1, h->lds, s));
     }
   }
@@ -1756,9 +1798,10 @@ int letkf_slopes(letkf_handle *h, const void *phase_dev, void *slopes_dev, void 
   return LETKF_OK;
 }
 
-int letkf_set_schedule(letkf_handle *h, int32_t use_graph, int32_t xcd_order) {
+int letkf_set_schedule(letkf_handle *h, int32_t use_graph, int32_t order) {
   if (!h) return fail(LETKF_E_INVAL, "NULL handle");
-  if (xcd_order != h->xcd_order) {
+  if (order < LETKF_ORDER_ROW || order > LETKF_ORDER_XCD_PAIRED) return fail(LETKF_E_INVAL, "unknown item order");
+  if (order != h->xcd_order) {
     for (int p = 0; p < 2; ++p) {
       if (h->gexec[p]) hipGraphExecDestroy(h->gexec[p]);
       if (h->graph[p]) hipGraphDestroy(h->graph[p]);
@@ -1768,23 +1811,80 @@ int letkf_set_schedule(letkf_handle *h, int32_t use_graph, int32_t xcd_order) {
     }
   }
   h->use_graph = use_graph ? 1 : 0;
-  h->xcd_order = xcd_order ? 1 : 0;
+  h->xcd_order = order;
   return LETKF_OK;
 }
 
-int letkf_get_schedule(letkf_handle *h, int32_t *use_graph, int32_t *xcd_order) {
+int letkf_get_schedule(letkf_handle *h, int32_t *use_graph, int32_t *order) {
   if (!h) return fail(LETKF_E_INVAL, "NULL handle");
   if (use_graph) *use_graph = h->use_graph;
-  if (xcd_order) *xcd_order = h->xcd_order;
+  if (order) *order = h->xcd_order;
   return LETKF_OK;
 }
+
+extern "C++" {
+namespace {
+// Saves the filter state that tuning frames change and puts it back (and the
+// schedule and the events) when it goes out of scope, whatever the exit path.
+struct TuneGuard {
+  letkf_handle *h;
+  std::vector<std::pair<void *, size_t>> keep;
+  std::vector<std::vector<unsigned char>> saved;
+  int cur0, graph0, order0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool armed = false;
+  explicit TuneGuard(letkf_handle *hh) : h(hh), cur0(hh->cur), graph0(hh->use_graph), order0(hh->xcd_order) {}
+  int save() {
+    const size_t xbytes = (size_t)h->total_x * h->esize, ubytes = (size_t)h->total_nodes * h->esize;
+    keep = {{h->d_xa[h->cur], xbytes}, {h->d_frame, 4}, {h->d_desc, h->n_inst * sizeof(InstDesc)}};
+    if (h->d_xprev) keep.push_back({h->d_xprev, xbytes});
+    if (h->any_loop) {
+      keep.push_back({h->d_u1, ubytes});
+      keep.push_back({h->d_u2, ubytes});
+    }
+    if (h->any_refit) keep.push_back({h->d_refit, h->n_inst * sizeof(RefitState)});
+    saved.assign(keep.size(), {});
+    HIPCHK(hipDeviceSynchronize());
+    for (size_t i = 0; i < keep.size(); ++i) {
+      saved[i].resize(keep[i].second);
+      HIPCHK(hipMemcpy(saved[i].data(), keep[i].first, keep[i].second, hipMemcpyDeviceToHost));
+    }
+    armed = true;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    return LETKF_OK;
+  }
+  ~TuneGuard() {
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (!armed) return;
+    hipDeviceSynchronize();
+    h->cur = cur0;
+    for (size_t i = 0; i < keep.size(); ++i)
+      hipMemcpy(keep[i].first, saved[i].data(), keep[i].second, hipMemcpyHostToDevice);
+    (void)hipGetLastError();
+  }
+};
+}  // namespace
+}  // extern "C++"
 
 int letkf_autotune(letkf_handle *h, const void *V_dev, const void *y_dev, int32_t frames,
                    const char *cache_path, void *stream) {
   if (!h || !y_dev || frames < 1) return fail(LETKF_E_INVAL, "bad argument");
+  int dev_cu = 0;
+  hipDeviceGetAttribute(&dev_cu, hipDeviceAttributeMultiprocessorCount, h->device);
   std::ostringstream key;
-  key << "gfx950 fp" << (h->fp64 ? 64 : 32) << " items " << h->items.size() << " m " << h->max_m
-      << " patch " << h->max_patch << " obs " << h->max_obs_sub;
+  int ar2 = h->any_ar2 ? 1 : 0, refit = h->any_refit ? 1 : 0;
+  const int loc = h->transform == kAnalysisCl ? 1 : 0;  // the transform field names CL's own kernel
+  int model = 0, gather = 0;
+  for (const auto &d : h->desc) {
+    model |= d.model;
+    gather |= d.blend;
+  }
+  key << "gfx950 cu " << dev_cu << " fp" << (h->fp64 ? 64 : 32) << " items " << h->items.size() << " m "
+      << h->max_m << " patch " << h->max_patch << " obs " << h->max_obs_sub << " transform " << h->transform
+      << " localisation " << loc << " model " << model << " gather " << gather << " ar2 " << ar2
+      << " refit " << refit;
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
@@ -1792,64 +1892,41 @@ int letkf_autotune(letkf_handle *h, const void *V_dev, const void *y_dev, int32_
       const size_t bar = line.find(" | ");
       if (bar != std::string::npos && line.substr(0, bar) == key.str()) {
         int g = 1, x = 1;
-        if (sscanf(line.c_str() + bar + 3, "graph %d xcd %d", &g, &x) == 2)
+        if (sscanf(line.c_str() + bar + 3, "graph %d order %d", &g, &x) == 2)
           return letkf_set_schedule(h, g, x);
       }
     }
   }
   hipStream_t s = (hipStream_t)stream;
   hipSetDevice(h->device);
-  // keep the state: tuning frames must not change it (ensemble, frame
-  // counter, AR(2) history, command history, refitted model and its sums)
-  const size_t xbytes = (size_t)h->total_x * h->esize, ubytes = (size_t)h->total_nodes * h->esize;
-  std::vector<std::pair<void *, size_t>> keep = {{h->d_xa[h->cur], xbytes}, {h->d_frame, 4},
-                                                 {h->d_desc, h->n_inst * sizeof(InstDesc)}};
-  if (h->d_xprev) keep.push_back({h->d_xprev, xbytes});
-  if (h->any_loop) {
-    keep.push_back({h->d_u1, ubytes});
-    keep.push_back({h->d_u2, ubytes});
-  }
-  if (h->any_refit) keep.push_back({h->d_refit, h->n_inst * sizeof(RefitState)});
-  std::vector<std::vector<unsigned char>> saved(keep.size());
-  HIPCHK(hipDeviceSynchronize());
-  for (size_t i = 0; i < keep.size(); ++i) {
-    saved[i].resize(keep[i].second);
-    HIPCHK(hipMemcpy(saved[i].data(), keep[i].first, keep[i].second, hipMemcpyDeviceToHost));
-  }
-  const int cur0 = h->cur;
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  // tuning frames must not change the filter state: the guard restores it on
+  // every return below
+  TuneGuard guard(h);
+  int rc = guard.save();
+  if (rc) return rc;
   float best = 1e30f;
-  int bg = 1, bx = 1;
+  int bg = 1, bx = LETKF_ORDER_XCD;
   for (int g = 0; g < 2; ++g)
-    for (int x = 0; x < 2; ++x) {
-      letkf_set_schedule(h, g, x);
-      int rc = letkf_step(h, V_dev, y_dev, stream);  // warm-up (and graph build)
-      if (rc) return rc;
-      HIPCHK(hipEventRecord(e0, s));
+    for (int x = LETKF_ORDER_ROW; x <= LETKF_ORDER_XCD_PAIRED; ++x) {
+      if ((rc = letkf_set_schedule(h, g, x))) return rc;
+      if ((rc = letkf_step(h, V_dev, y_dev, stream))) return rc;  // warm-up (and graph build)
+      HIPCHK(hipEventRecord(guard.e0, s));
       for (int f = 0; f < frames; ++f)
         if ((rc = letkf_step(h, V_dev, y_dev, stream))) return rc;
-      HIPCHK(hipEventRecord(e1, s));
-      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipEventRecord(guard.e1, s));
+      HIPCHK(hipEventSynchronize(guard.e1));
       float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      HIPCHK(hipEventElapsedTime(&ms, guard.e0, guard.e1));
       if (ms < best) {
         best = ms;
         bg = g;
         bx = x;
       }
     }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  HIPCHK(hipDeviceSynchronize());
-  h->cur = cur0;
-  for (size_t i = 0; i < keep.size(); ++i)
-    HIPCHK(hipMemcpy(keep[i].first, saved[i].data(), keep[i].second, hipMemcpyHostToDevice));
-  letkf_set_schedule(h, bg, bx);
+  if ((rc = letkf_set_schedule(h, bg, bx))) return rc;
   if (cache_path) {
     std::ofstream o(cache_path, std::ios::app);
-    o << key.str() << " | graph " << bg << " xcd " << bx << " ms_per_frame " << best / frames << "\n";
+    o << key.str() << " | graph " << bg << " order " << bx << " ms_per_frame " << best / frames << "\n";
   }
   return LETKF_OK;
 }
@@ -1919,6 +1996,7 @@ static AdjArgsHost<T> make_adj_args(letkf_handle *h, const void *xa_prev, const 
   D.F.x_out = nullptr;
   D.F.x_mean = nullptr;
   D.F.xcd_order = 0;
+  D.F.order = nullptr;
   // the adjoint goes through the eigenvectors themselves: converge them further
   // than the forward's transform needs
   D.F.jtol = h->fp64 ? h->jtol : std::min(h->jtol, 1e-6);

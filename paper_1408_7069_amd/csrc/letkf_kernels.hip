@@ -1072,6 +1072,7 @@ template <typename T> struct AnaArgs {
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
   int32_t off_clb, off_clr;  // covariance localisation: B and the solve's columns
   int32_t round_items;        // work items of one dispatch round per XCD (CUs per XCD)
+  const int32_t *order;       // grid slot -> work item (-1: none), or NULL for the fixed orders
 };
 
 __device__ inline int xcd_item(int b, int grid) {
@@ -1373,9 +1374,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int q = tid >> 6, lane = tid & 63;
-  int item = A.xcd_order ? xcd_item((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  int item = A.order ? A.order[blockIdx.x]
+                     : (A.xcd_order ? xcd_item((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x);
   item += A.item_base;
-  if (item >= A.n_items) return;
+  if (item < 0 || item >= A.n_items) return;
   const DomItem it = A.items[item];
   const InstDesc in = A.inst[it.inst];
   const int m = in.m;
@@ -1537,7 +1539,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 // (c = 0: no taper); with the whitened local slope operator Dt (rows scaled
 // by 1 / sqrt(s r)) and the whitened innovation dd,
 //   B = P_loc Dt^T (patch x p),  S = Dt B + I (p x p, FP64 Cholesky),
-//   [K^T | v] = S^{-1} [B_own^T | dd],
+//   K^T = S^{-1} B_own^T,
 //   x_a = x_b + K dd,  X'_a = sqrt(rho) (X'_own - K Dt X'_P / 2)
 // (the deterministic EnKF update of the anomalies), written to the owned
 // rows.  LDS: the patch rows, then one area for X'_P^T, P_loc and S in turn
@@ -1639,9 +1641,10 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int q = tid >> 6, lane = tid & 63;
-  int item = A.xcd_order ? xcd_item((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  int item = A.order ? A.order[blockIdx.x]
+                     : (A.xcd_order ? xcd_item((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x);
   item += A.item_base;
-  if (item >= A.n_items) return;
+  if (item < 0 || item >= A.n_items) return;
   const DomItem it = A.items[item];
   const InstDesc in = A.inst[it.inst];
   const int m = in.m, np = it.n_patch, nown = it.n_own, nobs = it.n_obs, p = 2 * nobs, ldp = p + 1;
@@ -1728,9 +1731,7 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   }
   __syncthreads();
   // the solve's columns: B's owned rows (patch rows 0..n_own - 1) as they
-  // stand, and dd in row n_own (a stencil row that S no longer needs, or the
-  // spare row after the patch)
-  for (int s = tid; s < p; s += kThreads) Bm[nown * ldp + s] = dd[s];
+  // stand
 
   // ---- 6. Cholesky S = L L^T in place (packed lower triangle), by panels
   // of kClPanel columns: wave 0 factors a panel in registers (rows k0 + lane
@@ -1800,9 +1801,9 @@ __global__ __launch_bounds__(kThreads) void k_analysis_cl(const AnaArgs<T> A) {
   }
   bad = bad || __syncthreads_or(fail);
 
-  // ---- 7. [K^T | v] = S^{-1} [B_own^T | dd] in place: wave q takes the
-  // columns q, q + 4, ..., up to eight at a time (cl_solve_columns) ----
-  const int nc = nown + 1;
+  // ---- 7. K^T = S^{-1} B_own^T in place: wave q takes the columns q,
+  // q + 4, ..., up to eight at a time (cl_solve_columns) ----
+  const int nc = nown;
   if (!bad)
     for (int cb = q; cb < nc; cb += 4 * 8) {
       const int nu = min(8, (nc - cb + 3) >> 2);  // this wave's columns in the chunk

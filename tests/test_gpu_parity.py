@@ -181,7 +181,8 @@ def test_plain_graph_and_direct_launches_agree_bitwise():
     case = Case(24, 0.2, 4, 1, 64, seed=14)
     bb = B()
     outs = []
-    for mode in ["plain", (True, True), (True, False), (False, True), (False, False)]:
+    modes = ["plain"] + [(g, o) for g in (True, False) for o in (bb.ORDER_ROW, bb.ORDER_XCD, bb.ORDER_XCD_PAIRED)]
+    for mode in modes:
         f = bb.Letkf([case.spec(bb)])
         rng = np.random.default_rng(0)
         for k in range(2):
@@ -195,6 +196,53 @@ def test_plain_graph_and_direct_launches_agree_bitwise():
         outs.append(f.get_ensemble().cpu().numpy())
     for o in outs[1:]:
         assert np.array_equal(outs[0], o)
+
+
+@pytest.mark.parametrize("copies", [1, 2])
+def test_every_schedule_gives_the_same_bits_at_full_size(copies):
+    # 80x80 (332 items: the paired order's two-round path) and two copies in
+    # one launch (664 items: its falling-cost path): every (graph, order)
+    # point the autotuner can choose computes the same ensemble bit for bit
+    case = Case(80, 0.28, 4, 1, 64, seed=17)
+    bb = B()
+    ys = [case.slopes(case.truth()) for _ in range(2)]
+    outs = []
+    for g in (True, False):
+        for o in (bb.ORDER_ROW, bb.ORDER_XCD, bb.ORDER_XCD_PAIRED):
+            f = bb.Letkf([case.spec(bb)] * copies)
+            f.set_schedule(g, o)
+            assert f.get_schedule() == (g, o)
+            for y in ys:
+                f.step(_t(np.tile(y, copies)), V=None)
+            torch.cuda.synchronize()
+            outs.append(f.get_ensemble().cpu().numpy())
+            f.close()
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
+def test_autotune_choice_is_cached_and_bitwise_neutral(tmp_path):
+    case = Case(40, 0.14, 4, 1, 48, seed=18)
+    bb = B()
+    ys = [_t(case.slopes(case.truth())) for _ in range(3)]
+    cache = str(tmp_path / "tune.txt")
+    f = bb.Letkf([case.spec(bb)])
+    sched = f.autotune(ys[0], frames=4, cache_path=cache)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and f"graph {int(sched[0])} order {sched[1]}" in lines[0]
+    assert " transform 0 " in lines[0] and " localisation 0 " in lines[0]
+    assert f.get_frame() == 0 and np.all(f.get_ensemble().cpu().numpy() == 0)   # state restored
+    g = bb.Letkf([case.spec(bb)])
+    assert g.autotune(ys[0], frames=4, cache_path=cache) == sched            # read from the cache
+    assert len(open(cache).read().splitlines()) == 1
+    g.set_schedule(True, bb.ORDER_XCD)                                      # the default
+    for y in ys:
+        f.step(y, V=None)
+        g.step(y, V=None)
+    torch.cuda.synchronize()
+    assert np.array_equal(f.get_ensemble().cpu().numpy(), g.get_ensemble().cpu().numpy())
+    with pytest.raises(bb.LetkfError):
+        f.set_schedule(True, 3)
 
 
 def test_restart_continues_bit_identically():

@@ -46,8 +46,6 @@ def _truth_seq(case, a_true, T):
 @pytest.mark.parametrize("fp64,tol", [(True, 1e-10), (False, 1e-4)])
 @pytest.mark.parametrize("model", [0, 1])
 def test_refit_frames(path, fp64, tol, model):
-    if model == 1 and path in ("direct", "plain"):
-        pytest.skip("the closed loop's launch paths are covered by the graph and split cases")
     a0, f_forget = 0.95, 0.9
     case = Case(12, 0.28, 4, 1, 32, seed=61, fp64=fp64, piston=True, a=a0, taper_c=1.5)
     bb = B()
