@@ -433,6 +433,23 @@ int letkf_residual_variance_adjoint(letkf_handle *h, const void *xa_dev, const v
 int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, uint32_t frame,
                   const void *y_dev, void *xbar_dev, double *theta_bar_dev, void *stream);
 
+/* letkf_adjoint for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels, arguments, results (bit for bit) and errors, but the
+ * adjoint's per-call buffers (node and slope adjoint slots, per-item partials,
+ * which letkf_adjoint allocates on its first call) are taken from a fixed
+ * device scratch array of the library, 16 MiB on each device it runs on,
+ * held until the process ends.  It calls no hipMalloc or hipFree.  The
+ * handle's own buffers (allocated by letkf_create) are used as by
+ * letkf_adjoint.  LETKF_E_INVAL, with a message naming the size, when the
+ * handle needs more scratch than that (an 80x80, m = 64 instance needs
+ * 6.7 MB in FP32 and 13.3 MB in FP64).  Every call on a device shares that
+ * device's scratch and leaves its last contents there (every entry a call
+ * reads is written by the same call first): calls that overlap on one
+ * device, from any handle, stream or thread, race; order them. */
+int letkf_adjoint_noalloc(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, uint32_t frame,
+                          const void *y_dev, void *xbar_dev, double *theta_bar_dev, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -116,6 +116,7 @@ _SIGS = {
     "letkf_residual_variance": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "letkf_residual_variance_adjoint": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "letkf_adjoint": (C.c_int, [_P, _P, _P, C.c_uint32, _P, _P, _P, _P]),
+    "letkf_adjoint_noalloc": (C.c_int, [_P, _P, _P, C.c_uint32, _P, _P, _P, _P]),
     "letkf_set_timing": (C.c_int, [_P, C.c_int32]),
     "letkf_analysis_times": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int32, _I32P]),
 }
@@ -449,6 +450,17 @@ class Letkf:
         self._check_f64(theta_bar, 3 * self.sizes["n_instances"], "theta_bar")
         _check(lib.letkf_adjoint(self._h, _ptr(xa_prev), _ptr(V), frame, _ptr(y), _ptr(xbar),
                                  _ptr(theta_bar), _stream(stream)), "letkf_adjoint")
+
+    def adjoint_noalloc(self, xa_prev, y, xbar, theta_bar, frame: int, V=None, stream=None):
+        """letkf_adjoint_noalloc: as adjoint, with the library's fixed device
+        scratch in place of buffers allocated on first use."""
+        self._check_tensor(xa_prev, self.sizes["ensemble_elems"], "xa_prev")
+        self._check_tensor(y, self.sizes["n_slopes"], "y")
+        self._check_tensor(xbar, self.sizes["ensemble_elems"], "xbar")
+        self._check_tensor(V, self.sizes["ensemble_elems"], "V")
+        self._check_f64(theta_bar, 3 * self.sizes["n_instances"], "theta_bar")
+        _check(lib.letkf_adjoint_noalloc(self._h, _ptr(xa_prev), _ptr(V), frame, _ptr(y), _ptr(xbar),
+                                         _ptr(theta_bar), _stream(stream)), "letkf_adjoint_noalloc")
 
 
 def eigh_spd(A, tol: float = 1e-12, max_sweeps: int = 30, stream=None):

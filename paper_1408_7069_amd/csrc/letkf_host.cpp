@@ -99,6 +99,8 @@ extern "C" void letkf_piston_grid(int which, int n_items, int n_inst, int max_no
                                   int *gx, int *gy);
 extern "C" hipError_t letkf_launch_piston(int fp64, int which, const void *args, int gx, int gy,
                                           hipStream_t s);
+extern "C" size_t letkf_noalloc_scratch_bytes(void);
+extern "C" hipError_t letkf_noalloc_scratch(int device, void **ptr);
 extern "C" hipError_t letkf_launch_theta_sum(const int32_t *dom_base, int n_inst, const double *theta,
                                              double *theta_acc, hipStream_t s);
 
@@ -2049,6 +2051,99 @@ int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, u
   return LETKF_OK;
 }
 
+
+// The adjoint's per-call buffers carved from the fixed device scratch, 256-byte
+// aligned: X' adjoint, x_b adjoint, slope slots, innovation slots, per-item
+// partials.  Returns the bytes needed.
+extern "C++" {
+static size_t noalloc_layout(const letkf_handle *h, unsigned char *base, void **xp, double **xb, void **yb,
+                             double **db, double **th) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t T = h->esize, items = std::max<size_t>(h->items.size(), 1);
+  size_t o = 0;
+  const size_t o_xp = o; o += up(std::max<size_t>((size_t)h->total_x * T, 16));
+  const size_t o_xb = o; o += up(std::max<size_t>((size_t)h->total_nodes * 8, 16));
+  const size_t o_yb = o; o += up(std::max<size_t>((size_t)h->total_obs * kLanes * T, 16));
+  const size_t o_db = o; o += up(std::max<size_t>((size_t)h->total_obs * 8, 16));
+  const size_t o_th = o; o += up(items * 4 * 8);
+  if (base) {
+    *xp = base + o_xp;
+    *xb = (double *)(base + o_xb);
+    *yb = base + o_yb;
+    *db = (double *)(base + o_db);
+    *th = (double *)(base + o_th);
+  }
+  return o;
+}
+}  // extern "C++"
+
+int letkf_adjoint_noalloc(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, uint32_t frame,
+                          const void *y_dev, void *xbar_dev, double *theta_bar_dev, void *stream) {
+  if (!h || !xa_prev_dev || !y_dev || !xbar_dev || !theta_bar_dev)
+    return fail(LETKF_E_INVAL, "NULL argument");
+  if (h->any_loop) return fail(LETKF_E_INVAL, "no adjoint for the closed-loop model");
+  if (h->any_ar2) return fail(LETKF_E_INVAL, "no adjoint for the AR(2) model");
+  if (h->any_blend) return fail(LETKF_E_INVAL, "no adjoint for the blend-mode gather");
+  if (h->transform == kAnalysisCl) return fail(LETKF_E_INVAL, "no adjoint for covariance localisation");
+  if (h->any_refit) return fail(LETKF_E_INVAL, "no adjoint with the online refit");
+  if (!h->adj_ok)
+    return fail(LETKF_E_INVAL, "the adjoint needs more LDS per workgroup than the device allows");
+  int rc = check_noise(h, V_dev);
+  if (rc) return rc;
+  const size_t need = noalloc_layout(h, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  if (need > letkf_noalloc_scratch_bytes())
+    return fail(LETKF_E_INVAL, "letkf_adjoint_noalloc: the handle needs " + std::to_string(need) +
+                                   " bytes of adjoint scratch, more than the fixed " +
+                                   std::to_string(letkf_noalloc_scratch_bytes()) + " (use letkf_adjoint)");
+  HIPCHK(hipSetDevice(h->device));
+  void *base = nullptr;
+  HIPCHK(letkf_noalloc_scratch(h->device, &base));
+  void *xp = nullptr, *yb = nullptr;
+  double *xb = nullptr, *db = nullptr, *th = nullptr;
+  noalloc_layout(h, (unsigned char *)base, &xp, &xb, &yb, &db, &th);
+  hipStream_t s = (hipStream_t)stream;
+  const int grid = (int)h->items.size();
+  // the piston step's adjoint first (its per-item buffers belong to the
+  // handle, allocated at create); argument blocks on the stack
+  if (h->any_piston) {
+    for (int which : {3, 1, 4}) {
+      int gx, gy;
+      letkf_piston_grid(which, (int)h->items.size(), h->n_inst, h->max_nodes, h->max_elems, &gx, &gy);
+      if (h->fp64) {
+        auto P = make_piston_args<double>(h, nullptr, xbar_dev);
+        if (sizeof(P) != letkf_piston_args_size(1)) return fail(LETKF_E_DEVICE, "piston argument layout mismatch");
+        HIPCHK(letkf_launch_piston(1, which, &P, gx, gy, s));
+      } else {
+        auto P = make_piston_args<float>(h, nullptr, xbar_dev);
+        if (sizeof(P) != letkf_piston_args_size(0)) return fail(LETKF_E_DEVICE, "piston argument layout mismatch");
+        HIPCHK(letkf_launch_piston(0, which, &P, gx, gy, s));
+      }
+    }
+  }
+  if (h->fp64) {
+    auto D = make_adj_args<double>(h, xa_prev_dev, V_dev, frame, y_dev, xbar_dev);
+    D.xpbar = (double *)xp;
+    D.xbbar = xb;
+    D.ybar = (double *)yb;
+    D.dbar = db;
+    D.theta = th;
+    if (sizeof(D) != letkf_adjoint_args_size(1)) return fail(LETKF_E_DEVICE, "argument layout mismatch");
+    HIPCHK(letkf_launch_adjoint(1, &D, grid, h->adj_lds, s));
+  } else {
+    auto D = make_adj_args<float>(h, xa_prev_dev, V_dev, frame, y_dev, xbar_dev);
+    D.xpbar = (float *)xp;
+    D.xbbar = xb;
+    D.ybar = (float *)yb;
+    D.dbar = db;
+    D.theta = th;
+    if (sizeof(D) != letkf_adjoint_args_size(0)) return fail(LETKF_E_DEVICE, "argument layout mismatch");
+    HIPCHK(letkf_launch_adjoint(0, &D, grid, h->adj_lds, s));
+  }
+  HIPCHK(letkf_launch_adjoint_nodes(h->fp64, h->d_desc, h->n_inst, h->d_node_adj, h->d_slot_off, h->d_slots,
+                                    xp, xb, yb, db, xbar_dev, h->max_nodes, s));
+  HIPCHK(letkf_launch_theta_sum(h->d_dom_base, h->n_inst, th, theta_bar_dev, s));
+  return LETKF_OK;
+}
 
 int letkf_set_timing(letkf_handle *h, int32_t enable) {
   if (!h) return fail(LETKF_E_INVAL, "NULL handle");

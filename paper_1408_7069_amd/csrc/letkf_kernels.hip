@@ -40,6 +40,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "letkf_types.h"
 
 namespace letkf {
@@ -2793,6 +2795,35 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 }
 
 }  // namespace letkf
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of letkf_adjoint_noalloc: the per-call buffers of the
+// adjoint (node and slope adjoint slots, per-item partials) for callers that
+// cannot allocate.  Each device holds its own copy for the life of the
+// process; host code reaches it only through the address that
+// hipGetSymbolAddress gives on that device.
+constexpr size_t kNoallocScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+extern "C" size_t letkf_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
+
+// The device address of `scratch` on the current device (looked up once per
+// device, under a lock).  Returns the HIP error of the lookup.
+#include <mutex>
+extern "C" hipError_t letkf_noalloc_scratch(int device, void **ptr) {
+  static std::mutex mu;
+  static void *addr[64] = {nullptr};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // Launch wrappers called by the host side.
