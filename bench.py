@@ -105,8 +105,10 @@ def trace_kernel_ms():
 
 
 def transform_name(B, t: int) -> str:
-    return {B.TRANSFORM_NS64: "NS64", B.TRANSFORM_NS32: "NS32", B.TRANSFORM_EVD: "EVD"}.get(
-        t, getattr(B, "TRANSFORM_NAMES", {}).get(t, str(t)))
+    for name, attr in TRANSFORMS.items():
+        if getattr(B, attr) == t:
+            return name.upper()
+    return str(t)
 
 
 def schedule_label(sched) -> str:
@@ -143,14 +145,23 @@ def batched_line(B, spec, y, K, W, copies: int) -> dict:
             "frac_frame": round(t_lb / (ms * 1e-3), 4)}
 
 
-def transform_variants(B, spec, y, K, W):
-    """The same frames with the other transforms of the local analyses: the
-    FP64 Jacobi eigendecomposition and the Newton-Schulz iteration with FP32
-    iterates (frame time by graph replay, analysis kernel by HIP events)."""
+TRANSFORMS = {"nsp_mixed": "TRANSFORM_NSP_MIXED", "nsp": "TRANSFORM_NSP", "ns64": "TRANSFORM_NS64",
+              "ns32": "TRANSFORM_NS32", "evd": "TRANSFORM_EVD"}
+TRANSFORM_LABELS = {"nsp_mixed": "P-form Newton-Schulz, FP64 then FP32 steps",
+                    "nsp": "P-form Newton-Schulz, FP64", "ns64": "coupled Newton-Schulz, FP64",
+                    "ns32": "coupled Newton-Schulz, FP32 iterates", "evd": "Jacobi eigendecomposition, FP64"}
+
+
+def transform_variants(B, spec, y, K, W, skip):
+    """The same frames with the other transforms of the local analyses (frame
+    time by graph replay, analysis kernel by HIP events)."""
     import dataclasses
     import torch
     out = {}
-    for name, tr in (("evd_jacobi_fp64", B.TRANSFORM_EVD), ("ns_fp32_iterates", B.TRANSFORM_NS32)):
+    for name, attr in TRANSFORMS.items():
+        if name == skip:
+            continue
+        tr = getattr(B, attr)
         g = B.Letkf([dataclasses.replace(spec, transform=tr)])
         g.set_schedule(True, True)
         ms = time_steps(g, y, K, W)
@@ -163,7 +174,8 @@ def transform_variants(B, spec, y, K, W):
         kt = float(np.mean(g.analysis_times()))
         g.set_timing(False)
         steps = (g.status()[1] >> 8) & 255
-        out[name] = {"ms_per_step": round(ms, 5), "frames_per_s": round(1000.0 / ms, 2),
+        out[name] = {"transform": TRANSFORM_LABELS[name], "ms_per_step": round(ms, 5),
+                     "frames_per_s": round(1000.0 / ms, 2),
                      "kernel_ms": round(kt, 4), "steps_mean": round(float(steps.mean()), 3)}
         g.close()
     return out
@@ -478,7 +490,7 @@ def cpu_baseline(w, bank, seed, truth, sigma_noise, budget_s=10.0, pool_s=8.0):
                               "paper_ms": 0.94, "paper_hardware": "1 core of 2x Intel Xeon E5-2680 v2 (Table 2)"}}
 
 
-def other_workloads(B, wl, K, W):
+def other_workloads(B, wl, K, W, transform):
     """Frame time of the other workloads (graph replay, bank noise, piston
     removal on): the 8x8 FP64 case, the 40x40 frozen-flow case and 64
     independent instances in one launch."""
@@ -497,7 +509,8 @@ def other_workloads(B, wl, K, W):
                                         mask=np.ones((w.n_sub, w.n_sub), bool) if w.obscuration is None else None,
                                         rho=w.rho, r_sigma2=w.sigma ** 2, ar_coeff=w.a, noise_bank=bank,
                                         seed=0x5EED0000 + w.seed + i,
-                                        precision=B.FP64 if w.precision == "fp64" else B.FP32, piston=True))
+                                        precision=B.FP64 if w.precision == "fp64" else B.FP32, piston=True,
+                                        transform=transform))
         f = B.Letkf(specs)
         dt = torch.float64 if f.fp64 else torch.float32
         y = torch.empty((frames, f.sizes["n_slopes"]), dtype=dt, device="cuda")
@@ -569,6 +582,10 @@ def main():
     ap.add_argument("--copies", default="1,4,16,64",
                     help="comma list: instances of the workload in one launch (batched throughput lines)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--transform", default="nsp_mixed", choices=list(TRANSFORMS),
+                    help="transform of the local analyses in the headline frame")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline frame, batched copies and transforms only (no loops, no CPU leg)")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: timed steps only")
     ap.add_argument("--grad-frames", type=int, default=200, help="frames of the gradient timing (0 = skip)")
     ap.add_argument("--other-workloads", type=int, default=1, help="also time the 8x8, 40x40 and 64-instance workloads")
@@ -589,7 +606,7 @@ def main():
     seed = 0x5EED0000 + w.seed
     spec = B.InstanceSpec(n_sub=w.n_sub, m=w.m, domain_size=w.b, halo=w.h, obscuration=w.obscuration,
                           rho=w.rho, r_sigma2=w.sigma ** 2, ar_coeff=w.a, noise_bank=bank, seed=seed,
-                          precision=B.FP32, piston=True)
+                          precision=B.FP32, piston=True, transform=getattr(B, TRANSFORMS[args.transform]))
     f = B.Letkf([spec])
     K, W = args.steps, args.warmup
     frames = min(K + W, 600)
@@ -674,15 +691,18 @@ def main():
     for nc in ([int(c) for c in args.copies.split(",") if c] if args.copies else []):
         batched.append(batched_line(B, spec, y, min(K, 100), W, nc))
 
-    others = other_workloads(B, wl, max(20, min(K, 100)), W) if args.other_workloads else None
+    others = (other_workloads(B, wl, max(20, min(K, 100)), W, spec.transform)
+              if args.other_workloads else None)
 
-    transforms = transform_variants(B, spec, y, K, W)
-    loop = closed_loop_line(B, spec, wl, w, y, truth, ij, K, W)
-    kfref = kf_reference_line(B, wl)
-    models = model_variants(B, spec, wl, w, y, truth, ij, K, W)
+    transforms = transform_variants(B, spec, y, K, W, args.transform)
+    loop = kfref = models = None
+    if not args.quick:
+        loop = closed_loop_line(B, spec, wl, w, y, truth, ij, K, W)
+        kfref = kf_reference_line(B, wl)
+        models = model_variants(B, spec, wl, w, y, truth, ij, K, W)
 
     grad = None
-    if args.grad_frames > 0:
+    if args.grad_frames > 0 and not args.quick:
         grad = gradient_timing(B, w, bank, seed, y, truth, ij, args.grad_frames)
 
     out = {
@@ -709,7 +729,7 @@ def main():
         "gradient": grad,
         "roofline": roof,
     }
-    if not args.no_cpu:
+    if not args.no_cpu and not args.quick:
         nrng = np.random.default_rng(w.seed + 1)
         T = min(frames, 400)   # more frames than the time budget reaches
         out["cpu_baseline"] = cpu_baseline(w, bank, seed, truth[:T],

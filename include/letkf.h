@@ -74,6 +74,21 @@ extern "C" {
 #define LETKF_TRANSFORM_NS64 0
 #define LETKF_TRANSFORM_NS32 1
 #define LETKF_TRANSFORM_EVD 2
+/*   NSP        the same iteration written on P = Z Y alone (P <- a P T^2,
+ *              T = (3 I - a P) / 2: two products of P with its own powers a
+ *              step, on the ten upper 16 x 16 tiles), in FP64, carrying only
+ *              what the update needs: Z X'^T for the owned rows and Z b.
+ *              Same stopping rule as NS64.
+ *   NSP_MIXED  NSP with the P updates in FP64 while the spectrum's lower
+ *              bound l is below 0.1 (the steps whose rounding the small
+ *              eigenvalues amplify) and in FP32 after; X' Z in FP32.  The
+ *              anomaly transform lands within ~1.5e-6 of the FP64 one, under
+ *              the rounding the FP32 Gram itself carries.  FP32 handles; an
+ *              FP64 handle runs NSP.
+ * A handle with the blend-mode gather runs NS64 when NSP or NSP_MIXED is
+ * asked for (the P forms carry the owned rows only). */
+#define LETKF_TRANSFORM_NSP 3
+#define LETKF_TRANSFORM_NSP_MIXED 4
 
 /* State model of an instance (letkf_config.model).
  *   PHASE        delay-free: x_k = phi_k, y_k = D phi_k + w_k.

@@ -28,7 +28,7 @@ lib = C.CDLL(LIB_PATH)
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6
 FP32, FP64 = 0, 1
 FLAG_NONFINITE, FLAG_NOCONV = 1, 2
-TRANSFORM_NS64, TRANSFORM_NS32, TRANSFORM_EVD = 0, 1, 2
+TRANSFORM_NS64, TRANSFORM_NS32, TRANSFORM_EVD, TRANSFORM_NSP, TRANSFORM_NSP_MIXED = 0, 1, 2, 3, 4
 MODEL_PHASE, MODEL_CLOSED_LOOP = 0, 1
 GATHER_CONCAT, GATHER_BLEND = 0, 1
 LOCALISATION_DOMAIN, LOCALISATION_COVARIANCE = 0, 1
@@ -161,7 +161,7 @@ class InstanceSpec:
     jacobi_tol: float = 0.0
     max_sweeps: int = 0
     piston: bool = False                  # differential-piston removal after the gather
-    transform: int = TRANSFORM_NS64       # how W, w come from A~ (NS64, NS32 or the Jacobi EVD)
+    transform: int = TRANSFORM_NSP_MIXED  # how W, w come from A~ (NSP_MIXED, NSP, NS64, NS32 or the Jacobi EVD)
     model: int = MODEL_PHASE              # delay-free phase state, or the closed AO loop (Sec. 2.2)
     ar2_coeff: float = 0.0                # a2 of an AR(2) turbulence model (0: AR(1))
     refit_forgetting: float = 0.0         # online AR(1) refit with this forgetting factor (0: off)

@@ -1027,7 +1027,8 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
       return fail(LETKF_E_INVAL, "all instances of a handle must share the localisation");
   }
   if (cfgs[0].transform != LETKF_TRANSFORM_NS64 && cfgs[0].transform != LETKF_TRANSFORM_NS32 &&
-      cfgs[0].transform != LETKF_TRANSFORM_EVD)
+      cfgs[0].transform != LETKF_TRANSFORM_EVD && cfgs[0].transform != LETKF_TRANSFORM_NSP &&
+      cfgs[0].transform != LETKF_TRANSFORM_NSP_MIXED)
     return fail(LETKF_E_INVAL, "unknown transform");
   letkf_handle *h = new letkf_handle();
   h->device = device;
@@ -1038,6 +1039,15 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
   h->max_sweeps = cfgs[0].max_sweeps > 0 ? cfgs[0].max_sweeps : 30;
   h->transform = cfgs[0].transform;
   if (h->fp64 && h->transform == LETKF_TRANSFORM_NS32) h->transform = LETKF_TRANSFORM_NS64;
+  if (h->fp64 && h->transform == LETKF_TRANSFORM_NSP_MIXED) h->transform = LETKF_TRANSFORM_NSP;
+  {
+    // the P-form transforms carry the owned rows only: the blend-mode gather
+    // (every patch row updated) runs the coupled FP64 iteration instead
+    bool blend = false;
+    for (int i = 0; i < n_instances; ++i) blend |= cfgs[i].gather_mode == LETKF_GATHER_BLEND;
+    if (blend && (h->transform == LETKF_TRANSFORM_NSP || h->transform == LETKF_TRANSFORM_NSP_MIXED))
+      h->transform = LETKF_TRANSFORM_NS64;
+  }
   // covariance localisation has its own kernel (no transform)
   if (cfgs[0].localisation == LETKF_LOCALISATION_COVARIANCE) h->transform = kAnalysisCl;
   h->geom.resize(n_instances);
@@ -1175,14 +1185,18 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     h->fwd_off[6] = (int32_t)f; f = align16(f + scratch * 8);
     h->fwd_off[0] = (int32_t)f;
     // (blend mode updates every patch row: the rows past the owned ones are
-    // staged again after the transform)
-    const size_t ub = align16(f + (size_t)h->max_own * kXsStride * T);
+    // staged again after the transform; the P-form transforms carry V = X' Z
+    // in place of the owned rows, in whole 16-row blocks)
+    const bool nsp = h->transform == LETKF_TRANSFORM_NSP || h->transform == LETKF_TRANSFORM_NSP_MIXED;
+    const size_t own_rows = nsp ? (size_t)16 * ((h->max_own + 15) / 16) : (size_t)h->max_own;
+    const size_t ub = align16(f + own_rows * kXsStride * T);
     const size_t rows_end = f + (size_t)h->max_patch * kXsStride * T;  // end of the patch rows
     const size_t ys_bytes = p4 * kYsStride * T;
     const size_t spill = rows_end > ub ? align16(rows_end - ub) : 0;
     // Newton-Schulz in FP64: A~, then the two FP64 iterates; with FP32
     // iterates: three of them and the FP32 Gram (row stride 68); Jacobi: A~
     // and its factor (the block exchange and W reuse the area)
+    // (the P-form transforms: A~ then P, and P^2, in the two FP64 areas)
     const size_t iter_bytes = h->transform == LETKF_TRANSFORM_NS32   ? (size_t)4 * 64 * 68 * 4
                               : h->transform == LETKF_TRANSFORM_EVD ? std::max(u, (size_t)64 * 65 * 8)
                                                                     : (size_t)2 * 64 * 65 * 8;

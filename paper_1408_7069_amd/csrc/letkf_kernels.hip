@@ -41,6 +41,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "letkf_types.h"
 
@@ -220,6 +221,23 @@ __device__ inline double swap_sum16(double a, double b) {
   const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a),
                                                    (unsigned)__double2hiint(b), false, false);
   return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// Sum over the 64 lanes in registers (DPP within 16-lane rows, then the
+// row swaps), result in every lane.
+__device__ inline double wave_sum_dpp(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  v = swap_sum16(v, v);
+  return swap_sum32(v, v);
+}
+
+// Sum over the four 16-lane rows (lanes l, l + 16, l + 32, l + 48), in every lane.
+__device__ inline double rows_sum(double v) {
+  v = swap_sum16(v, v);
+  return swap_sum32(v, v);
 }
 
 // Sums over the 64 rows (lanes) of 8 per-lane values f(j) of this wave:
@@ -1047,6 +1065,381 @@ __device__ inline double matvec_quad(const float *M, const double *x, int q, int
   return v;
 }
 
+// ------------------------------------------- P-form inverse square root
+// The scaled Newton-Schulz iteration written on P_k = Z_k Y_k alone: with
+// T_k = (3 I - a_k P_k) / 2 (a polynomial in P_k, so all these matrices
+// commute), Z_{k+1} = sqrt(a_k) T_k Z_k gives
+//     P_{k+1} = a_k P_k T_k^2 = a_k (9/4 P_k - 3/2 a_k P_k^2 + 1/4 a_k^2 P_k^3),
+// P_0 = A~ / s, and Z = prod_k sqrt(a_k) T_k -> (A~ / s)^{-1/2}.  Two products
+// of one symmetric matrix with its own powers a step (P^2, then P^2 P), each
+// on the ten upper 16 x 16 tiles: a rounding error of P_k is a slightly
+// different symmetric P_k, which the iteration carries to I like any other,
+// so no product of two separately rounded iterates is ever mirrored.  Z is
+// never formed: the rows the update needs are carried instead,
+//     V_{k+1} = sqrt(a_k) V_k T_k,  V_0 = X' (owned rows x members),
+// so V_final = X' Z and X' W = sqrt(c / s) V, and the mean weights through
+//     h_{k+1} = sqrt(a_k) T_k h_k,  h_0 = b:  X' w = X' Z^2 b / s = V h / s.
+// A rounding error delta of P_k enters Z as delta / mu where mu is the
+// eigenvalue it perturbs; the smallest eigenvalues are of order l_k, so the
+// steps with l_k small carry the cancellation.  MIXED (FP32 handles): P is
+// updated in FP64 until l_k >= kNspSwitch, then in FP32 (the rounding
+// divided by l_k stays under the FP32 Gram's own error).
+//
+// Storage: P and P^2 as full 64 x 64 matrices (both triangles; FP64 with row
+// stride kLaStride, or FP32 with row stride kNs32Stride in the FP32 steps,
+// in the same two areas), V in place of the owned patch rows ([row][member],
+// row stride kXsStride, element type of the handle).  Each wave keeps the
+// column block q of P in registers (the right operand of every product and
+// the column block q of T).
+constexpr double kNspSwitch = 0.1;
+
+// Tile I of a column block held in registers, I a runtime value (selects,
+// so that the block stays in registers).
+__device__ __forceinline__ f64x4 cb_tile(const ColBlock &B, int I) {
+  return I == 0 ? B[0] : I == 1 ? B[1] : I == 2 ? B[2] : B[3];
+}
+__device__ __forceinline__ f32x4 cb_tile32(const ColBlock32 &B, int I) {
+  return I == 0 ? B[0] : I == 1 ? B[1] : I == 2 ? B[2] : B[3];
+}
+
+// FP32 matrices (row stride kNs32Stride): the FP32 accumulator layout is
+// tile J, element r: row 16 J + 4 (lane / 16) + r; as the right operand with
+// the contraction order k = 16 J + 4 (lane / 16) + r at step 4 J + r, the
+// left operand of a lane is four consecutive floats of one row per J.
+__device__ __forceinline__ void f32_load_colblock(const float *M, ColBlock32 &B, int q, int lane) {
+  const int c16 = lane & 15, g4 = 4 * (lane >> 4);
+#pragma unroll
+  for (int J = 0; J < 4; ++J)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) B[J][r] = M[(16 * J + g4 + r) * kNs32Stride + 16 * q + c16];
+}
+
+// Store tile (I, q) (FP32 accumulator layout) and its mirror.
+__device__ __forceinline__ void f32_store_tile(float *M, int I, int q, const f32x4 &v, int lane) {
+  const int c16 = lane & 15, g4 = 4 * (lane >> 4);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) M[(16 * I + g4 + r) * kNs32Stride + 16 * q + c16] = v[r];
+  if (I != q) *(f32x4 *)(M + (16 * q + c16) * kNs32Stride + 16 * I + g4) = v;
+}
+
+// Store tile (I, q) (FP64 accumulator layout) into an FP64 matrix (row stride
+// kLaStride) or, with F32, an FP32 one, with its mirror.
+template <bool F32>
+__device__ __forceinline__ void store_tile64(void *Mv, int I, int q, const f64x4 &v, int lane) {
+  const int c16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * I + g + 4 * r;
+    if constexpr (F32) {
+      float *M = (float *)Mv;
+      M[row * kNs32Stride + 16 * q + c16] = (float)v[r];
+      if (I != q) M[(16 * q + c16) * kNs32Stride + row] = (float)v[r];
+    } else {
+      double *M = (double *)Mv;
+      M[row * kLaStride + 16 * q + c16] = v[r];
+      if (I != q) M[(16 * q + c16) * kLaStride + row] = v[r];
+    }
+  }
+}
+
+struct NspStatus {
+  int iters;   // steps taken (negative: no convergence)
+  bool finite;
+  double s;    // the scale: Z ~ (A~ / s)^{-1/2}
+};
+
+struct NspState {
+  double l, sc;   // lower bound of the spectrum of P_k; P_k = sc x (stored matrix)
+  int it;         // steps taken
+  bool conv, finite;
+};
+
+// NT tiles (rows (q + t) & 3) of M B: M an FP64 matrix in LDS (stride
+// kLaStride) as the left operand, B a column block in registers, the FP64
+// order (step kk takes k = 4 kk + lane / 16); all tiles in one pass over K
+// so that the matrix cores always have an independent product to issue.
+template <int NT>
+__device__ __forceinline__ void mm_rows64(const double *M, const ColBlock &B, f64x4 C[3], int q, int lane) {
+  const int c16 = lane & 15, g = lane >> 4;
+  const double *r[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) r[t] = M + (16 * ((q + t) & 3) + c16) * kLaStride + g;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) C[t] = Mfma<double>::zero();
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const double b = B[kk >> 2][kk & 3];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) C[t] = Mfma<double>::mac(r[t][4 * kk], b, C[t]);
+  }
+}
+
+// The same with FP32 matrices on the FP32 matrix cores (FP32 order).
+template <int NT>
+__device__ __forceinline__ void mm_rows32(const float *M, const ColBlock32 &B, f32x4 C[3], int q, int lane) {
+  const int c16 = lane & 15, g4 = 4 * (lane >> 4);
+  const float *r[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) r[t] = M + (16 * ((q + t) & 3) + c16) * kNs32Stride + g4;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) C[t] = Mfma<float>::zero();
+#pragma unroll
+  for (int J = 0; J < 4; ++J) {
+    f32x4 a[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) a[t] = *(const f32x4 *)(r[t] + 16 * J);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) C[t] = Mfma<float>::mac(a[t][rr], B[J][rr], C[t]);
+  }
+}
+
+// V T for the member block q: ncb row tiles of V (rows 16 cb + .., element
+// type TV, row stride kXsStride) times T's column block q, T = 3/2 I - ta Pc
+// formed from the registers.  FP64 order with an FP64 column block (F32
+// false), FP32 order on the FP32 matrix cores otherwise.
+template <typename TV, bool F32, typename CB>
+__device__ __forceinline__ void v_times_t(const TV *V, const CB &Pc, double ta, int ncb, f64x4 Vo[4], int q,
+                                          int lane) {
+  const int c16 = lane & 15, g = lane >> 4;
+  if constexpr (F32) {
+    ColBlock32 Tc;
+#pragma unroll
+    for (int J = 0; J < 4; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Tc[J][r] = ((16 * J + 4 * g + r) == (16 * q + c16) ? 1.5f : 0.0f) - (float)ta * Pc[J][r];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      if (cb < ncb) {
+        const TV *vr = V + (16 * cb + c16) * kXsStride + 4 * g;
+        f32x4 acc = Mfma<float>::zero();
+#pragma unroll
+        for (int J = 0; J < 4; ++J)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc = Mfma<float>::mac((float)vr[16 * J + r], Tc[J][r], acc);
+        Vo[cb] = f64x4{acc[0], acc[1], acc[2], acc[3]};
+      }
+    }
+  } else {
+    ColBlock Tc;
+#pragma unroll
+    for (int J = 0; J < 4; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Tc[J][r] = ((16 * J + g + 4 * r) == (16 * q + c16) ? 1.5 : 0.0) - ta * (double)Pc[J][r];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      if (cb < ncb) {
+        const TV *vr = V + (16 * cb + c16) * kXsStride + g;
+        f64x4 acc = Mfma<double>::zero();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) acc = Mfma<double>::mac((double)vr[4 * kk], Tc[kk >> 2][kk & 3], acc);
+        Vo[cb] = acc;
+      }
+    }
+  }
+}
+
+// One step of the P-form iteration with P held in FP64 (Pd; P^2 in Qd) or,
+// with F32, in FP32 (the same areas as float).  Forms T_k applied to V and h
+// and P^2 before the first barrier, stores V and h after it (every read of
+// them came before) with P_{k+1} (to FP32 storage when TO32).  Returns
+// whether P_{k+1} went to FP32.
+template <typename TV, bool F32>
+__device__ __forceinline__ bool nsp_step(double *Pd, double *Qd, TV *V, int ncb, double *hb, double *sm,
+                                         double tol, int max_it, bool may32, NspState &S, int q, int lane,
+                                         int rot) {
+  const int c16 = lane & 15, g = lane >> 4;
+  const int n1 = ((q - rot) & 3) < 2 ? 3 : 2, n2 = ((q - rot - 2) & 3) < 2 ? 3 : 2;  // tiles of P^2, of P^3
+  const double al = 3.0 / (1.0 + sqrt(S.l) + S.l), sa = sqrt(al);
+  const double ta = 0.5 * al;   // T = 3/2 I - ta P (P true, scale applied)
+  float *P32 = (float *)Pd, *Q32 = (float *)Qd;
+  using CB = typename std::conditional<F32, ColBlock32, ColBlock>::type;
+  using QV = typename std::conditional<F32, f32x4, f64x4>::type;
+  CB Pc;
+  double e2 = 0.0;
+  if constexpr (F32) {
+    f32_load_colblock(P32, Pc, q, lane);
+#pragma unroll
+    for (int J = 0; J < 4; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double d = fma(al, (double)Pc[J][r], (16 * J + 4 * g + r) == (16 * q + c16) ? -1.0 : 0.0);
+        e2 = fma(d, d, e2);
+      }
+  } else {
+    load_colblock(Pd, Pc, q, lane);
+#pragma unroll
+    for (int J = 0; J < 4; ++J) {
+      Pc[J] *= S.sc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double d = fma(al, Pc[J][r], (16 * J + g + 4 * r) == (16 * q + c16) ? -1.0 : 0.0);
+        e2 = fma(d, d, e2);
+      }
+    }
+  }
+  e2 = wave_sum_dpp(e2);
+  if (lane == 0) sm[S_RES + q] = e2;
+  // V T_k (member block q of every row block)
+  f64x4 Vo[4];
+  v_times_t<TV, F32, CB>(V, Pc, ta, ncb, Vo, q, lane);
+  // h: sqrt(a) (3/2 h - ta P h) for row 16 q + c16 (segment g, summed over lanes)
+  double hn;
+  {
+    const int i = 16 * q + c16;
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    if constexpr (F32) {
+      const float *pr = P32 + i * kNs32Stride + 16 * g;
+#pragma unroll
+      for (int j = 0; j < 16; j += 4) {
+        const f32x4 v = *(const f32x4 *)(pr + j);
+        p0 = fma((double)v[0], hb[16 * g + j], p0);
+        p1 = fma((double)v[1], hb[16 * g + j + 1], p1);
+        p2 = fma((double)v[2], hb[16 * g + j + 2], p2);
+        p3 = fma((double)v[3], hb[16 * g + j + 3], p3);
+      }
+    } else {
+      const double *pr = Pd + i * kLaStride + 16 * g;
+#pragma unroll
+      for (int j = 0; j < 16; j += 4) {
+        p0 = fma(pr[j], hb[16 * g + j], p0);
+        p1 = fma(pr[j + 1], hb[16 * g + j + 1], p1);
+        p2 = fma(pr[j + 2], hb[16 * g + j + 2], p2);
+        p3 = fma(pr[j + 3], hb[16 * g + j + 3], p3);
+      }
+    }
+    const double part = rows_sum(((p0 + p1) + (p2 + p3)) * S.sc);
+    hn = sa * fma(-ta, part, 1.5 * hb[i]);
+  }
+  // P^2 on this wave's tiles (q + t, q), t < n1 (not needed after the last step)
+  const bool more = S.it + 1 < max_it;
+  if (more) {
+    QV Qo[3];
+    if constexpr (F32) {
+      if (n1 == 3) mm_rows32<3>(P32, Pc, Qo, q, lane); else mm_rows32<2>(P32, Pc, Qo, q, lane);
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        if (t < n1) f32_store_tile(Q32, (q + t) & 3, q, Qo[t], lane);
+    } else {
+      if (n1 == 3) mm_rows64<3>(Pd, Pc, Qo, q, lane); else mm_rows64<2>(Pd, Pc, Qo, q, lane);
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        if (t < n1) store_tile64<false>(Qd, (q + t) & 3, q, Qo[t] * S.sc, lane);
+    }
+  }
+  __syncthreads();  // #1: P^2 and the residual complete; every read of P, V and h done
+  const double d2 = sum4(sm + S_RES);
+  S.finite = isfinite(d2);
+  S.conv = S.finite && 0.75 * d2 <= tol;
+  ++S.it;
+  // V <- sqrt(a) V T_k (this wave's members), h <- its update
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    if (cb < ncb) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * cb + (F32 ? 4 * g + r : g + 4 * r);
+        V[row * kXsStride + 16 * q + c16] = (TV)(sa * Vo[cb][r]);
+      }
+    }
+  }
+  if (g == 0) hb[16 * q + c16] = hn;
+  bool went32 = false;
+  if (!S.conv && S.finite && more) {
+    // P_{k+1} = a (9/4 P - 3/2 a P^2 + 1/4 a^2 P^3) on the tiles (q + t, q),
+    // t < n2 (the other role assignment), P^3 = P^2 P, P^2 read back;
+    // written over P (no wave reads P after the first barrier)
+    QV Ro[3];
+    if constexpr (F32) {
+      if (n2 == 3) mm_rows32<3>(Q32, Pc, Ro, q, lane); else mm_rows32<2>(Q32, Pc, Ro, q, lane);
+      const float alf = (float)al;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        if (t < n2) {
+          const int I = (q + t) & 3;
+          const f32x4 pv = cb_tile32(Pc, I);
+          f32x4 Pn;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float qv = Q32[(16 * I + 4 * g + r) * kNs32Stride + 16 * q + c16];
+            Pn[r] = alf * (2.25f * pv[r] - 1.5f * alf * qv + 0.25f * alf * alf * Ro[t][r]);
+          }
+          f32_store_tile(P32, I, q, Pn, lane);
+        }
+      }
+    } else {
+      if (n2 == 3) mm_rows64<3>(Qd, Pc, Ro, q, lane); else mm_rows64<2>(Qd, Pc, Ro, q, lane);
+      went32 = may32 && S.l >= kNspSwitch;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        if (t < n2) {
+          const int I = (q + t) & 3;
+          const f64x4 pv = cb_tile(Pc, I);
+          f64x4 Pn;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double qv = Qd[(16 * I + g + 4 * r) * kLaStride + 16 * q + c16];
+            Pn[r] = al * (2.25 * pv[r] - 1.5 * al * qv + 0.25 * al * al * Ro[t][r]);
+          }
+          if (went32)
+            store_tile64<true>(Pd, I, q, Pn, lane);
+          else
+            store_tile64<false>(Pd, I, q, Pn, lane);
+        }
+      }
+    }
+  }
+  __syncthreads();  // #2: P_{k+1}, V and h complete
+  S.sc = 1.0;
+  S.l = al * S.l * (3.0 - al * S.l) * (3.0 - al * S.l) * 0.25;
+  return went32;
+}
+
+// The P-form iteration on A~ (FP64, full, in area0; area1 the second
+// area) with V_0 = X' in V (owned rows x members, row stride kXsStride, ncb
+// row blocks) and h_0 = b in hb[0..63].  On return V holds V_final = X' Z
+// and hb h_final = Z b.  Every wave takes the same decisions (the residual
+// is summed over the workgroup).
+template <typename TV, bool MIXED>
+__device__ __forceinline__ NspStatus nsp_isqrt(double *area0, double *area1, TV *V, int ncb, double *hb,
+                                               double *sm, double c, double tol, int max_it, int q, int lane,
+                                               int rot) {
+  // s = ||A~||_F
+  {
+    double ss = 0.0;
+    const int col = 16 * q + (lane & 15), g = lane >> 4;
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double v = area0[(16 * I + g + 4 * r) * kLaStride + col];
+        ss = fma(v, v, ss);
+      }
+    ss = wave_sum(ss);
+    if (lane == 0) sm[S_RES + q] = ss;
+  }
+  __syncthreads();
+  const double s = sqrt(sum4(sm + S_RES));
+  NspState S{c / s, 1.0 / s, 0, false, true};
+  bool to32 = false;
+  for (;;) {
+    to32 = nsp_step<TV, false>(area0, area1, V, ncb, hb, sm, tol, max_it, MIXED, S, q, lane, rot);
+    if (S.conv || !S.finite || S.it >= max_it || to32) break;
+  }
+  if constexpr (MIXED) {
+    if (to32 && !S.conv && S.finite && S.it < max_it) {
+      for (;;) {
+        nsp_step<TV, true>(area0, area1, V, ncb, hb, sm, tol, max_it, false, S, q, lane, rot);
+        if (S.conv || !S.finite || S.it >= max_it) break;
+      }
+    }
+  }
+  return NspStatus{S.conv ? S.it : -S.it, S.finite, s};
+}
+
 template <typename T> struct AnaArgs {
   const InstDesc *inst;
   const DomItem *items;
@@ -1369,7 +1762,7 @@ __device__ __forceinline__ CoreStatus analysis_core(const AnaArgs<T> &A, const D
 // Transform of the analysis (stages 4-6): the inverse square root by the
 // Newton-Schulz iteration in FP64 (default) or with FP32 iterates, or the
 // symmetric eigendecomposition by the one-sided Jacobi.
-constexpr int kEigNs64 = 0, kEigNs32 = 1, kEigJacobi = 2;
+constexpr int kEigNs64 = 0, kEigNs32 = 1, kEigJacobi = 2, kEigNsp = 3, kEigNspMix = 4;
 
 template <typename T, bool FUSED, int EIG>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_analysis(const AnaArgs<T> A) {
@@ -1394,7 +1787,62 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   int flag;
   T wf[16];  // this wave's column block of W, right-operand layout of the update
 
-  if constexpr (EIG == kEigJacobi) {
+  if constexpr (EIG == kEigNsp || EIG == kEigNspMix) {
+    // ---- 1.-3. staging and the Gram; 4.-6. the P-form iteration carrying
+    // V = X' Z of the owned rows (in their place) and h = Z b ----
+    constexpr bool MIXED = EIG == kEigNspMix && sizeof(T) == 4;
+    const bool gbad = stage_gram<T, FUSED>(A, it, in, frame, smem);
+    double *area0 = (double *)(smem + A.off_u), *area1 = area0 + 64 * kLaStride;
+    const int ncb = (nown + 15) >> 4;
+    // V_0 = X' of the owned rows, in place (rows past n_own and members past m zero)
+    for (int e = tid; e < 16 * ncb * 64; e += kThreads) {
+      const int i = e >> 6, kk = e & 63;
+      xs[i * kXsStride + kk] = (i < nown && kk < m) ? xs[i * kXsStride + kk] - xm[i] : (T)0;
+    }
+    // the three-tile roles as in ns_isqrt: a function of the item alone
+    const int per = (A.n_items + 7) >> 3;
+    const int rot = ((item % per) / A.round_items) & 1;
+    double *hb = sm + S_VEC;  // h_0 = b
+    const NspStatus st = nsp_isqrt<T, MIXED>(area0, area1, xs, ncb, hb, sm, c, A.jtol * 0.01, A.max_sweeps, q,
+                                             lane, rot);
+    const int nit = st.iters > 0 ? st.iters : -st.iters;
+    const bool nconv = st.iters > 0;
+    const int nflag = (gbad || !st.finite ? 1 : 0) | (nconv || !st.finite ? 0 : 2) | (min(nit, 255) << 8);
+    const bool keep = gbad || !st.finite || !nconv;
+    if (tid == 0) A.flags[item] = nflag;
+    if (keep) {
+      // the forecast is the result: the owned rows of X_b again (V took their place)
+      __syncthreads();
+      BankDraw bd{};
+      if (FUSED && A.noise_bank) bd = bank_draw(in, frame, lane < m ? lane : 0);
+      stage_patch_rows<T, FUSED>(A, in, pn, bd, xs, nown, q, lane, 0);
+      __syncthreads();
+      for (int i = q; i < nown; i += kWaves)
+        if (lane < m) A.x_out[in.x_off + (int64_t)pn[i] * m + lane] = xs[i * kXsStride + lane];
+      if (tid < nown && A.x_mean) {
+        const T uo = (in.model == 1 && A.u_prev2) ? ((const T *)(pn + kPnU))[tid] : (T)0;
+        A.x_mean[in.node_off + pn[tid]] = xm[tid] - uo;
+      }
+      return;
+    }
+    // ---- 7. x_a = x_b + X' w = x_b + V h / s, X_a = x_a 1^T + sqrt(rho c / s) V ----
+    for (int i = q; i < nown; i += kWaves) {
+      double v = lane < m ? (double)xs[i * kXsStride + lane] * hb[lane] : 0.0;
+      v = wave_sum(v);
+      if (lane == 0) sm[S_XAM + i] = (double)xm[i] + v / st.s;
+    }
+    __syncthreads();
+    const double wsc = sqrt(in.rho * c / st.s);
+    for (int i = q; i < nown; i += kWaves)
+      if (lane < m)
+        A.x_out[in.x_off + (int64_t)pn[i] * m + lane] = (T)(sm[S_XAM + i] + wsc * (double)xs[i * kXsStride + lane]);
+    if (tid < nown && A.x_mean) {
+      // the piston fit reads this mean (in the closed loop: x_a - N u_{k-2})
+      const T uo = (in.model == 1 && A.u_prev2) ? ((const T *)(pn + kPnU))[tid] : (T)0;
+      A.x_mean[in.node_off + pn[tid]] = (T)sm[S_XAM + tid] - uo;
+    }
+    return;
+  } else if constexpr (EIG == kEigJacobi) {
     // ---- 1.-6. staging, Gram, Cholesky and w, Jacobi, W in LDS ----
     double X[8], Y[8];
     const CoreStatus cs = analysis_core<T, FUSED>(A, it, in, frame, smem, X, Y);
@@ -2836,6 +3284,10 @@ template <typename T> static const void *analysis_kernel_of(int fused, int eig) 
     return fused ? (const void *)k_analysis<T, true, kEigJacobi> : (const void *)k_analysis<T, false, kEigJacobi>;
   if (eig == kEigNs32 && sizeof(T) == 4)
     return fused ? (const void *)k_analysis<T, true, kEigNs32> : (const void *)k_analysis<T, false, kEigNs32>;
+  if (eig == kEigNspMix && sizeof(T) == 4)
+    return fused ? (const void *)k_analysis<T, true, kEigNspMix> : (const void *)k_analysis<T, false, kEigNspMix>;
+  if (eig == kEigNsp || eig == kEigNspMix)
+    return fused ? (const void *)k_analysis<T, true, kEigNsp> : (const void *)k_analysis<T, false, kEigNsp>;
   return fused ? (const void *)k_analysis<T, true, kEigNs64> : (const void *)k_analysis<T, false, kEigNs64>;
 }
 

@@ -10,7 +10,7 @@ constexpr int kMaxOwned = 64;     // (b + 1)^2 owned nodes at most
 constexpr int kMaxPatch = 64;     // owned nodes + every corner of the region
 constexpr int kYsStride = 80;     // row stride of K-major MFMA operands (no bank conflicts)
 constexpr int kXsStride = 65;     // row stride of node rows (lane = row reads)
-constexpr int kAnalysisCl = 3;    // analysis-kernel selector of covariance localisation (after the transforms)
+constexpr int kAnalysisCl = 8;    // analysis-kernel selector of covariance localisation (after the transforms)
 constexpr int kClXtStride = 66;   // covariance localisation: row stride of the FP64 transposed patch
 
 // One adaptive-optics instance.

@@ -36,17 +36,20 @@ def _frame_vs_oracle(case, f, Xa_prev, V, y):
     return got, ref
 
 
-TRANSFORMS = ["ns64", "ns32", "evd"]
+TRANSFORMS = ["ns64", "ns32", "evd", "nsp", "nspmix"]
 
 
 def _tr(name):
     bb = B()
-    return {"ns64": bb.TRANSFORM_NS64, "ns32": bb.TRANSFORM_NS32, "evd": bb.TRANSFORM_EVD}[name]
+    return {"ns64": bb.TRANSFORM_NS64, "ns32": bb.TRANSFORM_NS32, "evd": bb.TRANSFORM_EVD,
+            "nsp": bb.TRANSFORM_NSP, "nspmix": bb.TRANSFORM_NSP_MIXED}[name]
 
 
 @pytest.mark.parametrize("fp64,tol,transform", [(True, 1e-10, "ns64"), (True, 1e-10, "evd"),
+                                                (True, 1e-10, "nsp"), (True, 1e-10, "nspmix"),
                                                 (False, 1e-4, "ns64"), (False, 1e-4, "ns32"),
-                                                (False, 1e-4, "evd")])
+                                                (False, 1e-4, "evd"), (False, 1e-4, "nsp"),
+                                                (False, 1e-4, "nspmix")])
 def test_smallest_workload_frames(fp64, tol, transform):
     # 8x8 square pupil, 2x2 domains, halo 1, m = 20 (16 domains)
     case = Case(8, None, 2, 1, 20, seed=1, fp64=fp64, pitch=0.4)
@@ -158,6 +161,27 @@ def test_full_size_80x80_m64_in_the_timed_configuration(transform):
         Xa = ref
 
 
+def test_mixed_p_form_tracks_the_fp64_p_form():
+    # the FP32 steps of NSP_MIXED move the 80x80 ensemble by ~1e-6 of its
+    # size from the all-FP64 P-form on the same inputs, well under the FP32
+    # Gram's own rounding (same handle inputs, one frame each, three frames)
+    case = Case(80, 0.28, 4, 1, 64, seed=19)
+    bb = B()
+    fm = bb.Letkf([case.spec(bb, transform=bb.TRANSFORM_NSP_MIXED)])
+    fd = bb.Letkf([case.spec(bb, transform=bb.TRANSFORM_NSP)])
+    X = (case.rng.standard_normal((case.G.n_nodes, case.m)) * 0.3).astype(np.float32)
+    for k in range(3):
+        V, y = case.noise(), case.slopes(case.truth())
+        for f in (fm, fd):
+            f.set_ensemble(_t(X))
+            f.step(_t(y), V=_t(V))
+        torch.cuda.synchronize()
+        a, b = _ens(fm, case.m), _ens(fd, case.m)
+        assert rel_err(a, b) <= 1e-5, k
+        assert rel_err(a - a.mean(1, keepdims=True), b - b.mean(1, keepdims=True)) <= 2e-5, k
+        X = b.astype(np.float32)
+
+
 @pytest.mark.parametrize("transform", TRANSFORMS)
 def test_many_instances_in_one_launch(transform):
     bb = B()
@@ -230,7 +254,7 @@ def test_autotune_choice_is_cached_and_bitwise_neutral(tmp_path):
     sched = f.autotune(ys[0], frames=4, cache_path=cache)
     lines = open(cache).read().splitlines()
     assert len(lines) == 1 and f"graph {int(sched[0])} order {sched[1]}" in lines[0]
-    assert " transform 0 " in lines[0] and " localisation 0 " in lines[0]
+    assert f" transform {bb.TRANSFORM_NSP_MIXED} " in lines[0] and " localisation 0 " in lines[0]
     assert f.get_frame() == 0 and np.all(f.get_ensemble().cpu().numpy() == 0)   # state restored
     g = bb.Letkf([case.spec(bb)])
     assert g.autotune(ys[0], frames=4, cache_path=cache) == sched            # read from the cache
