@@ -145,6 +145,50 @@ def batched_line(B, spec, y, K, W, copies: int) -> dict:
             "frac_frame": round(t_lb / (ms * 1e-3), 4)}
 
 
+def paper_shape_lines(B, w, bank, seed, y, K, W, copies=(1, 4)) -> list:
+    """The shape of the paper's timings (Sec. 5.3, Tables 1-2): m = 101, 4x4
+    domains with a halo of 2 (9x9-node patches, up to 128 local slopes) on the
+    80x80 pupil, FP32 state, pistons, bank noise -- the wide analysis kernel
+    (8 wavefronts a domain, FP64 P-form iteration); `copies` instances in one
+    launch.  Frame time by the tuned schedule, the kernel's own duration by
+    HIP events around its direct launches, the roofline fraction on the same
+    count as the headline (9 m^3 + Gram + update per domain, m = 101)."""
+    import torch
+    out = []
+    for nc in copies:
+        spec = B.InstanceSpec(n_sub=w.n_sub, m=101, domain_size=4, halo=2, obscuration=w.obscuration,
+                              rho=w.rho, r_sigma2=w.sigma ** 2, ar_coeff=w.a, noise_bank=bank, seed=seed,
+                              precision=B.FP32, piston=True)
+        f = B.Letkf([spec] * nc)
+        yc = y.repeat(1, nc) if nc > 1 else y
+        sched = f.autotune(yc[0], frames=20)
+        zero = lambda: (f.set_ensemble(torch.zeros(f.sizes["ensemble_elems"], dtype=torch.float32,
+                                                   device="cuda")), f.set_frame(0))
+        zero()
+        ms = time_steps(f, yc, K, W)
+        zero()
+        f.set_schedule(False, sched[1])
+        time_steps(f, yc, 0, W)
+        f.set_timing(True)
+        time_steps(f, yc, K, 0, offset=W)
+        kt = float(np.mean(f.analysis_times()))
+        f.set_timing(False)
+        t_lb, _ = handle_bound(f)
+        nd = int(f.sizes["n_domains"])
+        steps = (f.status()[1] >> 8) & 255
+        out.append({"instances": nc, "domains": nd, "m": 101, "max_local_slopes": int(f.sizes["max_obs"]),
+                    "max_patch_nodes": int(f.sizes["max_patch"]), "schedule": schedule_label(sched),
+                    "ms_per_step": round(ms, 4), "frames_per_s": round(1000.0 / ms, 2),
+                    "kernel_ms": round(kt, 4), "local_analyses_per_s": round(nd * 1000.0 / ms, 1),
+                    "us_per_local_analysis_kernel": round(kt * 1000.0 / nd, 4),
+                    "t_lb_us": round(t_lb * 1e6, 3), "frac_kernel": round(t_lb / (kt * 1e-3), 4),
+                    "frac_frame": round(t_lb / (ms * 1e-3), 4),
+                    "transform_steps_mean": round(float(steps.mean()), 3),
+                    "paper_cpu_ms_per_domain": 0.94})
+        f.close()
+    return out
+
+
 TRANSFORMS = {"nsp_mixed": "TRANSFORM_NSP_MIXED", "nsp": "TRANSFORM_NSP", "ns64": "TRANSFORM_NS64",
               "ns32": "TRANSFORM_NS32", "evd": "TRANSFORM_EVD"}
 TRANSFORM_LABELS = {"nsp_mixed": "P-form Newton-Schulz, FP64 then FP32 steps",
@@ -589,6 +633,8 @@ def main():
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: timed steps only")
     ap.add_argument("--grad-frames", type=int, default=200, help="frames of the gradient timing (0 = skip)")
     ap.add_argument("--other-workloads", type=int, default=1, help="also time the 8x8, 40x40 and 64-instance workloads")
+    ap.add_argument("--paper-shape", type=int, default=1,
+                    help="also time the paper's timing shape (m = 101, halo 2) on the 80x80 pupil")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the frame is not sharded "
@@ -695,6 +741,7 @@ def main():
               if args.other_workloads else None)
 
     transforms = transform_variants(B, spec, y, K, W, args.transform)
+    paper_shape = paper_shape_lines(B, w, bank, seed, y, min(K, 100), W) if args.paper_shape else None
     loop = kfref = models = None
     if not args.quick:
         loop = closed_loop_line(B, spec, wl, w, y, truth, ij, K, W)
@@ -721,6 +768,7 @@ def main():
         "step_ms_p99": round(float(np.percentile(per, 99)), 4),
         "batched_copies": batched,
         "transforms": transforms,
+        "paper_shape": paper_shape,
         "closed_loop": loop,
         "kf_reference": kfref,
         "model_variants": models,

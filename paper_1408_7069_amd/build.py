@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libletkf.so")
-SOURCES = ["letkf_kernels.hip", "letkf_host.cpp"]
+SOURCES = ["letkf_kernels.hip", "letkf_wide.hip", "letkf_host.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wno-unused-result", "-Wno-unused-value",
          # keep hipcc from forming packed FP32 instructions

@@ -69,6 +69,10 @@ extern "C" hipError_t letkf_launch_eigh(const double *A, int m, int batch, doubl
                                         hipStream_t s);
 extern "C" size_t letkf_args_size(int fp64);
 extern "C" int letkf_analysis_threads(void);
+extern "C" int letkf_analysis_threads_for(int eig);
+extern "C" size_t letkf_wide_scratch_doubles(void);
+extern "C" size_t letkf_wide_pn_ints(void);
+extern "C" size_t letkf_wide_tri_bytes(int nb);
 extern "C" size_t letkf_analysis_scratch_doubles(void);
 extern "C" size_t letkf_analysis_fwd_scratch_doubles(void);
 extern "C" size_t letkf_analysis_xch_bytes(void);
@@ -220,6 +224,7 @@ struct letkf_handle {
   double jtol = 0.0;
   int max_sweeps = 30;
   int transform = LETKF_TRANSFORM_NS64;  // forward transform (FP64 handles: never NS32)
+  bool wide = false;  // shapes past the 64-member, 64-node layout: the wide analysis kernel
   size_t lds = 0;
   int32_t off[9] = {0};      // LDS layout of the adjoint's forward stages
   int32_t fwd_off[9] = {0};  // LDS layout of the analysis
@@ -388,8 +393,8 @@ int plan_instance(const letkf_config &c, InstGeom &g, std::string &err) {
       extra.erase(std::unique(extra.begin(), extra.end()), extra.end());
       for (int nd : extra)
         if (std::find(own.begin(), own.end(), nd) == own.end()) patch.push_back(nd);
-      if (patch.size() > (size_t)kMaxPatch || obs.size() > (size_t)kMaxObsSub) {
-        err = "domain patch exceeds 64 nodes or 64 observation subapertures";
+      if (patch.size() > (size_t)kMaxPatchWide || obs.size() > (size_t)kMaxObsSubWide) {
+        err = "domain patch exceeds 128 nodes or 100 observation subapertures";
         return LETKF_E_INVAL;
       }
       std::vector<uint32_t> corners;
@@ -553,10 +558,10 @@ int validate(const letkf_config &c, int idx, std::string &err) {
   std::ostringstream o;
   o << "instance " << idx << ": ";
   if (c.n_sub < 1 || c.n_sub > 4096) err = o.str() + "n_sub out of range";
-  else if (c.m < 2 || c.m > 64) err = o.str() + "m must be in [2, 64]";
+  else if (c.m < 2 || c.m > kMaxMembers) err = o.str() + "m must be in [2, 128]";
   else if (c.domain_size < 1) err = o.str() + "domain_size must be >= 1";
   else if (c.halo < 0) err = o.str() + "halo must be >= 0";
-  else if (c.domain_size + 2 * c.halo > 7) err = o.str() + "domain_size + 2*halo must be <= 7";
+  else if (c.domain_size + 2 * c.halo > 10) err = o.str() + "domain_size + 2*halo must be <= 10";
   else if (!(c.rho > 0)) err = o.str() + "rho must be > 0";
   else if (!(c.r_scale > 0)) err = o.str() + "r_scale must be > 0";
   else if (!c.r_diag && !(c.r_sigma2 > 0)) err = o.str() + "r_sigma2 must be > 0";
@@ -825,7 +830,7 @@ int graph_step(letkf_handle *h, const void *V, const void *y, hipStream_t s) {
     args.assign((unsigned char *)&A, (unsigned char *)&A + sizeof(A));
   }
   hipKernelNodeParams kp{};
-  kp.blockDim = dim3(letkf_analysis_threads());
+  kp.blockDim = dim3(letkf_analysis_threads_for(h->transform));
   kp.gridDim = dim3(grid_for(h));
   kp.func = (void *)letkf_analysis_kernel(h->fp64, 1, h->transform);
   kp.sharedMemBytes = (unsigned)h->lds;
@@ -1219,6 +1224,49 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
       h->cl_off[1] = h->cl_off[0];
       h->lds = align16(h->cl_off[0] + ((size_t)h->max_patch + 1) * ld * 8);
     }
+  }
+  // Shapes past 64 members or past the 64-node patch run the wide analysis
+  // (8 wavefronts a work item, the FP64 P-form iteration); it has the
+  // delay-free AR(1) phase model with the concatenating gather only.
+  h->wide = h->max_m > kLanes || h->max_patch > kMaxPatch || h->max_obs_sub > kMaxObsSub;
+  if (h->wide) {
+    std::string why;
+    if (h->any_loop) why = "the closed-loop model";
+    else if (h->any_ar2) why = "the AR(2) model";
+    else if (h->any_refit) why = "the online refit";
+    else if (h->any_blend) why = "the blend-mode gather";
+    else if (h->transform == kAnalysisCl) why = "covariance localisation";
+    else if (h->transform == LETKF_TRANSFORM_EVD || h->transform == LETKF_TRANSFORM_NS32)
+      why = "the EVD and NS32 transforms (it runs the P-form iteration in FP64)";
+    if (!why.empty()) {
+      free_handle(h);
+      return fail(LETKF_E_INVAL, "more than 64 members or a patch of more than 64 nodes runs the wide analysis, "
+                                 "which has no " + why);
+    }
+    const int nb = std::max(4, (h->max_m + 15) / 16), M = 16 * nb;
+    h->transform = kAnalysisWide + nb;
+    // small arrays, then the patch rows (row stride M + 1); the Gram's
+    // 16-slope operand after them.  From the transform on: V in place of the
+    // first owned-row blocks, its second buffer and the stored upper block
+    // triangle of P after them, over the dead patch rows and operand.
+    const size_t T = h->esize, XS = M + 1, YS = M + 1;
+    const size_t vrows = (size_t)16 * ((h->max_own + 15) / 16);
+    size_t f = 0;
+    h->fwd_off[5] = (int32_t)f; f = align16(f + letkf_wide_pn_ints() * 4);
+    h->fwd_off[6] = (int32_t)f; f = align16(f + letkf_wide_scratch_doubles() * 8);
+    h->fwd_off[1] = (int32_t)f; f = align16(f + (size_t)kMaxPatchWide * 8);
+    h->fwd_off[2] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * 8);
+    h->fwd_off[3] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * 8);
+    h->fwd_off[4] = (int32_t)f; f = align16(f + 2 * (size_t)h->max_obs_sub * 8);
+    h->fwd_off[0] = (int32_t)f;
+    const size_t xrows = std::max((size_t)h->max_patch, vrows) * XS * T;
+    h->fwd_off[8] = (int32_t)align16(f + xrows);
+    const size_t end1 = h->fwd_off[8] + (size_t)16 * YS * 8;
+    h->cl_off[0] = (int32_t)align16(f + vrows * XS * T);
+    h->cl_off[1] = h->cl_off[0];
+    h->fwd_off[7] = (int32_t)align16(h->cl_off[0] + vrows * XS * T);
+    const size_t end2 = h->fwd_off[7] + letkf_wide_tri_bytes(nb);
+    h->lds = align16(std::max(end1, end2));
   }
   {  // the adjoint kernel: a larger U area (FP64 64 x 64), Q, a second matrix, scratch
     size_t oa = align16(o + std::max(u, (size_t)64 * 65 * 8));
@@ -2041,6 +2089,7 @@ int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, u
   if (h->any_blend) return fail(LETKF_E_INVAL, "no adjoint for the blend-mode gather");
   if (h->transform == kAnalysisCl) return fail(LETKF_E_INVAL, "no adjoint for covariance localisation");
   if (h->any_refit) return fail(LETKF_E_INVAL, "no adjoint with the online refit");
+  if (h->wide) return fail(LETKF_E_INVAL, "no adjoint for the wide analysis (m > 64 or a patch over 64 nodes)");
   int rc = check_noise(h, V_dev);
   if (rc) return rc;
   hipSetDevice(h->device);
@@ -2100,6 +2149,7 @@ int letkf_adjoint_noalloc(letkf_handle *h, const void *xa_prev_dev, const void *
   if (h->any_blend) return fail(LETKF_E_INVAL, "no adjoint for the blend-mode gather");
   if (h->transform == kAnalysisCl) return fail(LETKF_E_INVAL, "no adjoint for covariance localisation");
   if (h->any_refit) return fail(LETKF_E_INVAL, "no adjoint with the online refit");
+  if (h->wide) return fail(LETKF_E_INVAL, "no adjoint for the wide analysis (m > 64 or a patch over 64 nodes)");
   if (!h->adj_ok)
     return fail(LETKF_E_INVAL, "the adjoint needs more LDS per workgroup than the device allows");
   int rc = check_noise(h, V_dev);

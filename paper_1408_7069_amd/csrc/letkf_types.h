@@ -11,6 +11,10 @@ constexpr int kMaxPatch = 64;     // owned nodes + every corner of the region
 constexpr int kYsStride = 80;     // row stride of K-major MFMA operands (no bank conflicts)
 constexpr int kXsStride = 65;     // row stride of node rows (lane = row reads)
 constexpr int kAnalysisCl = 8;    // analysis-kernel selector of covariance localisation (after the transforms)
+constexpr int kAnalysisWide = 16;  // selector of the wide-shape analysis: kAnalysisWide + its 16-column blocks
+constexpr int kMaxPatchWide = 128;  // node patch of the wide analysis ((b + 2h + 1)^2 <= 121)
+constexpr int kMaxObsSubWide = 100; // its observation subapertures ((b + 2h)^2 <= 100)
+constexpr int kMaxMembers = 128;    // ensemble size of the wide analysis
 constexpr int kClXtStride = 66;   // covariance localisation: row stride of the FP64 transposed patch
 
 // One adaptive-optics instance.

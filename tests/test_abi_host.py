@@ -27,8 +27,9 @@ def test_strerror_and_codes():
         assert binding.lib.letkf_strerror(code) != b"unknown error"
 
 
-@pytest.mark.parametrize("bad", [dict(m=1), dict(m=65), dict(rho=0.0), dict(r_scale=-1.0),
-                                 dict(domain_size=0), dict(halo=-1), dict(domain_size=4, halo=2),
+@pytest.mark.parametrize("bad", [dict(m=1), dict(m=129), dict(rho=0.0), dict(r_scale=-1.0),
+                                 dict(domain_size=0), dict(halo=-1), dict(domain_size=6, halo=3),
+                                 dict(domain_size=11, halo=0),
                                  dict(r_sigma2=0.0), dict(obscuration=1.0), dict(taper_c=-1.0)])
 def test_invalid_configs_are_rejected(bad):
     spec = binding.InstanceSpec(n_sub=8, m=16, domain_size=2, halo=1)
@@ -47,7 +48,10 @@ def test_bank_shape_is_validated():
 
 
 CASES = [(8, None, 2, 1), (12, 0.28, 4, 1), (40, 0.14, 4, 1), (80, 0.28, 4, 1), (13, 0.3, 3, 2),
-         (17, 0.0, 5, 1), (5, None, 1, 0), (1, None, 1, 0), (33, 0.1, 4, 0)]
+         (17, 0.0, 5, 1), (5, None, 1, 0), (1, None, 1, 0), (33, 0.1, 4, 0),
+         # the wide shapes: the paper's 4 x 4 domains with a halo of 2, and
+         # domain size plus twice the halo at its limit of 10
+         (80, 0.28, 4, 2), (24, 0.28, 6, 2), (30, None, 10, 0), (21, 0.2, 2, 4)]
 
 
 @pytest.mark.parametrize("N,eps,b,h", CASES)

@@ -205,3 +205,34 @@ def test_one_frame_adjoint_at_full_size(fp64):
         scale = np.array([c.prm.rho, c.prm.r_scale, c.prm.taper_c])
         assert rel_err(scale * g, scale * gk) <= 1e-3, (g, gk)
         assert np.all(_grad_err(g, gk) <= 1e-2), (g, gk)
+
+
+def test_full_size_gradient_over_200_frames():
+    # the tuning run at full size: 80x80, 28 % obscuration, m = 64, taper
+    # c = 2, T = 200 frames with a checkpoint every 20, bank noise.  The FP64
+    # gradient against central differences of the GPU loss (relative step
+    # 1e-4) at 1e-3 per component; the FP32 handle's gradient on the same
+    # inputs against it at 1e-3 of the largest log-parameter derivative
+    # theta_i dJ/dtheta_i.
+    r64, r32 = Run(True, T=200, N=80, seed=44), Run(False, T=200, N=80, seed=44)
+    f = B().Letkf([r64.c.spec(B())])
+    th = r64.theta()
+    r64.gpu(f, th, every=20).sum().backward()
+    g64 = th.grad.numpy().copy()
+    h = 1e-4
+    fd = np.zeros(3)
+    for i in range(3):
+        vals = []
+        for s in (1.0, -1.0):
+            t2 = th.detach().clone()
+            t2[i] *= 1.0 + s * h
+            with torch.no_grad():
+                vals.append(r64.gpu(f, t2, every=20).item())
+        fd[i] = (vals[0] - vals[1]) / (2 * h * th[i].item())
+    err = _grad_err(g64, fd)
+    assert np.all(err <= 1e-3), (g64, fd, err)
+    f32 = B().Letkf([r32.c.spec(B())])
+    t32 = r32.theta()
+    r32.gpu(f32, t32, every=20).sum().backward()
+    scale = th.detach().numpy()
+    assert rel_err(scale * t32.grad.numpy(), scale * g64) <= 1e-3, (t32.grad, g64)

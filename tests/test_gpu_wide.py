@@ -1,0 +1,222 @@
+"""The wide analysis (more than 64 members, or node patches past 64 nodes:
+m <= 128, domain size plus twice the halo <= 10) on the GPU against the FP64
+oracle, through the C ABI: the shape of the paper's timings (m = 101, 4 x 4
+domains with a halo of 2, up to 128 local slopes; Sec. 5.3, Tables 1-2) in
+both precisions on a 24x24 and the full 80x80 pupil, every 16-column count
+from m = 65 to m = 128, the patch at its limit, each launch path and work
+order, mixed instances, the taper, the pistons, a non-finite slope, and what
+the wide analysis refuses.
+
+Bars as for the 64-member frame: FP64 handles 1e-10, FP32 handles 1e-4 in
+max relative error of the ensemble; launch paths and work orders bitwise."""
+import numpy as np
+import pytest
+
+from _cases import Case, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def B():
+    from paper_1408_7069_amd import binding
+    return binding
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a).ravel()).to(DEV)
+
+
+def _ens(f, m):
+    return f.get_ensemble().cpu().numpy().astype(np.float64).reshape(-1, m)
+
+
+def _frames(case, f, T, tol, bank=False, X0=None):
+    Xa = np.zeros((case.G.n_nodes, case.m)) if X0 is None else np.asarray(X0, np.float64)
+    if X0 is not None:
+        f.set_ensemble(_t(np.asarray(X0, case.dt)))
+    for k in range(T):
+        y = case.slopes(case.truth())
+        if bank:
+            frame = f.get_frame()
+            f.step(_t(y), V=None)
+            V = case.bank_V(frame)
+        else:
+            V = case.noise()
+            f.step(_t(y), V=_t(V))
+        torch.cuda.synchronize()
+        got = _ens(f, case.m)
+        ref = case.oracle_analysis(case.prm.a * Xa + np.asarray(V, np.float64), y)
+        assert rel_err(got.mean(1), ref.mean(1)) <= tol, k
+        assert rel_err(got, ref) <= tol, k
+        Xa = ref
+    rc, flags = f.status()
+    assert rc == 0 and not (flags & 3).any()
+    assert ((flags >> 8) > 0).all()
+    return Xa
+
+
+@pytest.mark.parametrize("fp64,tol,piston", [(True, 1e-10, False), (True, 1e-10, True),
+                                             (False, 1e-4, False), (False, 1e-4, True)])
+def test_paper_shape_frames(fp64, tol, piston):
+    # 24x24, 28 % obscuration, 4x4 domains with a halo of 2 (patches of up to
+    # 77 nodes and 120 local slopes at this size), m = 101
+    case = Case(24, 0.28, 4, 2, 101, seed=70, fp64=fp64, piston=piston)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    assert f.sizes["max_patch"] == 77 and f.sizes["max_obs"] == 120
+    _frames(case, f, 3, tol)
+
+
+@pytest.mark.parametrize("fp64,tol", [(True, 1e-10), (False, 1e-4)])
+def test_paper_shape_full_size_with_bank_noise(fp64, tol):
+    # the full 80x80 pupil at the paper's shape, bank noise, pistons, in the
+    # launch configuration the benchmark times (graph replay, tuned order)
+    case = Case(80, 0.28, 4, 2, 101, seed=71, fp64=fp64, piston=True)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    # 332 domains; inside the pupil 8 x 8 observation subapertures (p_l = 128)
+    # and 9 x 9 patch nodes
+    assert f.sizes["n_domains"] == 332 and f.sizes["max_obs"] == 128 and f.sizes["max_patch"] == 81
+    X0 = (case.rng.standard_normal((case.G.n_nodes, 101)) * 0.3).astype(case.dt)
+    _frames(case, f, 2, tol, bank=True, X0=X0)
+
+
+@pytest.mark.parametrize("m", [65, 80, 96, 112, 128])
+@pytest.mark.parametrize("fp64,tol", [(True, 1e-10), (False, 1e-4)])
+def test_every_column_block_count(m, fp64, tol):
+    case = Case(12, 0.28, 4, 1, m, seed=72 + m, fp64=fp64)
+    f = B().Letkf([case.spec(B())])
+    _frames(case, f, 2, tol)
+
+
+@pytest.mark.parametrize("fp64,tol", [(True, 1e-10), (False, 1e-4)])
+@pytest.mark.parametrize("N,eps,b,h,m", [(24, 0.28, 6, 2, 48), (21, 0.2, 2, 4, 40), (16, None, 3, 3, 70)])
+def test_patch_at_its_limit(N, eps, b, h, m, fp64, tol):
+    # domain size plus twice the halo = 10 (patches of up to 121 nodes,
+    # 100 observation subapertures), also with m <= 64
+    case = Case(N, eps, b, h, m, seed=80 + b, fp64=fp64, taper_c=1.5)
+    f = B().Letkf([case.spec(B())])
+    assert f.sizes["max_patch"] > 64
+    _frames(case, f, 2, tol)
+
+
+def test_owned_block_of_121_nodes():
+    # 10x10 domains without a halo: 121 owned rows (eight row blocks of V);
+    # FP32 fits the LDS, FP64 is refused with the sizes
+    case = Case(30, None, 10, 0, 32, seed=90)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    assert f.sizes["max_owned"] == 121
+    _frames(case, f, 2, 1e-4)
+    with pytest.raises(bb.LetkfError) as e:
+        bb.Letkf([case.spec(bb, precision=bb.FP64)])
+    assert e.value.code == bb.E_INVAL and "LDS" in str(e.value)
+
+
+def test_launch_paths_and_orders_agree_bitwise():
+    case = Case(16, 0.28, 4, 2, 101, seed=73, piston=True)
+    bb = B()
+    X0 = (case.rng.standard_normal((case.G.n_nodes, case.m)) * 0.5).astype(np.float32)
+    V, y = case.noise(), case.slopes(case.truth())
+    outs = []
+    for path, order in (("graph", bb.ORDER_ROW), ("graph", bb.ORDER_XCD), ("graph", bb.ORDER_XCD_PAIRED),
+                        ("direct", bb.ORDER_ROW), ("direct", bb.ORDER_XCD_PAIRED), ("plain", bb.ORDER_ROW),
+                        ("split", bb.ORDER_ROW)):
+        f = bb.Letkf([case.spec(bb)])
+        f.set_schedule(path == "graph", order)
+        for _ in range(2):
+            f.set_ensemble(_t(X0))
+            if path == "plain":
+                f.step_plain(_t(y), V=_t(V))
+            elif path == "split":
+                f.forecast(_t(V))
+                f.analyse(_t(y))
+            else:
+                f.step(_t(y), V=_t(V))
+        torch.cuda.synchronize()
+        outs.append(f.get_ensemble().cpu().numpy())
+        f.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    ref = case.oracle_analysis(case.prm.a * X0.astype(np.float64) + V.astype(np.float64), y)
+    assert rel_err(outs[0].astype(np.float64).reshape(-1, case.m), ref) <= 1e-4
+
+
+def test_autotune_on_a_wide_handle_is_bitwise_neutral():
+    case = Case(16, 0.28, 4, 2, 101, seed=74)
+    bb = B()
+    f, g = bb.Letkf([case.spec(bb)]), bb.Letkf([case.spec(bb)])
+    y = case.slopes(case.truth())
+    f.autotune(_t(y), frames=3)
+    assert f.get_frame() == 0
+    for h in (f, g):
+        h.step(_t(y))
+    torch.cuda.synchronize()
+    assert np.array_equal(f.get_ensemble().cpu().numpy(), g.get_ensemble().cpu().numpy())
+
+
+def test_mixed_instances_in_one_wide_launch():
+    # one instance at m = 101 makes every instance of the handle run wide
+    c0 = Case(12, 0.28, 4, 2, 101, seed=75, piston=True)
+    c1 = Case(10, None, 2, 1, 40, seed=76)
+    c2 = Case(14, 0.2, 3, 1, 128, seed=77, taper_c=2.0)
+    bb = B()
+    cases = [c0, c1, c2]
+    f = bb.Letkf([c.spec(bb) for c in cases])
+    Vs = [c.noise() for c in cases]
+    ys = [c.slopes(c.truth()) for c in cases]
+    f.step(_t(np.concatenate(ys)), V=_t(np.concatenate([v.ravel() for v in Vs])))
+    torch.cuda.synchronize()
+    flat = f.get_ensemble().cpu().numpy().astype(np.float64)
+    off = 0
+    for c, V, y in zip(cases, Vs, ys):
+        n = c.G.n_nodes * c.m
+        got = flat[off:off + n].reshape(-1, c.m)
+        off += n
+        ref = c.oracle_analysis(np.asarray(V, np.float64), y)
+        assert rel_err(got, ref) <= 1e-4
+
+
+def test_nonfinite_slope_keeps_the_forecast():
+    case = Case(16, 0.28, 4, 2, 101, seed=78, fp64=True)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    X0 = case.rng.standard_normal((case.G.n_nodes, case.m)) * 0.5
+    f.set_ensemble(_t(X0))
+    V, y = case.noise(), case.slopes(case.truth())
+    y[5] = np.nan
+    f.step(_t(y), V=_t(V))
+    torch.cuda.synchronize()
+    rc, flags = f.status()
+    hit = [k for k, d in enumerate(case.doms) if 5 in d.obs]
+    assert hit and all(flags[k] & 1 for k in hit)
+    got = _ens(f, case.m)
+    Xb = case.prm.a * X0 + V
+    for k in hit:
+        own = case.doms[k].owned
+        assert rel_err(got[own], Xb[own]) <= 1e-15   # (the forecast's fma rounds once)
+
+
+@pytest.mark.parametrize("kw", [dict(model=1), dict(ar2_coeff=0.1), dict(refit_forgetting=0.9),
+                                dict(gather_mode=1, piston=False), dict(localisation=1),
+                                dict(transform=2), dict(transform=1)])
+def test_what_the_wide_analysis_refuses(kw):
+    case = Case(12, 0.28, 4, 2, 101, seed=79)
+    bb = B()
+    with pytest.raises(bb.LetkfError) as e:
+        bb.Letkf([case.spec(bb, **kw)])
+    assert e.value.code == bb.E_INVAL
+
+
+def test_no_adjoint_on_a_wide_handle():
+    case = Case(12, 0.28, 4, 1, 80, seed=81)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    xa = torch.zeros(f.sizes["ensemble_elems"], dtype=torch.float32, device=DEV)
+    y = _t(case.slopes(case.truth()))
+    th = torch.zeros(3, dtype=torch.float64, device=DEV)
+    with pytest.raises(bb.LetkfError):
+        f.adjoint(xa, y, torch.zeros_like(xa), th, 0, V=_t(case.noise()))
