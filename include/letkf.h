@@ -128,7 +128,8 @@ typedef struct letkf_config {
                                   valid when > 50 % of the subaperture lies in
                                   eps*N/2 <= r <= N/2 (Sec. 5), 64x64 sampling    */
   double obscuration;          /* eps, used when subap_mask == NULL                */
-  int32_t m;                   /* ensemble size, 2 <= m <= 64                      */
+  int32_t m;                   /* ensemble size, 2 <= m <= 128 (past 64: the wide
+                                  analysis, see letkf_create)                      */
   int32_t domain_size;         /* b: domains are b x b subaperture blocks (Sec. 4.1) */
   int32_t halo;                /* h >= 0: observation region = block grown by h    */
   double rho;                  /* multiplicative inflation > 0                     */
@@ -242,11 +243,23 @@ typedef struct letkf_sizes {
 /* Build the geometry of every instance on the host (pupil mask, node and slope
  * numbering, b x b domains with halo h, taper distances, a work list in
  * instance-major, row-major domain order) and allocate the device state on `device`.  The ensemble starts at
- * zero (Sec. 3.1: X_{1/0} = 0).  Returns LETKF_E_INVAL for m < 2 or m > 64,
- * rho <= 0, r_scale <= 0, any r <= 0, b < 1, h < 0, b + 2h > 7 (a domain's
- * node patch must fit one 64-lane wavefront),
+ * zero (Sec. 3.1: X_{1/0} = 0).  Returns LETKF_E_INVAL for m < 2 or m > 128,
+ * rho <= 0, r_scale <= 0, any r <= 0, b < 1, h < 0, b + 2h > 10,
  * an instance with no valid subaperture, or a bank that is not a power of two
- * wide or is narrower than N + 1. */
+ * wide or is narrower than N + 1.
+ *
+ * Wide analysis.  A handle in which some instance has m > 64, a node patch of
+ * more than 64 nodes or more than 64 observation subapertures (for instance
+ * the paper's timing shape, Sec. 5.3 Tables 1-2: m = 101, b = 4, h = 2: 9 x 9
+ * patch nodes, 128 local slopes) runs every local analysis on the wide kernel:
+ * 8 wavefronts a domain, the Gram in FP64, the P-form iteration in FP64
+ * whatever `transform` names (NS64, NSP and NSP_MIXED are accepted).  Such a
+ * handle has the delay-free AR(1) phase model with the concatenating gather
+ * only: the closed loop, AR(2), the online refit, the blend gather, covariance
+ * localisation and the EVD/NS32 transforms give LETKF_E_INVAL, and so does
+ * letkf_adjoint.  LETKF_E_INVAL also when the layout of the largest domain
+ * does not fit the LDS of one workgroup (FP64 with more than about 96 owned
+ * nodes, e.g. 10 x 10 domains without a halo). */
 int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device,
                  letkf_handle **out);
 void letkf_destroy(letkf_handle *h);
@@ -442,9 +455,10 @@ int letkf_residual_variance_adjoint(letkf_handle *h, const void *xa_dev, const v
  * runs the Jacobi to min(jacobi_tol, 1e-6) (the forward's transform W only
  * needs the looser default).  Returns LETKF_E_INVAL when the device cannot
  * give the adjoint kernel its LDS, and for handles with a closed-loop
- * instance, an AR(2) model, the online refit, the blend-mode gather or
- * covariance localisation (the frame it reverses is the delay-free AR(1) one
- * with the local analysis and the concatenation). */
+ * instance, an AR(2) model, the online refit, the blend-mode gather,
+ * covariance localisation or the wide analysis (the frame it reverses is the
+ * delay-free AR(1) one with the 64-member local analysis and the
+ * concatenation). */
 int letkf_adjoint(letkf_handle *h, const void *xa_prev_dev, const void *V_dev, uint32_t frame,
                   const void *y_dev, void *xbar_dev, double *theta_bar_dev, void *stream);
 

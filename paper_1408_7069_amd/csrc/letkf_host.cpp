@@ -73,6 +73,7 @@ extern "C" int letkf_analysis_threads_for(int eig);
 extern "C" size_t letkf_wide_scratch_doubles(void);
 extern "C" size_t letkf_wide_pn_ints(void);
 extern "C" size_t letkf_wide_tri_bytes(int nb);
+extern "C" size_t letkf_resvar_stats_doubles(int n_inst);
 extern "C" size_t letkf_analysis_scratch_doubles(void);
 extern "C" size_t letkf_analysis_fwd_scratch_doubles(void);
 extern "C" size_t letkf_analysis_xch_bytes(void);
@@ -1489,7 +1490,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
       (rc = to_device(&h->d_node_adj, node_adj)) || (rc = to_device(&h->d_slot_off, slot_off)) ||
       (rc = to_device(&h->d_slots, slots)) || (rc = to_device(&h->d_dom_base, dom_base)) ||
       (rc = to_device(&h->d_ones, std::vector<double>((size_t)n_instances, 1.0))) ||
-      (rc = to_device(&h->d_stats, std::vector<double>(2 * (size_t)n_instances, 0.0))) ||
+      (rc = to_device(&h->d_stats, std::vector<double>(letkf_resvar_stats_doubles(n_instances), 0.0))) ||
       (rc = to_device(&h->d_owner_item, owner_item)) || (rc = to_device(&h->d_minv_off, minv_off)) ||
       (rc = to_device(&h->d_minv, minv)) ||
       (rc = to_device(&h->d_prhs, std::vector<double>(std::max<size_t>(h->items.size(), 1), 0.0))) ||

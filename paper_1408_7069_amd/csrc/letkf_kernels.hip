@@ -1166,6 +1166,10 @@ template <typename TV, bool F32>
 __device__ __forceinline__ bool nsp_step(double *Pd, double *Qd, TV *V, int ncb, double *hb, double *sm,
                                          double tol, int max_it, bool may32, NspState &S, int q, int lane,
                                          int rot) {
+  // (the lane index made opaque a step: the lane-dependent diagonal selects
+  // and addresses are formed where used rather than hoisted out of the step
+  // loops, where the two loops of the mixed form would hold both sets)
+  asm volatile("" : "+v"(lane));
   const int c16 = lane & 15, g = lane >> 4;
   const int n1 = ((q - rot) & 3) < 2 ? 3 : 2, n2 = ((q - rot - 2) & 3) < 2 ? 3 : 2;  // tiles of P^2, of P^3
   const double al = 3.0 / (1.0 + sqrt(S.l) + S.l), sa = sqrt(al);
@@ -2607,41 +2611,66 @@ __global__ void k_adjoint_nodes(const InstDesc *insts, const int32_t *node_adj,
 }
 
 // Sum over the threads of a 256-thread block (result in every thread).
-__device__ inline double block_sum(double v, double *red) {
-  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  v = wave_sum(v);
-  __syncthreads();
-  if (lane == 0) red[q] = v;
-  __syncthreads();
-  return (red[0] + red[1]) + (red[2] + red[3]);
+// Residual variance of the analysis mean against the true phase:
+// stats[2 i] = mean error, stats[2 i + 1] = variance; acc[i] += weights[i] *
+// variance when acc is given.  k_resvar_part: kResvarBlocks workgroups per
+// instance (blockIdx.y), each a contiguous run of nodes, one wavefront per
+// node (lanes over the members); it sums d = e - e_0 and d^2, e the node's
+// error and e_0 node 0's (every workgroup forms e_0 alike: the shift keeps
+// the one-pass variance clear of cancellation when the mean error is large
+// against the spread).  k_resvar_finish adds the partial sums in a fixed
+// order.  Deterministic for any launch.
+constexpr int kResvarBlocks = 64;
+
+template <typename T>
+__device__ inline double node_error(const InstDesc &in, const T *x, const T *truth, int g, int lane) {
+  const int m = in.m;
+  double v = 0.0;
+  for (int k = lane; k < m; k += 64) v += (double)x[in.x_off + (int64_t)g * m + k];
+  return wave_sum(v) / (double)m - (double)truth[in.node_off + g];
 }
 
-// Residual variance of the analysis mean against the true phase, one block per
-// instance: stats[2 i] = mean error, stats[2 i + 1] = variance; acc[i] +=
-// weights[i] * variance when acc is given.
 template <typename T>
-__global__ __launch_bounds__(256) void k_resvar(const InstDesc *insts, const T *x, const T *truth,
-                                               const double *weights, double *stats, double *acc) {
-  __shared__ double red[4];
-  const InstDesc in = insts[blockIdx.x];
-  const int n = in.n_nodes, m = in.m;
-  double s1 = 0.0;
-  for (int g = threadIdx.x; g < n; g += 256) {
-    double s = 0.0;
-    for (int j = 0; j < m; ++j) s += (double)x[in.x_off + (int64_t)g * m + j];
-    s1 += s / (double)m - (double)truth[in.node_off + g];
+__global__ __launch_bounds__(256) void k_resvar_part(const InstDesc *insts, const T *x, const T *truth,
+                                                    double *part) {
+  __shared__ double red[8];
+  const InstDesc in = insts[blockIdx.y];
+  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n = in.n_nodes, per = (n + kResvarBlocks - 1) / kResvarBlocks;
+  const int g0 = (int)blockIdx.x * per, g1 = min(n, g0 + per);
+  const double e0 = node_error(in, x, truth, 0, lane);
+  double s1 = 0.0, s2 = 0.0;
+  for (int g = g0 + q; g < g1; g += 4) {
+    const double d = node_error(in, x, truth, g, lane) - e0;
+    s1 += d;
+    s2 = fma(d, d, s2);
   }
-  const double ebar = block_sum(s1, red) / (double)n;
-  double s2 = 0.0;
-  for (int g = threadIdx.x; g < n; g += 256) {
-    double s = 0.0;
-    for (int j = 0; j < m; ++j) s += (double)x[in.x_off + (int64_t)g * m + j];
-    const double e = s / (double)m - (double)truth[in.node_off + g] - ebar;
-    s2 += e * e;
+  if (lane == 0) {
+    red[2 * q] = s1;
+    red[2 * q + 1] = s2;
   }
-  const double var = block_sum(s2, red) / (double)n;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    stats[2 * blockIdx.x] = ebar;
+    double* o = part + 2 * ((int64_t)blockIdx.y * kResvarBlocks + blockIdx.x);
+    o[0] = (red[0] + red[2]) + (red[4] + red[6]);
+    o[1] = (red[1] + red[3]) + (red[5] + red[7]);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_resvar_finish(const InstDesc *insts, const T *x, const T *truth,
+                                                     const double *part, const double *weights, double *stats,
+                                                     double *acc) {
+  const InstDesc in = insts[blockIdx.x];
+  const int lane = threadIdx.x;
+  const double e0 = node_error(in, x, truth, 0, lane);
+  const double *pp = part + 2 * (int64_t)blockIdx.x * kResvarBlocks;
+  const double s1 = wave_sum(lane < kResvarBlocks ? pp[2 * lane] : 0.0);
+  const double s2 = wave_sum(lane < kResvarBlocks ? pp[2 * lane + 1] : 0.0);
+  const double n = (double)in.n_nodes, dbar = s1 / n;
+  const double var = fma(-dbar, dbar, s2 / n);
+  if (lane == 0) {
+    stats[2 * blockIdx.x] = e0 + dbar;
     stats[2 * blockIdx.x + 1] = var;
     if (acc) acc[blockIdx.x] += weights[blockIdx.x] * var;
   }
@@ -2664,16 +2693,20 @@ __global__ void k_resvar_adjoint(const InstDesc *insts, const T *x, const T *tru
   for (int k = lane; k < m; k += 64) xbar[e + k] = (T)((double)xbar[e + k] + coef);
 }
 
-// theta_acc[3 i + t] += sum over the items of instance i of theta[4 item + t],
-// in item order.
-__global__ void k_theta_sum(const int32_t *dom_base, int n_inst, const double *theta,
-                            double *theta_acc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 3 * n_inst) return;
-  const int inst = i / 3, t = i % 3;
+// theta_acc[3 i + t] += sum over the items of instance i of theta[4 item + t]:
+// one workgroup per (t, instance), strided partial sums and a fixed-order
+// tree (deterministic).
+__global__ __launch_bounds__(256) void k_theta_sum(const int32_t *dom_base, int n_inst, const double *theta,
+                                                  double *theta_acc) {
+  __shared__ double red[4];
+  const int t = blockIdx.x, inst = blockIdx.y;
+  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int k = dom_base[inst]; k < dom_base[inst + 1]; ++k) s += theta[4 * (int64_t)k + t];
-  theta_acc[i] += s;
+  for (int k = dom_base[inst] + (int)threadIdx.x; k < dom_base[inst + 1]; k += 256) s += theta[4 * (int64_t)k + t];
+  s = wave_sum(s);
+  if (lane == 0) red[q] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) theta_acc[3 * inst + t] += (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // ------------------------------------------------- differential pistons
@@ -3382,15 +3415,25 @@ extern "C" hipError_t letkf_launch_adjoint_nodes(int fp64, const InstDesc *insts
   return hipGetLastError();
 }
 
+// Doubles of the stats buffer letkf_launch_resvar needs for n_inst instances.
+extern "C" size_t letkf_resvar_stats_doubles(int n_inst) { return (size_t)2 * n_inst * (1 + kResvarBlocks); }
+
 extern "C" hipError_t letkf_launch_resvar(int fp64, const InstDesc *insts, int n_inst, const void *x,
                                           const void *truth, const double *weights, double *stats,
                                           double *acc, hipStream_t s) {
-  if (fp64)
-    hipLaunchKernelGGL(k_resvar<double>, dim3(n_inst), dim3(256), 0, s, insts, (const double *)x,
-                       (const double *)truth, weights, stats, acc);
-  else
-    hipLaunchKernelGGL(k_resvar<float>, dim3(n_inst), dim3(256), 0, s, insts, (const float *)x,
-                       (const float *)truth, weights, stats, acc);
+  // stats holds 2 n_inst results, then the 2 kResvarBlocks n_inst partial sums
+  double *part = stats + 2 * n_inst;
+  if (fp64) {
+    hipLaunchKernelGGL(k_resvar_part<double>, dim3(kResvarBlocks, n_inst), dim3(256), 0, s, insts,
+                       (const double *)x, (const double *)truth, part);
+    hipLaunchKernelGGL(k_resvar_finish<double>, dim3(n_inst), dim3(64), 0, s, insts, (const double *)x,
+                       (const double *)truth, part, weights, stats, acc);
+  } else {
+    hipLaunchKernelGGL(k_resvar_part<float>, dim3(kResvarBlocks, n_inst), dim3(256), 0, s, insts,
+                       (const float *)x, (const float *)truth, part);
+    hipLaunchKernelGGL(k_resvar_finish<float>, dim3(n_inst), dim3(64), 0, s, insts, (const float *)x,
+                       (const float *)truth, part, weights, stats, acc);
+  }
   return hipGetLastError();
 }
 
@@ -3410,9 +3453,7 @@ extern "C" hipError_t letkf_launch_resvar_adjoint(int fp64, const InstDesc *inst
 
 extern "C" hipError_t letkf_launch_theta_sum(const int32_t *dom_base, int n_inst, const double *theta,
                                              double *theta_acc, hipStream_t s) {
-  const int n = 3 * n_inst;
-  hipLaunchKernelGGL(k_theta_sum, dim3((n + 255) / 256), dim3(256), 0, s, dom_base, n_inst, theta,
-                     theta_acc);
+  hipLaunchKernelGGL(k_theta_sum, dim3(3, n_inst), dim3(256), 0, s, dom_base, n_inst, theta, theta_acc);
   return hipGetLastError();
 }
 
