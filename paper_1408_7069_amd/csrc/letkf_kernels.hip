@@ -1157,6 +1157,72 @@ __device__ __forceinline__ void v_times_t(const TV *V, const CB &Pc, double ta, 
   }
 }
 
+// (M h)_i for row i = 16 q + c16 of a symmetric matrix M in LDS (FP64, row
+// stride kLaStride, or with F32 FP32, stride kNs32Stride): lane group g sums
+// the columns 16 g .. 16 g + 15, rows_sum adds the four groups.
+template <bool F32>
+__device__ __forceinline__ double row_dot(const void *Mv, const double *hb, int i, int g) {
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+  if constexpr (F32) {
+    const float *pr = (const float *)Mv + i * kNs32Stride + 16 * g;
+#pragma unroll
+    for (int j = 0; j < 16; j += 4) {
+      const f32x4 v = *(const f32x4 *)(pr + j);
+      p0 = fma((double)v[0], hb[16 * g + j], p0);
+      p1 = fma((double)v[1], hb[16 * g + j + 1], p1);
+      p2 = fma((double)v[2], hb[16 * g + j + 2], p2);
+      p3 = fma((double)v[3], hb[16 * g + j + 3], p3);
+    }
+  } else {
+    const double *pr = (const double *)Mv + i * kLaStride + 16 * g;
+#pragma unroll
+    for (int j = 0; j < 16; j += 4) {
+      p0 = fma(pr[j], hb[16 * g + j], p0);
+      p1 = fma(pr[j + 1], hb[16 * g + j + 1], p1);
+      p2 = fma(pr[j + 2], hb[16 * g + j + 2], p2);
+      p3 = fma(pr[j + 3], hb[16 * g + j + 3], p3);
+    }
+  }
+  return rows_sum((p0 + p1) + (p2 + p3));
+}
+
+// V M for the member block q: ncb row tiles of V times the column block q of
+// the symmetric matrix M in LDS (FP64 order, or FP32 order and storage with
+// F32), as v_times_t forms V T.
+template <typename TV, bool F32>
+__device__ __forceinline__ void v_times_m(const TV *V, const void *Mv, int ncb, f64x4 Wo[4], int q, int lane) {
+  const int c16 = lane & 15, g = lane >> 4;
+  if constexpr (F32) {
+    ColBlock32 B;
+    f32_load_colblock((const float *)Mv, B, q, lane);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      if (cb < ncb) {
+        const TV *vr = V + (16 * cb + c16) * kXsStride + 4 * g;
+        f32x4 acc = Mfma<float>::zero();
+#pragma unroll
+        for (int J = 0; J < 4; ++J)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc = Mfma<float>::mac((float)vr[16 * J + r], B[J][r], acc);
+        Wo[cb] = f64x4{acc[0], acc[1], acc[2], acc[3]};
+      }
+    }
+  } else {
+    ColBlock B;
+    load_colblock((const double *)Mv, B, q, lane);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      if (cb < ncb) {
+        const TV *vr = V + (16 * cb + c16) * kXsStride + g;
+        f64x4 acc = Mfma<double>::zero();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) acc = Mfma<double>::mac((double)vr[4 * kk], B[kk >> 2][kk & 3], acc);
+        Wo[cb] = acc;
+      }
+    }
+  }
+}
+
 // One step of the P-form iteration with P held in FP64 (Pd; P^2 in Qd) or,
 // with F32, in FP32 (the same areas as float).  Forms T_k applied to V and h
 // and P^2 before the first barrier, stores V and h after it (every read of
@@ -1164,8 +1230,8 @@ __device__ __forceinline__ void v_times_t(const TV *V, const CB &Pc, double ta, 
 // whether P_{k+1} went to FP32.
 template <typename TV, bool F32>
 __device__ __forceinline__ bool nsp_step(double *Pd, double *Qd, TV *V, int ncb, double *hb, double *sm,
-                                         double tol, int max_it, bool may32, NspState &S, int q, int lane,
-                                         int rot) {
+                                         double tol, double tol2, int max_it, bool may32, NspState &S, int q,
+                                         int lane, int rot) {
   // (the lane index made opaque a step: the lane-dependent diagonal selects
   // and addresses are formed where used rather than hoisted out of the step
   // loops, where the two loops of the mixed form would hold both sets)
@@ -1206,33 +1272,8 @@ __device__ __forceinline__ bool nsp_step(double *Pd, double *Qd, TV *V, int ncb,
   f64x4 Vo[4];
   v_times_t<TV, F32, CB>(V, Pc, ta, ncb, Vo, q, lane);
   // h: sqrt(a) (3/2 h - ta P h) for row 16 q + c16 (segment g, summed over lanes)
-  double hn;
-  {
-    const int i = 16 * q + c16;
-    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-    if constexpr (F32) {
-      const float *pr = P32 + i * kNs32Stride + 16 * g;
-#pragma unroll
-      for (int j = 0; j < 16; j += 4) {
-        const f32x4 v = *(const f32x4 *)(pr + j);
-        p0 = fma((double)v[0], hb[16 * g + j], p0);
-        p1 = fma((double)v[1], hb[16 * g + j + 1], p1);
-        p2 = fma((double)v[2], hb[16 * g + j + 2], p2);
-        p3 = fma((double)v[3], hb[16 * g + j + 3], p3);
-      }
-    } else {
-      const double *pr = Pd + i * kLaStride + 16 * g;
-#pragma unroll
-      for (int j = 0; j < 16; j += 4) {
-        p0 = fma(pr[j], hb[16 * g + j], p0);
-        p1 = fma(pr[j + 1], hb[16 * g + j + 1], p1);
-        p2 = fma(pr[j + 2], hb[16 * g + j + 2], p2);
-        p3 = fma(pr[j + 3], hb[16 * g + j + 3], p3);
-      }
-    }
-    const double part = rows_sum(((p0 + p1) + (p2 + p3)) * S.sc);
-    hn = sa * fma(-ta, part, 1.5 * hb[i]);
-  }
+  const int hi = 16 * q + c16;
+  const double th = fma(-ta, row_dot<F32>(F32 ? (const void *)P32 : (const void *)Pd, hb, hi, g) * S.sc, 1.5 * hb[hi]);
   // P^2 on this wave's tiles (q + t, q), t < n1 (not needed after the last step)
   const bool more = S.it + 1 < max_it;
   if (more) {
@@ -1253,20 +1294,58 @@ __device__ __forceinline__ bool nsp_step(double *Pd, double *Qd, TV *V, int ncb,
   const double d2 = sum4(sm + S_RES);
   S.finite = isfinite(d2);
   S.conv = S.finite && 0.75 * d2 <= tol;
+  // second-order finish when the residual is below tol2 (P^2 is at hand):
+  // sqrt(a) (I - E/2 + 3/8 E^2), E = a P - I, in place of sqrt(a) T = sqrt(a)
+  // (I - E/2); with V T and T h known it is sqrt(a) (5/2 X T - 15/8 X + 3/8
+  // a^2 X P^2) for X = V, h.  Its truncation, about 5/16 |E|^3, stays under
+  // the rounding the handle's precision leaves
+  const bool fin2 = S.finite && !S.conv && more && 0.75 * d2 <= tol2;
   ++S.it;
-  // V <- sqrt(a) V T_k (this wave's members), h <- its update
+  bool went32 = false;
+  if (fin2) {
+    f64x4 W2[4];
+    v_times_m<TV, F32>(V, F32 ? (const void *)Q32 : (const void *)Qd, ncb, W2, q, lane);
+    const double q2 = row_dot<F32>(F32 ? (const void *)Q32 : (const void *)Qd, hb, hi, g);
+    const double hold = hb[hi];
+    f64x4 Vold[4];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
-    if (cb < ncb) {
+    for (int cb = 0; cb < 4; ++cb) {
+      if (cb < ncb) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * cb + (F32 ? 4 * g + r : g + 4 * r);
-        V[row * kXsStride + 16 * q + c16] = (TV)(sa * Vo[cb][r]);
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * cb + (F32 ? 4 * g + r : g + 4 * r);
+          Vold[cb][r] = (double)V[row * kXsStride + 16 * q + c16];
+        }
       }
     }
+    __syncthreads();  // every read of V, h and P^2 done
+    const double c2 = 0.375 * al * al;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      if (cb < ncb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * cb + (F32 ? 4 * g + r : g + 4 * r);
+          V[row * kXsStride + 16 * q + c16] = (TV)(sa * fma(c2, W2[cb][r], fma(2.5, Vo[cb][r], -1.875 * Vold[cb][r])));
+        }
+      }
+    }
+    if (g == 0) hb[hi] = sa * fma(c2, q2, fma(2.5, th, -1.875 * hold));
+    S.conv = true;
+  } else {
+    // V <- sqrt(a) V T_k (this wave's members), h <- its update
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      if (cb < ncb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * cb + (F32 ? 4 * g + r : g + 4 * r);
+          V[row * kXsStride + 16 * q + c16] = (TV)(sa * Vo[cb][r]);
+        }
+      }
+    }
+    if (g == 0) hb[hi] = sa * th;
   }
-  if (g == 0) hb[16 * q + c16] = hn;
-  bool went32 = false;
   if (!S.conv && S.finite && more) {
     // P_{k+1} = a (9/4 P - 3/2 a P^2 + 1/4 a^2 P^3) on the tiles (q + t, q),
     // t < n2 (the other role assignment), P^3 = P^2 P, P^2 read back;
@@ -1343,15 +1422,21 @@ __device__ __forceinline__ NspStatus nsp_isqrt(double *area0, double *area1, TV 
   __syncthreads();
   const double s = sqrt(sum4(sm + S_RES));
   NspState S{c / s, 1.0 / s, 0, false, true};
+  // threshold of the second-order finish: with FP32 state the rounding keeps
+  // the result near 1e-6 whatever the truncation below it, so sqrt(tol) (the
+  // residual at 1e-3: a step earlier on the 80x80 domains, no loss); in FP64
+  // tol^(2/3) keeps its truncation, about 5/16 |E|^3, where the first-order
+  // finish at tol leaves its own, 3/8 |E|^2
+  const double tol2 = sizeof(TV) == 4 ? sqrt(tol) : cbrt(tol * tol);
   bool to32 = false;
   for (;;) {
-    to32 = nsp_step<TV, false>(area0, area1, V, ncb, hb, sm, tol, max_it, MIXED, S, q, lane, rot);
+    to32 = nsp_step<TV, false>(area0, area1, V, ncb, hb, sm, tol, tol2, max_it, MIXED, S, q, lane, rot);
     if (S.conv || !S.finite || S.it >= max_it || to32) break;
   }
   if constexpr (MIXED) {
     if (to32 && !S.conv && S.finite && S.it < max_it) {
       for (;;) {
-        nsp_step<TV, true>(area0, area1, V, ncb, hb, sm, tol, max_it, false, S, q, lane, rot);
+        nsp_step<TV, true>(area0, area1, V, ncb, hb, sm, tol, tol2, max_it, false, S, q, lane, rot);
         if (S.conv || !S.finite || S.it >= max_it) break;
       }
     }

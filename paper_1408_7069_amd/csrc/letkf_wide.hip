@@ -276,6 +276,8 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
   // ---- 4.-6. P-form iteration ----
   double *hb = sm + W_H;
   const double tol = A.jtol * 0.01;
+  // threshold of the second-order finish (the 64-member kernel's rule)
+  const double tol2 = sizeof(T) == 4 ? sqrt(tol) : cbrt(tol * tol);
   const int max_it = A.max_sweeps;
   double l = c / s;
   int nit = 0;
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
     asm volatile("" : "+v"(dq));
     T *Vc = (nit & 1) ? xs1 : xs, *Vn = (nit & 1) ? xs : xs1;
     f64x4 Pc[NB];
-    double e2 = 0.0, hn = 0.0;
+    double e2 = 0.0, th = 0.0, hold = 0.0, q2 = 0.0;
     if (act) {
       load_cb<NB>(Pp, Pc, q, lane);
 #pragma unroll
@@ -322,7 +324,8 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) part = fma(Pc[K][r], hb[16 * K + g + 4 * r], part);
       part = col_sum(part);
-      hn = sa * fma(-ta, part, 1.5 * hb[16 * q + c16]);
+      hold = hb[16 * q + c16];
+      th = fma(-ta, part, 1.5 * hold);
     }
     e2 = wave_sum(e2);
     if (lane == 0) sm[W_RES + q] = e2;
@@ -330,15 +333,48 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
     f64x4 Qc[NB];
 #pragma unroll
     for (int I = 0; I < NB; ++I) Qc[I] = Mfma<double>::zero();
-    if (act && more) mm_cb<NB>(Pp, Pc, Qc, lane);
+    if (act && more) {
+      mm_cb<NB>(Pp, Pc, Qc, lane);
+      // (P^2 h) for row 16 q + c16, for a second-order finish
+#pragma unroll
+      for (int K = 0; K < NB; ++K)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) q2 = fma(Qc[K][r], hb[16 * K + g + 4 * r], q2);
+      q2 = col_sum(q2);
+    }
     __syncthreads();  // #1: residual, P^2 complete; every read of h done
     double d2 = 0.0;
 #pragma unroll
     for (int w = 0; w < kW; ++w) d2 += sm[W_RES + w];
     finite = isfinite(d2);
     conv = finite && 0.75 * d2 <= tol;
+    // second-order finish (as in the 64-member kernel): sqrt(a) (5/2 X T -
+    // 15/8 X + 3/8 a^2 X P^2) for X = V, h, once the residual is below tol2
+    const bool fin2 = finite && !conv && more && 0.75 * d2 <= tol2;
     ++nit;
-    if (act && g == 0) hb[16 * q + c16] = hn;
+    if (fin2) {
+      const double c2 = 0.375 * al * al;
+      if (act) {
+        for (int cb = 0; cb < ncbo; ++cb) {
+          const T *vr = Vc + (16 * cb + c16) * XS + g;
+          f64x4 o = Mfma<double>::zero();
+#pragma unroll
+          for (int K = 0; K < NB; ++K)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) o = Mfma<double>::mac((double)vr[16 * K + 4 * kk], Qc[K][kk], o);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = (16 * cb + g + 4 * r) * XS + 16 * q + c16;
+            // Vn holds sqrt(a) V T (this wave's columns, written by it)
+            Vn[e] = (T)fma(sa * c2, o[r], fma(2.5, (double)Vn[e], -1.875 * sa * (double)Vc[e]));
+          }
+        }
+        if (g == 0) hb[16 * q + c16] = sa * fma(c2, q2, fma(2.5, th, -1.875 * hold));
+      }
+      conv = true;
+    } else if (act && g == 0) {
+      hb[16 * q + c16] = sa * th;
+    }
     if (!conv && finite && more) {
       // P_{k+1} = a (9/4 P - 3/2 a P^2 + 1/4 a^2 P^3), P^3 = P P^2 (P read
       // from LDS, P^2's column block from the registers)
