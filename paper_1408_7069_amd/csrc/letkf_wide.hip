@@ -33,6 +33,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "letkf_device.h"
 #include "letkf_types.h"
 
@@ -62,40 +64,66 @@ __device__ inline double col_sum(double v) {
   return v;
 }
 
-// The column block q of P (registers, FP64 accumulator layout: tile K,
-// element r = P[16 K + g + 4 r][16 q + c16]) from the stored upper triangle.
-template <int NB>
-__device__ __forceinline__ void load_cb(const double *Pp, f64x4 (&B)[NB], int q, int lane) {
+// Layouts of a 16 x 16 tile in the registers of a wavefront (c16 = lane % 16,
+// g = lane / 16): element r of a lane is row off(r) of column c16, off(r) =
+// g + 4 r for the FP64 16x16x4 accumulator, 4 g + r for the FP32 one.  The
+// same off(j) is the contraction index a lane supplies at step j of a
+// 16-wide block (FP32: the permuted order 4 g + j), so an accumulator tile is
+// the right operand of the next product as it stands.
+template <bool F32> __device__ __forceinline__ int off(int g, int r) { return F32 ? 4 * g + r : g + 4 * r; }
+template <bool F32> using Acc = typename std::conditional<F32, f32x4, f64x4>::type;
+template <bool F32> using Elem = typename std::conditional<F32, float, double>::type;
+
+// The column block q of P in the registers (F32: rounded to FP32) from the
+// stored upper triangle.
+template <int NB, bool F32>
+__device__ __forceinline__ void load_cb(const double *Pp, Acc<F32> (&B)[NB], int q, int lane) {
   const int c16 = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int K = 0; K < NB; ++K) {
     const bool up = K <= q;
     const double *t = Pp + (up ? tix(K, q) : tix(q, K)) * kTile;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) B[K][r] = up ? t[(g + 4 * r) * kTS + c16] : t[c16 * kTS + g + 4 * r];
+    for (int r = 0; r < 4; ++r)
+      B[K][r] = (Elem<F32>)(up ? t[off<F32>(g, r) * kTS + c16] : t[c16 * kTS + off<F32>(g, r)]);
   }
+}
+
+// Tiles (I, q), I <= q, of a column block into the stored upper triangle.
+template <int NB, bool F32>
+__device__ __forceinline__ void store_cb(double *Pp, const Acc<F32> (&C)[NB], int q, int lane) {
+  const int c16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+    if (I <= q) {
+      double *t = Pp + tix(I, q) * kTile;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) t[off<F32>(g, r) * kTS + c16] = (double)C[I][r];
+    }
 }
 
 // acc[I] += (P R)[16 I.., 16 q..] for every row block I: P the symmetric
 // matrix stored as its upper block triangle (left operand, tile (I, K) read
 // from the stored (I, K) or, below the diagonal, transposed from (K, I)), R a
-// column block in registers (right operand; step kk of block K pairs with
-// k = 16 K + 4 kk + g).  One pass over K with NB independent accumulators.
-template <int NB>
-__device__ __forceinline__ void mm_cb(const double *Pp, const f64x4 (&R)[NB], f64x4 (&acc)[NB], int lane) {
+// column block in registers (right operand; step j of block K pairs with
+// k = 16 K + off(j)).  One pass over K with NB independent accumulators, the
+// loads of one step in flight at a time (register pressure); FP32 products
+// (operands rounded) with F32.
+template <int NB, bool F32>
+__device__ __forceinline__ void mm_cb(const double *Pp, const Acc<F32> (&R)[NB], Acc<F32> (&acc)[NB], int lane) {
   const int c16 = lane & 15, g = lane >> 4;
-  const int offN = c16 * kTS + g, offT = g * kTS + c16;
+  const int offN = c16 * kTS + off<F32>(g, 0), offT = off<F32>(g, 0) * kTS + c16;
+  constexpr int dj = F32 ? 1 : 4;  // step of the contraction index with j
 #pragma unroll
   for (int K = 0; K < NB; ++K)
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const double b = R[K][kk];
+    for (int j = 0; j < 4; ++j) {
+      const Elem<F32> b = R[K][j];
 #pragma unroll
       for (int I = 0; I < NB; ++I) {
-        const double a = I <= K ? Pp[tix(I, K) * kTile + offN + 4 * kk] : Pp[tix(K, I) * kTile + offT + 4 * kk * kTS];
-        acc[I] = Mfma<double>::mac(a, b, acc[I]);
+        const double a = I <= K ? Pp[tix(I, K) * kTile + offN + dj * j] : Pp[tix(K, I) * kTile + offT + dj * j * kTS];
+        acc[I] = Mfma<Elem<F32>>::mac((Elem<F32>)a, b, acc[I]);
       }
-      // (the loads of one K block in flight at a time: register pressure)
       __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -264,12 +292,8 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
   if (act) {
     const double is = 1.0 / s;
 #pragma unroll
-    for (int I = 0; I < NB; ++I)
-      if (I <= q) {
-        double *t = Pp + tix(I, q) * kTile;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) t[(g + 4 * r) * kTS + c16] = acc[I][r] * is;
-      }
+    for (int I = 0; I < NB; ++I) acc[I] *= is;
+    store_cb<NB, false>(Pp, acc, q, lane);
   }
   __syncthreads();
 
@@ -282,47 +306,56 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
   double l = c / s;
   int nit = 0;
   bool conv = false, finite = isfinite(s);
-  // the diagonal element a lane holds in its column block: tile q, element
-  // (c16 - g) / 4 when c16 - g is a non-negative multiple of 4
-  const int dpos = (c16 >= g && ((c16 - g) & 3) == 0) ? 4 * q + ((c16 - g) >> 2) : -1;
-  while (finite) {
+  // FP32 state: the P updates on the FP32 matrix cores once the spectrum's
+  // lower bound passes 0.1 (as NSP_MIXED in the 64-member kernel); P stays
+  // in the FP64 triangle (holding FP32 values), the operands rounded
+  constexpr bool MIXED = sizeof(T) == 4;
+  constexpr double kSwitch = 0.1;
+  auto step = [&](auto f32tag) {
+    constexpr bool F32 = decltype(f32tag)::value;
+    using E = Elem<F32>;
+    using AC = Acc<F32>;
+    using MF = Mfma<E>;
+    constexpr int dj = F32 ? 1 : 4;
     const double al = 3.0 / (1.0 + sqrt(l) + l), sa = sqrt(al), ta = 0.5 * al;
-    // (opaque a step: the diagonal selects are formed where used, not kept
-    // across the loop in registers)
-    int dq = dpos;
+    // the diagonal element a lane holds in its column block (tile q, element
+    // r with off(r) = c16), made opaque a step so that the selects are formed
+    // where used, not kept across the loop in registers
+    const int rd = F32 ? c16 - 4 * g : ((c16 - g) >= 0 && ((c16 - g) & 3) == 0 ? (c16 - g) >> 2 : -1);
+    int dq = (rd >= 0 && rd < 4) ? 4 * q + rd : -1;
     asm volatile("" : "+v"(dq));
     T *Vc = (nit & 1) ? xs1 : xs, *Vn = (nit & 1) ? xs : xs1;
-    f64x4 Pc[NB];
+    AC Pc[NB];
     double e2 = 0.0, th = 0.0, hold = 0.0, q2 = 0.0;
     if (act) {
-      load_cb<NB>(Pp, Pc, q, lane);
+      load_cb<NB, F32>(Pp, Pc, q, lane);
 #pragma unroll
       for (int K = 0; K < NB; ++K)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const double d = fma(al, Pc[K][r], 4 * K + r == dq ? -1.0 : 0.0);
+          const double d = fma(al, (double)Pc[K][r], 4 * K + r == dq ? -1.0 : 0.0);
           e2 = fma(d, d, e2);
         }
       // V_{k+1} = sqrt(a) V_k T_k on this wave's columns, row block by row block
       for (int cb = 0; cb < ncbo; ++cb) {
-        const T *vr = Vc + (16 * cb + c16) * XS + g;
-        f64x4 o = Mfma<double>::zero();
+        const T *vr = Vc + (16 * cb + c16) * XS + off<F32>(g, 0);
+        AC o{};
 #pragma unroll
         for (int K = 0; K < NB; ++K)
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const double tb = fma(-ta, Pc[K][kk], 4 * K + kk == dq ? 1.5 : 0.0);
-            o = Mfma<double>::mac((double)vr[16 * K + 4 * kk], tb, o);
+          for (int jj = 0; jj < 4; ++jj) {
+            const E tb = (E)fma(-ta, (double)Pc[K][jj], 4 * K + jj == dq ? 1.5 : 0.0);
+            o = MF::mac((E)vr[16 * K + dj * jj], tb, o);
           }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Vn[(16 * cb + g + 4 * r) * XS + 16 * q + c16] = (T)(sa * o[r]);
+        for (int r = 0; r < 4; ++r) Vn[(16 * cb + off<F32>(g, r)) * XS + 16 * q + c16] = (T)(sa * (double)o[r]);
       }
       // h_{k+1} = sqrt(a) (3/2 h - ta P h) for row 16 q + c16
       double part = 0.0;
 #pragma unroll
       for (int K = 0; K < NB; ++K)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) part = fma(Pc[K][r], hb[16 * K + g + 4 * r], part);
+        for (int r = 0; r < 4; ++r) part = fma((double)Pc[K][r], hb[16 * K + off<F32>(g, r)], part);
       part = col_sum(part);
       hold = hb[16 * q + c16];
       th = fma(-ta, part, 1.5 * hold);
@@ -330,16 +363,16 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
     e2 = wave_sum(e2);
     if (lane == 0) sm[W_RES + q] = e2;
     const bool more = nit + 1 < max_it;
-    f64x4 Qc[NB];
+    AC Qc[NB];
 #pragma unroll
-    for (int I = 0; I < NB; ++I) Qc[I] = Mfma<double>::zero();
+    for (int I = 0; I < NB; ++I) Qc[I] = AC{};
     if (act && more) {
-      mm_cb<NB>(Pp, Pc, Qc, lane);
+      mm_cb<NB, F32>(Pp, Pc, Qc, lane);
       // (P^2 h) for row 16 q + c16, for a second-order finish
 #pragma unroll
       for (int K = 0; K < NB; ++K)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) q2 = fma(Qc[K][r], hb[16 * K + g + 4 * r], q2);
+        for (int r = 0; r < 4; ++r) q2 = fma((double)Qc[K][r], hb[16 * K + off<F32>(g, r)], q2);
       q2 = col_sum(q2);
     }
     __syncthreads();  // #1: residual, P^2 complete; every read of h done
@@ -356,17 +389,17 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
       const double c2 = 0.375 * al * al;
       if (act) {
         for (int cb = 0; cb < ncbo; ++cb) {
-          const T *vr = Vc + (16 * cb + c16) * XS + g;
-          f64x4 o = Mfma<double>::zero();
+          const T *vr = Vc + (16 * cb + c16) * XS + off<F32>(g, 0);
+          AC o{};
 #pragma unroll
           for (int K = 0; K < NB; ++K)
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) o = Mfma<double>::mac((double)vr[16 * K + 4 * kk], Qc[K][kk], o);
+            for (int jj = 0; jj < 4; ++jj) o = MF::mac((E)vr[16 * K + dj * jj], Qc[K][jj], o);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int e = (16 * cb + g + 4 * r) * XS + 16 * q + c16;
+            const int e = (16 * cb + off<F32>(g, r)) * XS + 16 * q + c16;
             // Vn holds sqrt(a) V T (this wave's columns, written by it)
-            Vn[e] = (T)fma(sa * c2, o[r], fma(2.5, (double)Vn[e], -1.875 * sa * (double)Vc[e]));
+            Vn[e] = (T)fma(sa * c2, (double)o[r], fma(2.5, (double)Vn[e], -1.875 * sa * (double)Vc[e]));
           }
         }
         if (g == 0) hb[16 * q + c16] = sa * fma(c2, q2, fma(2.5, th, -1.875 * hold));
@@ -377,30 +410,27 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
     }
     if (!conv && finite && more) {
       // P_{k+1} = a (9/4 P - 3/2 a P^2 + 1/4 a^2 P^3), P^3 = P P^2 (P read
-      // from LDS, P^2's column block from the registers)
-      // (accumulated over P's own column block: two blocks live at a time)
+      // from LDS, P^2's column block from the registers), accumulated over
+      // P's own column block: two blocks live at a time
       if (act) {
-        const double i2 = 1.0 / (al * al);
+        const E i2 = (E)(1.0 / (al * al)), a6 = (E)(6.0 * al), f3 = (E)(0.25 * al * al * al);
 #pragma unroll
-        for (int K = 0; K < NB; ++K) Pc[K] = (9.0 * Pc[K] - (6.0 * al) * Qc[K]) * i2;
-        mm_cb<NB>(Pp, Qc, Pc, lane);
-        const double f3 = 0.25 * al * al * al;
+        for (int K = 0; K < NB; ++K) Pc[K] = ((E)9 * Pc[K] - a6 * Qc[K]) * i2;
+        mm_cb<NB, F32>(Pp, Qc, Pc, lane);
 #pragma unroll
         for (int K = 0; K < NB; ++K) Pc[K] *= f3;
       }
       __syncthreads();  // #2: every read of P_k done
-      if (act) {
-#pragma unroll
-        for (int I = 0; I < NB; ++I)
-          if (I <= q) {
-            double *t = Pp + tix(I, q) * kTile;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) t[(g + 4 * r) * kTS + c16] = Pc[I][r];
-          }
-      }
+      if (act) store_cb<NB, F32>(Pp, Pc, q, lane);
     }
     __syncthreads();  // P_{k+1}, V and h complete
     l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
+  };
+  while (finite) {
+    if (MIXED && l >= kSwitch)
+      step(std::true_type{});
+    else
+      step(std::false_type{});
     if (conv || nit >= max_it) break;
   }
   const bool keep = bad || !finite || !conv;
