@@ -16,15 +16,17 @@
 //      into an FP64 K-major operand, and the Gram on the FP64 matrix cores:
 //      wave q accumulates the column block q of A~ = (m-1)/rho I + Y^T Y over
 //      the slopes; b = Y^T sqrt(g) d along the way;
-//   4.-6. the inverse square root by the P-form Newton-Schulz iteration in
-//      FP64 (the same steps as the 64-member kernel): P_0 = A~ / s with
+//   4.-6. the inverse square root by the P-form Newton-Schulz iteration
+//      (the same steps as the 64-member kernel): P_0 = A~ / s with
 //      s = ||A~||_F, P_{k+1} = a_k P_k T_k^2, T_k = (3 I - a_k P_k) / 2,
-//      carrying V = X' Z (owned rows) and h = Z b, Z = prod sqrt(a_k) T_k;
-//      P lives in LDS as its upper block triangle (16 x 16 tiles), each wave
-//      keeps the column block q of P in registers and forms the column block
-//      q of P^2 and of P^3 = P P^2 from it (the right operands stay in
-//      registers, the left ones are tiles of P read from LDS, mirrored where
-//      below the diagonal);
+//      carrying V = X' Z (owned rows) and h = Z b, Z = prod sqrt(a_k) T_k,
+//      in FP64 (FP32 state: on the FP32 matrix cores once the spectrum's
+//      lower bound passes 0.1), the last step second-order once the
+//      residual allows; P lives in LDS as its upper block triangle (16 x 16
+//      tiles), each wave keeps the column block q of P in registers and
+//      forms the column block q of P^2 and of P^3 = P P^2 from it (the right
+//      operands stay in registers, the left ones are tiles of P read from
+//      LDS, mirrored where below the diagonal);
 //   7. owned rows: x_a = x_b + V h / s, X_a = x_a 1^T + sqrt(rho c / s) V,
 //      written straight into the global analysis ensemble.
 // A work item that meets a non-finite observation or does not converge
