@@ -78,7 +78,10 @@ extern "C" {
  *              T = (3 I - a P) / 2: two products of P with its own powers a
  *              step, on the ten upper 16 x 16 tiles), in FP64, carrying only
  *              what the update needs: Z X'^T for the owned rows and Z b.
- *              Same stopping rule as NS64.
+ *              Same stopping rule as NS64, and a second-order last step
+ *              once the residual is below sqrt(tol) (FP32 state) or
+ *              tol^(2/3) (FP64): sqrt(a)(I - E/2 + 3/8 E^2), E = a P - I,
+ *              in place of one more step.
  *   NSP_MIXED  NSP with the P updates in FP64 while the spectrum's lower
  *              bound l is below 0.1 (the steps whose rounding the small
  *              eigenvalues amplify) and in FP32 after; X' Z in FP32.  The
