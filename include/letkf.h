@@ -83,11 +83,11 @@ extern "C" {
  *              tol^(2/3) (FP64): sqrt(a)(I - E/2 + 3/8 E^2), E = a P - I,
  *              in place of one more step.
  *   NSP_MIXED  NSP with the P updates in FP64 while the spectrum's lower
- *              bound l is below 0.1 (the steps whose rounding the small
+ *              bound l is below 0.01 (the steps whose rounding the small
  *              eigenvalues amplify) and in FP32 after; X' Z in FP32.  The
- *              anomaly transform lands within ~1.5e-6 of the FP64 one, under
- *              the rounding the FP32 Gram itself carries.  FP32 handles; an
- *              FP64 handle runs NSP.
+ *              FP32 steps add a few percent to the error the FP32 Gram
+ *              itself carries (its rounding times the condition number of
+ *              A~).  FP32 handles; an FP64 handle runs NSP.
  * A handle with the blend-mode gather runs NS64 when NSP or NSP_MIXED is
  * asked for (the P forms carry the owned rows only). */
 #define LETKF_TRANSFORM_NSP 3
@@ -256,7 +256,8 @@ typedef struct letkf_sizes {
  * the paper's timing shape, Sec. 5.3 Tables 1-2: m = 101, b = 4, h = 2: 9 x 9
  * patch nodes, 128 local slopes) runs every local analysis on the wide kernel:
  * 8 wavefronts a domain, the Gram in FP64, the P-form iteration in FP64
- * whatever `transform` names (NS64, NSP and NSP_MIXED are accepted).  Such a
+ * (NS64, NSP and NSP_MIXED are accepted; with FP32 state and NSP_MIXED its P
+ * updates run in FP32 once the spectrum's lower bound passes 0.05).  Such a
  * handle has the delay-free AR(1) phase model with the concatenating gather
  * only: the closed loop, AR(2), the online refit, the blend gather, covariance
  * localisation and the EVD/NS32 transforms give LETKF_E_INVAL, and so does

@@ -126,6 +126,7 @@ template <typename T> struct AnaArgs {
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
   int32_t off_clb, off_clr;  // covariance localisation: B and the solve's columns
   int32_t round_items;        // work items of one dispatch round per XCD (CUs per XCD)
+  int32_t p32;                // wide analysis, FP32 state: P updates in FP32 past the switch (NSP_MIXED)
   const int32_t *order;       // grid slot -> work item (-1: none), or NULL for the fixed orders
 };
 

@@ -153,6 +153,7 @@ template <typename T> struct AnaArgsHost {
   int32_t off_xs, off_xm, off_sg, off_dd, off_yb, off_pn, off_s, off_u, off_ys;
   int32_t off_clb, off_clr;
   int32_t round_items;
+  int32_t p32;
   const int32_t *order;  // grid slot -> work item (-1: none), or NULL
 };
 
@@ -226,6 +227,7 @@ struct letkf_handle {
   int max_sweeps = 30;
   int transform = LETKF_TRANSFORM_NS64;  // forward transform (FP64 handles: never NS32)
   bool wide = false;  // shapes past the 64-member, 64-node layout: the wide analysis kernel
+  bool wide_p32 = false;  // the wide analysis with FP32 state asked for NSP_MIXED
   size_t lds = 0;
   int32_t off[9] = {0};      // LDS layout of the adjoint's forward stages
   int32_t fwd_off[9] = {0};  // LDS layout of the analysis
@@ -671,6 +673,7 @@ AnaArgsHost<T> make_args(letkf_handle *h, bool fused, const void *V, const void 
   A.off_clb = h->cl_off[0];
   A.off_clr = h->cl_off[1];
   A.round_items = h->round_items;
+  A.p32 = h->wide_p32 ? 1 : 0;
   A.stage_mean = h->d_smean;
   A.flags = h->d_flags;
   A.frame = h->d_frame;
@@ -1245,6 +1248,7 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
                                  "which has no " + why);
     }
     const int nb = std::max(4, (h->max_m + 15) / 16), M = 16 * nb;
+    h->wide_p32 = !h->fp64 && h->transform == LETKF_TRANSFORM_NSP_MIXED;
     h->transform = kAnalysisWide + nb;
     // small arrays, then the patch rows (row stride M + 1); the Gram's
     // 16-slope operand after them.  From the transform on: V in place of the
@@ -1948,7 +1952,7 @@ int letkf_autotune(letkf_handle *h, const void *V_dev, const void *y_dev, int32_
   }
   key << "gfx950 cu " << dev_cu << " fp" << (h->fp64 ? 64 : 32) << " items " << h->items.size() << " m "
       << h->max_m << " patch " << h->max_patch << " obs " << h->max_obs_sub << " transform " << h->transform
-      << " localisation " << loc << " model " << model << " gather " << gather << " ar2 " << ar2
+      << (h->wide_p32 ? " p32" : "") << " localisation " << loc << " model " << model << " gather " << gather << " ar2 " << ar2
       << " refit " << refit;
   if (cache_path) {
     std::ifstream in(cache_path);

@@ -997,8 +997,14 @@ __device__ inline double matvec_quad(const float *M, const double *x, int q, int
 // A rounding error delta of P_k enters Z as delta / mu where mu is the
 // eigenvalue it perturbs; the smallest eigenvalues are of order l_k, so the
 // steps with l_k small carry the cancellation.  MIXED (FP32 handles): P is
-// updated in FP64 until l_k >= kNspSwitch, then in FP32 (the rounding
-// divided by l_k stays under the FP32 Gram's own error).
+// updated in FP64 until l_k >= kNspSwitch, then in FP32: P_{k+1} is stored
+// in FP32 from l_k = 0.01 on, when its own bound l_{k+1} is 0.059 or more,
+// so its rounding enters Z at 1e-6 at most.  The FP32 Gram already perturbs
+// the smallest eigen-directions by about eps32 times the condition number
+// kappa of A~, and l_0 = lambda_min / ||A~||_F <= 1 / kappa: the FP32 steps
+// add a few percent to the Gram's error.  (The mean weights Z^2 b lean on
+// the smallest eigenvalues: a switch at 1e-3 saves one more FP64 step but
+// adds a quarter to the error of the analysis mean.)
 //
 // Storage: P and P^2 as full 64 x 64 matrices (both triangles; FP64 with row
 // stride kLaStride, or FP32 with row stride kNs32Stride in the FP32 steps,
@@ -1006,7 +1012,7 @@ __device__ inline double matvec_quad(const float *M, const double *x, int q, int
 // row stride kXsStride, element type of the handle).  Each wave keeps the
 // column block q of P in registers (the right operand of every product and
 // the column block q of T).
-constexpr double kNspSwitch = 0.1;
+constexpr double kNspSwitch = 0.01;
 
 // Tile I of a column block held in registers, I a runtime value (selects,
 // so that the block stays in registers).

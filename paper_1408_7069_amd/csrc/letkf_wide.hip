@@ -20,9 +20,9 @@
 //      (the same steps as the 64-member kernel): P_0 = A~ / s with
 //      s = ||A~||_F, P_{k+1} = a_k P_k T_k^2, T_k = (3 I - a_k P_k) / 2,
 //      carrying V = X' Z (owned rows) and h = Z b, Z = prod sqrt(a_k) T_k,
-//      in FP64 (FP32 state: on the FP32 matrix cores once the spectrum's
-//      lower bound passes 0.1), the last step second-order once the
-//      residual allows; P lives in LDS as its upper block triangle (16 x 16
+//      in FP64 (FP32 state with NSP_MIXED: on the FP32 matrix cores once
+//      the spectrum's lower bound passes 0.05), the last step second-order
+//      once the residual allows; P lives in LDS as its upper block triangle (16 x 16
 //      tiles), each wave keeps the column block q of P in registers and
 //      forms the column block q of P^2 and of P^3 = P P^2 from it (the right
 //      operands stay in registers, the left ones are tiles of P read from
@@ -308,11 +308,12 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
   double l = c / s;
   int nit = 0;
   bool conv = false, finite = isfinite(s);
-  // FP32 state: the P updates on the FP32 matrix cores once the spectrum's
-  // lower bound passes 0.1 (as NSP_MIXED in the 64-member kernel); P stays
-  // in the FP64 triangle (holding FP32 values), the operands rounded
-  constexpr bool MIXED = sizeof(T) == 4;
-  constexpr double kSwitch = 0.1;
+  // FP32 state with NSP_MIXED: the P updates on the FP32 matrix cores once
+  // the spectrum's lower bound passes 0.05 (where the 64-member kernel's
+  // first FP32 step starts: its switch rounds P_{k+1} once l_k >= 0.01);
+  // P stays in the FP64 triangle (holding FP32 values), the operands rounded
+  const bool mixed = sizeof(T) == 4 && A.p32 != 0;
+  constexpr double kSwitch = 0.05;
   auto step = [&](auto f32tag) {
     constexpr bool F32 = decltype(f32tag)::value;
     using E = Elem<F32>;
@@ -429,7 +430,7 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
     l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
   };
   while (finite) {
-    if (MIXED && l >= kSwitch)
+    if (mixed && l >= kSwitch)
       step(std::true_type{});
     else
       step(std::false_type{});

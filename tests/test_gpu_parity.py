@@ -162,14 +162,18 @@ def test_full_size_80x80_m64_in_the_timed_configuration(transform):
 
 
 def test_mixed_p_form_tracks_the_fp64_p_form():
-    # the FP32 steps of NSP_MIXED move the 80x80 ensemble by ~1e-6 of its
-    # size from the all-FP64 P-form on the same inputs, well under the FP32
-    # Gram's own rounding (same handle inputs, one frame each, three frames)
+    # the FP32 steps of NSP_MIXED (P_{k+1} stored in FP32 once l_k >= 0.01)
+    # move the 80x80 ensemble by ~1e-5 of its size from the all-FP64 P-form
+    # on the same inputs (the anomalies by ~2e-6), under the FP32 Gram's own
+    # rounding that both carry: against the FP64 oracle the mixed form adds
+    # at most a quarter to the FP64 P-form's distance (same handle inputs,
+    # one frame each, three frames)
     case = Case(80, 0.28, 4, 1, 64, seed=19)
     bb = B()
     fm = bb.Letkf([case.spec(bb, transform=bb.TRANSFORM_NSP_MIXED)])
     fd = bb.Letkf([case.spec(bb, transform=bb.TRANSFORM_NSP)])
     X = (case.rng.standard_normal((case.G.n_nodes, case.m)) * 0.3).astype(np.float32)
+    anom = lambda e: e - e.mean(1, keepdims=True)
     for k in range(3):
         V, y = case.noise(), case.slopes(case.truth())
         for f in (fm, fd):
@@ -177,8 +181,11 @@ def test_mixed_p_form_tracks_the_fp64_p_form():
             f.step(_t(y), V=_t(V))
         torch.cuda.synchronize()
         a, b = _ens(fm, case.m), _ens(fd, case.m)
-        assert rel_err(a, b) <= 1e-5, k
-        assert rel_err(a - a.mean(1, keepdims=True), b - b.mean(1, keepdims=True)) <= 2e-5, k
+        assert rel_err(a, b) <= 2.5e-5, k
+        assert rel_err(anom(a), anom(b)) <= 5e-6, k
+        ref = case.oracle_analysis(case.prm.a * X.astype(np.float64) + V.astype(np.float64), y)
+        assert rel_err(a, ref) <= 1.25 * rel_err(b, ref) + 2e-6, k
+        assert rel_err(a, ref) <= 1e-4, k
         X = b.astype(np.float32)
 
 

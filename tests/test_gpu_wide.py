@@ -103,6 +103,28 @@ def test_patch_at_its_limit(N, eps, b, h, m, fp64, tol):
     _frames(case, f, 2, tol)
 
 
+def test_fp32_state_runs_the_transform_it_names():
+    # FP32 state: NSP keeps every P update in FP64, NSP_MIXED moves them to
+    # the FP32 matrix cores once the spectrum's lower bound passes 0.05; both
+    # within the FP32 bar, the FP64 iteration well inside it
+    case = Case(24, 0.28, 4, 2, 101, seed=82, piston=True)
+    bb = B()
+    X0 = (case.rng.standard_normal((case.G.n_nodes, case.m)) * 0.5).astype(np.float32)
+    V, y = case.noise(), case.slopes(case.truth())
+    ref = case.oracle_analysis(case.prm.a * X0.astype(np.float64) + V.astype(np.float64), y)
+    outs = {}
+    for tr in (bb.TRANSFORM_NSP, bb.TRANSFORM_NSP_MIXED):
+        f = bb.Letkf([case.spec(bb, transform=tr)])
+        f.set_ensemble(_t(X0))
+        f.step(_t(y), V=_t(V))
+        torch.cuda.synchronize()
+        outs[tr] = _ens(f, case.m)
+        f.close()
+    assert not np.array_equal(outs[bb.TRANSFORM_NSP], outs[bb.TRANSFORM_NSP_MIXED])
+    assert rel_err(outs[bb.TRANSFORM_NSP], ref) <= 1e-5
+    assert rel_err(outs[bb.TRANSFORM_NSP_MIXED], ref) <= 1e-4
+
+
 def test_owned_block_of_121_nodes():
     # 10x10 domains without a halo: 121 owned rows (eight row blocks of V);
     # FP32 fits the LDS, FP64 is refused with the sizes
