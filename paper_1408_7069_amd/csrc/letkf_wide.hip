@@ -312,8 +312,8 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
   // the spectrum's lower bound passes 0.05 (where the 64-member kernel's
   // first FP32 step starts: its switch rounds P_{k+1} once l_k >= 0.01);
   // P stays in the FP64 triangle (holding FP32 values), the operands rounded
-  const bool mixed = sizeof(T) == 4 && A.p32 != 0;
-  constexpr double kSwitch = 0.05;
+  constexpr bool kF32State = sizeof(T) == 4;
+  const double l_switch = A.p32 != 0 ? 0.05 : INFINITY;
   auto step = [&](auto f32tag) {
     constexpr bool F32 = decltype(f32tag)::value;
     using E = Elem<F32>;
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(kWT) void k_analysis_wide(const AnaArgs<T> A) {
     l = al * l * (3.0 - al * l) * (3.0 - al * l) * 0.25;
   };
   while (finite) {
-    if (mixed && l >= kSwitch)
+    if (kF32State && l >= l_switch)
       step(std::true_type{});
     else
       step(std::false_type{});
