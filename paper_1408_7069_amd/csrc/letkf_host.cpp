@@ -192,6 +192,22 @@ template <typename T> struct AdjArgsHost {
   int32_t off_q, off_wb, off_sa;
 };
 
+// Whether the host mirrors of the kernel argument blocks have the kernels'
+// sizes: 0, else the first block that differs (1 analysis, 2 adjoint, 3
+// piston).  The kernels and this file are separate translation units, so a
+// field added on one side only is caught here rather than read shifted.
+extern "C" int letkf_layout_check(void) {
+  if (sizeof(AnaArgsHost<float>) != letkf_args_size(0) || sizeof(AnaArgsHost<double>) != letkf_args_size(1))
+    return 1;
+  if (sizeof(AdjArgsHost<float>) != letkf_adjoint_args_size(0) ||
+      sizeof(AdjArgsHost<double>) != letkf_adjoint_args_size(1))
+    return 2;
+  if (sizeof(PistonArgsHost<float>) != letkf_piston_args_size(0) ||
+      sizeof(PistonArgsHost<double>) != letkf_piston_args_size(1))
+    return 3;
+  return 0;
+}
+
 struct InstGeom {
   int N = 0, b = 0, h = 0, m = 0;
   std::vector<uint8_t> mask;           // N*N
@@ -1024,6 +1040,9 @@ const char *letkf_last_error(void) { return g_last_error.c_str(); }
 int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, letkf_handle **out) {
   if (!out) return fail(LETKF_E_INVAL, "out is NULL");
   *out = nullptr;
+  if (const int bad = letkf_layout_check())
+    return fail(LETKF_E_DEVICE, "kernel argument block " + std::to_string(bad) +
+                                    " differs between the kernels and the host (mismatched build)");
   if (!cfgs || n_instances < 1) return fail(LETKF_E_INVAL, "need at least one instance");
   std::string err;
   for (int i = 0; i < n_instances; ++i) {

@@ -21,6 +21,12 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(binding.lib, n), n
 
 
+def test_kernel_argument_blocks_match_their_host_mirrors():
+    # analysis, adjoint and piston argument blocks: the kernels' sizeof against
+    # the host-side mirrors (separate translation units of the library)
+    assert binding.lib.letkf_layout_check() == 0
+
+
 def test_strerror_and_codes():
     assert binding.lib.letkf_strerror(0) == b"ok"
     for code in range(-6, 0):
