@@ -64,10 +64,17 @@ extern "C" {
  *   NS64  A~^{-1/2} by the scaled coupled Newton-Schulz iteration in FP64 on
  *         the FP64 matrix cores (Higham 1997), w = A~^{-1} b from the same
  *         iterate; stops when the predicted residual ||a Z Y - I||_F^2 after
- *         a step is <= jacobi_tol / 100.  Default.
+ *         a step is <= jacobi_tol / 100.  With FP32 state its symmetric
+ *         products are formed on the upper tiles and mirrored while the
+ *         spectrum's lower bound (m-1)/rho / ||A~||_F is at least 1e-4, in
+ *         full below (mirrored iterates drift apart past condition numbers
+ *         of about 2e4).  Default.
  *   NS32  the same iteration with FP32 iterates on the FP32 matrix cores
  *         (W within ~2e-5 relative), w refined once in FP64 against A~.
- *         FP32 handles only; an FP64 handle runs NS64.
+ *         FP32 handles only; an FP64 handle runs NS64.  Its FP32 iterates
+ *         lose accuracy sooner than the others as A~ grows ill-conditioned
+ *         (3.6 times the FP64 transforms' distance from the oracle at a
+ *         condition number of 8e6).
  *   EVD   A~ = Q Lambda Q^T by the FP64 one-sided Jacobi on the Cholesky
  *         factor (stop: jacobi_tol on the relative inner products), then
  *         W = sqrt(c) Q Lambda^{-1/2} Q^T and w from the Cholesky factor. */

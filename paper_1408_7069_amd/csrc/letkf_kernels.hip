@@ -680,30 +680,27 @@ struct IsqrtStatus {
 // tolerance W then stays within 4e-9 of the eigendecomposition's on the
 // steady-state 80 x 80 matrices, as with full products (the stopping rule
 // sets the error); at FP64 tolerances the mirroring costs up to two digits,
-// so FP64 mode forms every product in full (W within 2e-13).  The iteration
-// stops once the predicted residual after the step, 3/4 ||a_k Z_k Y_k - I||_F^2, is
-// <= tol.  On return Z is in Zc (this wave's column block) and in Zb (LDS);
-// A's area (Yb) has been overwritten.  Every wave takes the same decisions
-// (the residual is summed over the workgroup).
+// so FP64 mode forms every product in full (W within 2e-13).  Mirroring also
+// lets the two iterates drift apart as A grows ill-conditioned (the rounding
+// of Y and Z no longer commutes): FP32 mode forms every product in full too
+// once l_0 = lmin / s is below kNsMirrorMinL.  The iteration stops once the
+// predicted residual after the step, 3/4 ||a_k Z_k Y_k - I||_F^2, is <= tol.
+// On return Z is in Zc (this wave's column block) and in Zb (LDS); A's area
+// (Yb) has been overwritten.  Every wave takes the same decisions (the
+// residual is summed over the workgroup).
+//
+// kNsMirrorMinL: with FP32 state the mirrored iterates track the full ones
+// up to condition numbers of A~ near 2e4 (l_0 ~ 5e-5) and fall behind by
+// 3.7e4 (2e-3 from the oracle against 3e-4); 1e-4 keeps a factor of two.
+constexpr double kNsMirrorMinL = 1e-4;
+
+// The iteration of ns_isqrt from its scale s and l = lmin / s, with Yc the
+// column block q of A (read by the prologue).
 template <bool SYM>
-__device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, double lmin, double tol,
-                                       int max_it, ColBlock &Zc, int q, int lane, int rot) {
+__device__ inline IsqrtStatus ns_iterate(double *Yb, double *Zb, double *sm, double s, double l, double tol,
+                                         int max_it, ColBlock &Yc, ColBlock &Zc, int q, int lane, int rot) {
   const int col = 16 * q + (lane & 15), k4 = lane >> 4;
-  ColBlock Yc, Tc;
-  double ss = 0.0;
-#pragma unroll
-  for (int I = 0; I < 4; ++I)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const double v = Yb[(16 * I + k4 + 4 * r) * kLaStride + col];
-      Yc[I][r] = v;
-      ss = fma(v, v, ss);
-    }
-  ss = wave_sum(ss);
-  if (lane == 0) sm[S_RES + q] = ss;
-  __syncthreads();
-  const double s = sqrt(sum4(sm + S_RES));
-  double l = lmin / s;
+  ColBlock Tc;
   // k = 0 (Z_0 = I): T_0 = (3 I - a A / s) / 2, Z_1 = sqrt(a) T_0,
   // Y_1 = sqrt(a) / s A T_0 (A read from LDS)
   double al = 3.0 / (1.0 + sqrt(l) + l);
@@ -808,6 +805,31 @@ __device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, doubl
     ++it;
   }
   return IsqrtStatus{conv ? it : -it, finite, s};
+}
+
+template <bool SYM>
+__device__ inline IsqrtStatus ns_isqrt(double *Yb, double *Zb, double *sm, double lmin, double tol,
+                                       int max_it, ColBlock &Zc, int q, int lane, int rot) {
+  const int col = 16 * q + (lane & 15), k4 = lane >> 4;
+  ColBlock Yc;
+  double ss = 0.0;
+#pragma unroll
+  for (int I = 0; I < 4; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double v = Yb[(16 * I + k4 + 4 * r) * kLaStride + col];
+      Yc[I][r] = v;
+      ss = fma(v, v, ss);
+    }
+  ss = wave_sum(ss);
+  if (lane == 0) sm[S_RES + q] = ss;
+  __syncthreads();
+  const double s = sqrt(sum4(sm + S_RES));
+  const double l = lmin / s;
+  if constexpr (SYM) {
+    if (l >= kNsMirrorMinL) return ns_iterate<true>(Yb, Zb, sm, s, l, tol, max_it, Yc, Zc, q, lane, rot);
+  }
+  return ns_iterate<false>(Yb, Zb, sm, s, l, tol, max_it, Yc, Zc, q, lane, rot);
 }
 
 // The same iteration in FP32 on the FP32 matrix cores (twice the FP64 rate).

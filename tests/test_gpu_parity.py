@@ -342,6 +342,47 @@ def test_edge_shapes(N, eps, b, h, m, transform):
     assert rel_err(got, ref) <= 1e-4
 
 
+def _transform_errors(case, names):
+    bb = B()
+    X0 = (case.rng.standard_normal((case.G.n_nodes, case.m)) * 0.5).astype(case.dt)
+    V, y = case.noise(), case.slopes(case.truth())
+    ref = case.oracle_analysis(case.prm.a * X0.astype(np.float64) + V.astype(np.float64), y)
+    errs = {}
+    for name in names:
+        f = bb.Letkf([case.spec(bb, transform=_tr(name))])
+        f.set_ensemble(_t(X0))
+        f.step(_t(y), V=_t(V))
+        torch.cuda.synchronize()
+        rc, flags = f.status()
+        assert rc == 0 and not (flags & 3).any(), name
+        errs[name] = rel_err(_ens(f, case.m), ref)
+        f.close()
+    return errs
+
+
+@pytest.mark.parametrize("sigma", [0.015, 0.01])
+def test_ill_conditioned_fp32_frames_agree_across_transforms(sigma):
+    # a smaller slope noise makes A~ worse conditioned, as 1/sigma^2 (condition
+    # numbers to 3.7e4 and 8.2e4 here, ~1e3 at sigma = 0.1).  With FP32 state
+    # the FP32 Gram's rounding times that condition number sets every
+    # transform's distance from the FP64 oracle (3e-4 and 5e-4, past the 1e-4
+    # bar, which holds to condition numbers near 1e4); each transform stays
+    # within 1.5 times the FP64 eigensolve's distance.  (The coupled
+    # iteration on mirrored tiles drifted to 2e-3 and 3e-2 here.)
+    case = Case(24, 0.28, 4, 1, 64, seed=5, sigma=sigma)
+    errs = _transform_errors(case, TRANSFORMS)
+    for name, e in errs.items():
+        assert e <= 1.5 * errs["evd"], (name, errs)
+
+
+def test_ill_conditioned_fp64_frames_meet_the_fp64_bar():
+    # condition numbers to 8.2e4: the FP64 transforms still within 1e-10
+    case = Case(24, 0.28, 4, 1, 64, seed=5, sigma=0.01, fp64=True)
+    errs = _transform_errors(case, ["ns64", "evd", "nsp"])
+    for name, e in errs.items():
+        assert e <= 1e-10, (name, errs)
+
+
 def test_slope_operator_kernel():
     bb = B()
     cases = [Case(16, 0.2, 4, 1, 8, seed=20), Case(9, None, 3, 1, 8, seed=21)]
