@@ -125,6 +125,31 @@ def test_fp32_state_runs_the_transform_it_names():
     assert rel_err(outs[bb.TRANSFORM_NSP_MIXED], ref) <= 1e-4
 
 
+def test_ill_conditioned_fp32_state():
+    # slope noise 1e-3 (A~'s condition number near 1e7): the wide kernel's
+    # FP64 Gram keeps NSP within the FP32 bar (~4e-5); NSP_MIXED's FP32 steps
+    # sit 10-20 times above NSP at every conditioning (3e-4 here), still far
+    # inside what the 64-member kernel's FP32 Gram leaves at this
+    # conditioning (~7e-2)
+    case = Case(24, 0.28, 4, 2, 101, seed=6, sigma=0.001)
+    bb = B()
+    X0 = (case.rng.standard_normal((case.G.n_nodes, case.m)) * 0.5).astype(np.float32)
+    V, y = case.noise(), case.slopes(case.truth())
+    ref = case.oracle_analysis(case.prm.a * X0.astype(np.float64) + V.astype(np.float64), y)
+    errs = {}
+    for tr in (bb.TRANSFORM_NSP, bb.TRANSFORM_NSP_MIXED):
+        f = bb.Letkf([case.spec(bb, transform=tr)])
+        f.set_ensemble(_t(X0))
+        f.step(_t(y), V=_t(V))
+        torch.cuda.synchronize()
+        rc, flags = f.status()
+        assert rc == 0 and not (flags & 3).any()
+        errs[tr] = rel_err(_ens(f, case.m), ref)
+        f.close()
+    assert errs[bb.TRANSFORM_NSP] <= 1e-4
+    assert errs[bb.TRANSFORM_NSP_MIXED] <= 1e-3
+
+
 def test_owned_block_of_121_nodes():
     # 10x10 domains without a halo: 121 owned rows (eight row blocks of V);
     # FP32 fits the LDS, FP64 is refused with the sizes
