@@ -229,6 +229,34 @@ def test_plain_graph_and_direct_launches_agree_bitwise():
         assert np.array_equal(outs[0], o)
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(model=1), dict(refit_forgetting=0.95), dict(ar2_coeff=0.1),
+                                dict(gather_mode=1, piston=False), dict(localisation=1), dict(m=101, halo=2)])
+def test_graph_replays_match_direct_launches_frame_by_frame(kw):
+    # the frame's graph (analysis, pistons, the model's own nodes; the wide
+    # analysis at m = 101) replayed six times with the program's own eager
+    # work between replays (a reduction over many blocks, fills, host
+    # copies): every replay bitwise equal to the same frame launched directly
+    case = Case(24, 0.28, 4, 1, 64, seed=31, piston=True)
+    bb = B()
+    fg = bb.Letkf([case.spec(bb, **kw)])
+    fd = bb.Letkf([case.spec(bb, **kw)])
+    fg.set_schedule(True, bb.ORDER_XCD_PAIRED)
+    fd.set_schedule(False, bb.ORDER_XCD_PAIRED)
+    scratch = torch.randn(1 << 22, device=DEV)
+    for k in range(6):
+        y = _t(case.slopes(case.truth()))
+        for f in (fg, fd):
+            f.step(y, V=None)
+        total = float(scratch.sum())
+        scratch.zero_()
+        scratch.add_(total * 1e-9 + k)
+        torch.cuda.synchronize()
+        a, b = fg.get_ensemble().cpu().numpy(), fd.get_ensemble().cpu().numpy()
+        assert np.array_equal(a, b), k
+        assert np.isfinite(a).all()
+    assert fg.get_frame() == fd.get_frame() == 6
+
+
 @pytest.mark.parametrize("copies", [1, 2])
 def test_every_schedule_gives_the_same_bits_at_full_size(copies):
     # 80x80 (332 items: the paired order's two-round path) and two copies in
