@@ -1592,7 +1592,7 @@ __device__ __forceinline__ bool stage_gram(const AnaArgs<T> &A, const DomItem &i
   const int tid = threadIdx.x;
   const int q = tid >> 6, lane = tid & 63;
   const int m = in.m;
-  const int np = it.n_patch, nown = it.n_own, nobs = it.n_obs;
+  const int np = it.n_patch, nobs = it.n_obs;
   const int p = 2 * nobs, p4 = (p + 3) & ~3;
 
   T *xs = (T *)(smem + A.off_xs);
@@ -2809,7 +2809,7 @@ __global__ void k_resvar_adjoint(const InstDesc *insts, const T *x, const T *tru
 // theta_acc[3 i + t] += sum over the items of instance i of theta[4 item + t]:
 // one workgroup per (t, instance), strided partial sums and a fixed-order
 // tree (deterministic).
-__global__ __launch_bounds__(256) void k_theta_sum(const int32_t *dom_base, int n_inst, const double *theta,
+__global__ __launch_bounds__(256) void k_theta_sum(const int32_t *dom_base, const double *theta,
                                                   double *theta_acc) {
   __shared__ double red[4];
   const int t = blockIdx.x, inst = blockIdx.y;
@@ -3566,7 +3566,7 @@ extern "C" hipError_t letkf_launch_resvar_adjoint(int fp64, const InstDesc *inst
 
 extern "C" hipError_t letkf_launch_theta_sum(const int32_t *dom_base, int n_inst, const double *theta,
                                              double *theta_acc, hipStream_t s) {
-  hipLaunchKernelGGL(k_theta_sum, dim3(3, n_inst), dim3(256), 0, s, dom_base, n_inst, theta, theta_acc);
+  hipLaunchKernelGGL(k_theta_sum, dim3(3, n_inst), dim3(256), 0, s, dom_base, theta, theta_acc);
   return hipGetLastError();
 }
 
