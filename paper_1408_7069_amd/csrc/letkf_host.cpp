@@ -189,7 +189,7 @@ template <typename T> struct AdjArgsHost {
   double *dbar;
   double *theta;
   uint32_t frame;
-  int32_t off_q, off_wb, off_sa;
+  int32_t off_q, off_sa;
 };
 
 // Whether the host mirrors of the kernel argument blocks have the kernels'
@@ -274,7 +274,7 @@ struct letkf_handle {
   // adjoint: node -> subaperture roles, per-subaperture slot lists, item
   // ranges per instance, LDS layout, and buffers allocated on first use
   size_t adj_lds = 0;
-  int32_t adj_off[3] = {0, 0, 0};
+  int32_t adj_off[2] = {0, 0};
   bool adj_ok = false;
   int32_t *d_node_adj = nullptr, *d_slot_off = nullptr, *d_slots = nullptr, *d_dom_base = nullptr;
   double *d_ones = nullptr, *d_stats = nullptr;
@@ -1292,11 +1292,12 @@ int letkf_create(const letkf_config *cfgs, int32_t n_instances, int32_t device, 
     const size_t end2 = h->fwd_off[7] + letkf_wide_tri_bytes(nb);
     h->lds = align16(std::max(end1, end2));
   }
-  {  // the adjoint kernel: a larger U area (FP64 64 x 64), Q, a second matrix, scratch
+  {  // the adjoint kernel: a larger U area (FP64 64 x 64: W_bar and the DK
+     // products), Q (then S) in the state's precision, scratch.  FP32 at
+     // 80x80, m = 64: 78.4 KiB, so two work items share a CU
     size_t oa = align16(o + std::max(u, (size_t)64 * 65 * 8));
-    h->adj_off[0] = (int32_t)oa; oa = align16(oa + (size_t)64 * 65 * 8);
-    h->adj_off[1] = (int32_t)oa; oa = align16(oa + (size_t)64 * 65 * 8);
-    h->adj_off[2] = (int32_t)oa; oa = align16(oa + letkf_adjoint_scratch_doubles() * 8);
+    h->adj_off[0] = (int32_t)oa; oa = align16(oa + (size_t)64 * 65 * T);
+    h->adj_off[1] = (int32_t)oa; oa = align16(oa + letkf_adjoint_scratch_doubles() * 8);
     h->adj_lds = oa;
   }
   // adjoint maps: node -> (subaperture for corner roles a, b, c, d), the slots
@@ -2098,8 +2099,7 @@ static AdjArgsHost<T> make_adj_args(letkf_handle *h, const void *xa_prev, const 
   D.theta = h->d_theta;
   D.frame = frame;
   D.off_q = h->adj_off[0];
-  D.off_wb = h->adj_off[1];
-  D.off_sa = h->adj_off[2];
+  D.off_sa = h->adj_off[1];
   return D;
 }
 }  // extern "C++"

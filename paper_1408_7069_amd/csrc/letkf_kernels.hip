@@ -2397,7 +2397,7 @@ template <typename T> struct AdjArgs {
   double *dbar;      // out: adjoint of d per slot
   double *theta;     // out: (rho, s, c) adjoint per item, [item][4]
   uint32_t frame;    // frame number of the bank draws
-  int32_t off_q, off_wb, off_sa;
+  int32_t off_q, off_sa;
 };
 
 __device__ inline double block_sum4(double v, double *red, int slot, int q, int lane) {
@@ -2427,8 +2427,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjArgs<T> D) {
   double *sm = (double *)(smem + A.off_s);
   unsigned char *U = smem + A.off_u;
   double *Ub = (double *)U;
-  double *Qs = (double *)(smem + D.off_q);
-  double *Wb = (double *)(smem + D.off_wb);
+  T *Qs = (T *)(smem + D.off_q);  // Q in the state's precision; S after the DK stage
   double *sa = (double *)(smem + D.off_sa);
   const int64_t slot0 = 2 * (int64_t)it.obs_off;
 
@@ -2451,21 +2450,18 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjArgs<T> D) {
   }
   const double kc = (double)(m - 1) / in.rho;
 
-  // ---- A1. Q = U Lambda^{-1/2} into LDS ----
+  // ---- A1. Q = U Lambda^{-1/2} into LDS (the state's precision) ----
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int px = pos_x(q, j), py = pos_y(q, j);
-    Qs[lane * kQStride + px] = X[j] / sqrt(sm[S_LAMV + px]);
-    Qs[lane * kQStride + py] = Y[j] / sqrt(sm[S_LAMV + py]);
+    Qs[lane * kQStride + px] = (T)(X[j] / sqrt(sm[S_LAMV + px]));
+    Qs[lane * kQStride + py] = (T)(Y[j] / sqrt(sm[S_LAMV + py]));
   }
-  // ---- A2. adjoint of the owned rows (in the Wb area until the DK stage) ----
-  double *xab = Wb;
-  for (int i = q; i < nown; i += kWaves)
-    xab[i * kQStride + lane] = lane < m ? (double)D.xbar[in.x_off + (int64_t)pn[i] * m + lane] : 0.0;
-  __syncthreads();
+  // ---- A2. adjoint of the owned rows: read from the global array where used ----
+  const T *xab = D.xbar + in.x_off;  // row pn[i], member j at pn[i] * m + j
   if (tid < nown) {
     double s = 0.0;
-    for (int j = 0; j < m; ++j) s += xab[tid * kQStride + j];
+    for (int j = 0; j < m; ++j) s += (double)xab[(int64_t)pn[tid] * m + j];
     sa[A_XAB + tid] = s;
   }
   __syncthreads();
@@ -2482,7 +2478,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjArgs<T> D) {
       const int k = 4 * kk + k4;
       const bool ok = ia < nown && k < m;
       const T av = ok ? xs[ia * kXsStride + k] - mu : (T)0;
-      const T rv = ok ? (T)xab[ia * kQStride + k] : (T)0;
+      const T rv = ok ? xab[(int64_t)pn[ia] * m + k] : (T)0;
       const T bv = wmat[k * kYsStride + 16 * q + c16];
       oP = Mfma<T>::mac(av, bv, oP);
       oR = Mfma<T>::mac(rv, bv, oR);
@@ -2491,7 +2487,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjArgs<T> D) {
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * I + Mfma<T>::row(lane, r), j = 16 * q + c16;
       if (i < nown && j < m) {
-        rho1 += xab[i * kQStride + j] * (double)oP[r];
+        rho1 += (double)xab[(int64_t)pn[i] * m + j] * (double)oP[r];
         const double v = srho * (double)oR[r] + sa[A_XAB + i] * sm[S_WV + j];
         D.xpbar[in.x_off + (int64_t)pn[i] * m + j] = (T)v;
       }
@@ -2511,7 +2507,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjArgs<T> D) {
         const int k = 4 * kk + k4;
         const bool ok = k < nown;
         const double av = (ok && i < m) ? (double)(xs[k * kXsStride + i] - xm[k]) : 0.0;
-        const double bv = ok ? xab[k * kQStride + 16 * J + c16] : 0.0;
+        const double bv = (ok && 16 * J + c16 < m) ? (double)xab[(int64_t)pn[k] * m + 16 * J + c16] : 0.0;
         acc = Mfma<double>::mac(av, bv, acc);
       }
 #pragma unroll
@@ -2529,7 +2525,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjArgs<T> D) {
       for (int k = 0; k < nown; ++k) s += (double)(xs[k * kXsStride + lane] - xm[k]) * sa[A_XAB + k];
     sa[A_WBB + lane] = s;
   }
-  __syncthreads();  // W (in U) and Xa_bar (in Wb) are no longer read
+  __syncthreads();  // W (in U) is no longer read
 #pragma unroll
   for (int J = 0; J < 4; ++J)
 #pragma unroll
@@ -2538,32 +2534,38 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjArgs<T> D) {
   // ---- A5. b_bar = Q Lambda^{-1} Q^T w_bar ----
   if (q == 0) {
     double t = 0.0;
-    for (int r = 0; r < 64; ++r) t = fma(Qs[r * kQStride + lane], sa[A_WBB + r], t);
+    for (int r = 0; r < 64; ++r) t = fma((double)Qs[r * kQStride + lane], sa[A_WBB + r], t);
     sa[A_TV + lane] = t / sm[S_LAMV + lane];
   }
   __syncthreads();
   if (q == 0) {
     double bb = 0.0;
-    for (int c = 0; c < 64; ++c) bb = fma(Qs[lane * kQStride + c], sa[A_TV + c], bb);
+    for (int c = 0; c < 64; ++c) bb = fma((double)Qs[lane * kQStride + c], sa[A_TV + c], bb);
     sa[A_BB + lane] = bb;
   }
 
   // ---- A6. A_bar of the transform through the eigenpairs (Daleckii-Krein) ----
+  // Four products, each held in the waves' registers until every wave has
+  // read its operand in Ub and then stored over it: one FP64 work matrix.
   f64x4 t4[4];
+  auto store_t4 = [&]() {
+    __syncthreads();  // every read of Ub's operand is done
+#pragma unroll
+    for (int J = 0; J < 4; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Ub[(16 * q + Mfma<double>::row(lane, r)) * kQStride + 16 * J + c16] = t4[J][r];
+    __syncthreads();
+  };
 #pragma unroll
   for (int J = 0; J < 4; ++J)  // P1 = sym(W_bar) Q
     t4[J] = mm64_tile([&](int i, int k) { return 0.5 * (Ub[i * kQStride + k] + Ub[k * kQStride + i]); },
-                      [&](int k, int j) { return Qs[k * kQStride + j]; }, q, J, lane);
-#pragma unroll
-  for (int J = 0; J < 4; ++J)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Wb[(16 * q + Mfma<double>::row(lane, r)) * kQStride + 16 * J + c16] = t4[J][r];
-  __syncthreads();
+                      [&](int k, int j) { return (double)Qs[k * kQStride + j]; }, q, J, lane);
+  store_t4();
   const double skc = sqrt(kc);
 #pragma unroll
   for (int J = 0; J < 4; ++J) {  // M = F o (Q^T P1), times sqrt(k)
-    t4[J] = mm64_tile([&](int i, int k) { return Qs[k * kQStride + i]; },
-                      [&](int k, int j) { return Wb[k * kQStride + j]; }, q, J, lane);
+    t4[J] = mm64_tile([&](int i, int k) { return (double)Qs[k * kQStride + i]; },
+                      [&](int k, int j) { return Ub[k * kQStride + j]; }, q, J, lane);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * q + Mfma<double>::row(lane, r), j = 16 * J + c16;
@@ -2571,36 +2573,25 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjArgs<T> D) {
       t4[J][r] *= -skc / (si * sj * (si + sj));
     }
   }
-#pragma unroll
-  for (int J = 0; J < 4; ++J)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Ub[(16 * q + Mfma<double>::row(lane, r)) * kQStride + 16 * J + c16] = t4[J][r];
-  __syncthreads();
+  store_t4();
 #pragma unroll
   for (int J = 0; J < 4; ++J)  // P2 = Q M
-    t4[J] = mm64_tile([&](int i, int k) { return Qs[i * kQStride + k]; },
+    t4[J] = mm64_tile([&](int i, int k) { return (double)Qs[i * kQStride + k]; },
                       [&](int k, int j) { return Ub[k * kQStride + j]; }, q, J, lane);
-#pragma unroll
-  for (int J = 0; J < 4; ++J)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Wb[(16 * q + Mfma<double>::row(lane, r)) * kQStride + 16 * J + c16] = t4[J][r];
-  __syncthreads();
+  store_t4();
 #pragma unroll
   for (int J = 0; J < 4; ++J)  // P2 Q^T
-    t4[J] = mm64_tile([&](int i, int k) { return Wb[i * kQStride + k]; },
-                      [&](int k, int j) { return Qs[j * kQStride + k]; }, q, J, lane);
-#pragma unroll
-  for (int J = 0; J < 4; ++J)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Ub[(16 * q + Mfma<double>::row(lane, r)) * kQStride + 16 * J + c16] = t4[J][r];
-  __syncthreads();
-  // S = sym(A_bar) into Wb
+    t4[J] = mm64_tile([&](int i, int k) { return Ub[i * kQStride + k]; },
+                      [&](int k, int j) { return (double)Qs[j * kQStride + k]; }, q, J, lane);
+  store_t4();
+  // S = sym(A_bar) over Q (no longer read), in the state's precision
+  T *Ss = Qs;
   double tr = 0.0;
   for (int e = tid; e < 64 * 64; e += kThreads) {
     const int i = e >> 6, j = e & 63;
     const double v = 0.5 * (Ub[i * kQStride + j] + Ub[j * kQStride + i]) -
                      0.5 * (sa[A_BB + i] * sm[S_WV + j] + sm[S_WV + i] * sa[A_BB + j]);
-    Wb[i * kQStride + j] = v;
+    Ss[i * kQStride + j] = (T)v;
     if (i == j) tr += v;
   }
   __syncthreads();
@@ -2643,7 +2634,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjArgs<T> D) {
     for (int kk = 0; kk < 16; ++kk) {
       const int k = 4 * kk + k4;
       const double av = ia < p ? sgi * (double)yu[ia * kYsStride + k] : 0.0;
-      acc = Mfma<double>::mac(av, Wb[k * kQStride + 16 * q + c16], acc);
+      acc = Mfma<double>::mac(av, (double)Ss[k * kQStride + 16 * q + c16], acc);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
