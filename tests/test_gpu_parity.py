@@ -411,6 +411,34 @@ def test_ill_conditioned_fp64_frames_meet_the_fp64_bar():
         assert e <= 1e-10, (name, errs)
 
 
+def test_long_run_tracks_the_phase():
+    # 3000 frames of a 24x24 loop (AR(1) truth, its noisy slopes, bank noise,
+    # pistons, the default transform): every frame's status clean, the
+    # ensemble finite, the residual phase variance of the mean over the last
+    # 1000 frames a small fraction of the phase's and no larger than over the
+    # 1000 before (no drift)
+    from oracle import letkf as ol
+    from paper_1408_7069_amd import workload as wl
+    case = Case(24, 0.28, 4, 1, 64, seed=33, piston=True)
+    bb = B()
+    f = bb.Letkf([case.spec(bb)])
+    T = 3000
+    grid = wl.ar1_truth(24, T, case.pitch, case.r0, 25.0, case.prm.a, case.rng)
+    res, var = np.empty(T), np.empty(T)
+    for k in range(T):
+        truth = grid[k][case.ij[:, 0], case.ij[:, 1]]
+        f.step(_t(case.slopes(truth)), V=None)
+        rc, flags = f.status()
+        assert rc == 0 and not (flags & 3).any(), k
+        mean = f.get_mean().cpu().numpy().astype(np.float64)
+        res[k] = ol.residual_variance(mean, truth)
+        var[k] = np.var(truth)
+    assert np.isfinite(f.get_ensemble().cpu().numpy()).all()
+    late, before = res[2000:].mean(), res[1000:2000].mean()
+    assert late <= 0.01 * var[2000:].mean(), (late, var[2000:].mean())
+    assert late <= 1.5 * before, (late, before)
+
+
 def test_slope_operator_kernel():
     bb = B()
     cases = [Case(16, 0.2, 4, 1, 8, seed=20), Case(9, None, 3, 1, 8, seed=21)]
